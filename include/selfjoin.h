@@ -1,0 +1,171 @@
+/*
+ * selfjoin.h -- C ABI of the MI355X (gfx950) Euclidean epsilon self-join.
+ *
+ * The operation (Gowanlock & Karsin, "GPU Accelerated Similarity Self-Join
+ * for Multi-Dimensional Data", Section 3.1, problem statement): given a set D
+ * of n points in d dimensions and a radius epsilon, return every ordered
+ * tuple (a, b) of points of D with dist(a, b) <= epsilon, dist being the
+ * Euclidean (L2) distance over all d dimensions.  The result may be much
+ * larger than D and may exceed device memory; D itself must fit (Section
+ * 3.1, last paragraph).
+ *
+ * Canonical predicate.  A pair (i, j) is in the result iff
+ *     acc <= eps2,   eps2 = epsilon * epsilon   (binary64, one rounding),
+ *     acc = sum over t = 0 .. d-1 in the caller's dimension order of
+ *           diff*diff, diff = (double)p_i[t] - (double)p_j[t],
+ * every operation a separately rounded binary64 operation.  Whatever
+ * precision the device filters use, every include/exclude decision equals
+ * this predicate's.
+ *
+ * Result convention.  Indices are the caller's row indices 0 .. n-1.  The
+ * result holds (i, i) for every point and both (i, j) and (j, i) for every
+ * pair, so |R| = n * (S_D + 1) with S_D the selectivity of Section 5.2.
+ * Pairs are returned sorted ascending by (i, j).
+ *
+ * Method (Algorithm 1 and Sections 3.2, 4.1, 4.2, 4.4): dimensions are
+ * reordered by variance estimated on a 1% sample, points are binned into a
+ * grid of cells of side >= epsilon over the first k reordered dimensions
+ * (only non-empty cells stored), each query cell searches the 3^k adjacent
+ * cells by binary search, and candidate pairs are filtered by their distance
+ * over all d dimensions with a short-circuit once the partial sum of squares
+ * exceeds the threshold.  Results are produced in batches (Section 3.2.2).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SJ_OK (0) or a negative SJ_ERR_* code.  On error,
+ *    out-parameters are left untouched and selfjoin_last_error() returns a
+ *    message for the calling thread (valid until that thread's next call).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    ordered on it; each call returns only after its work on `stream` is
+ *    complete, so buffers may be reused immediately after the call.
+ *  - Pointers marked "host or device" may point to host memory (pageable or
+ *    pinned) or to device memory of the current HIP device.
+ *  - A handle is used by one thread at a time; distinct handles may be used
+ *    concurrently.  The handle lives on the HIP device that was current when
+ *    it was built, and that device must be current for every later call.
+ *  - Maximum sizes: n <= 2^32 - 1, 1 <= d <= SJ_MAX_DIM.
+ */
+#ifndef SELFJOIN_H
+#define SELFJOIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SJ_OK                 0
+#define SJ_ERR_INVALID_ARG   -1  /* NULL pointer, n or d out of range, epsilon <= 0 or not finite, NaN/Inf coordinates, bad option */
+#define SJ_ERR_OUT_OF_MEMORY -2  /* a device or pinned-host allocation failed */
+#define SJ_ERR_DEVICE        -3  /* a HIP runtime call failed */
+#define SJ_ERR_KEY_OVERFLOW  -4  /* an explicit k makes the linearised cell id exceed 63 bits */
+#define SJ_ERR_STATE         -5  /* call out of order, e.g. fetch before run */
+#define SJ_ERR_RANGE         -6  /* fetch offset beyond the result */
+
+#define SJ_MAX_DIM 128
+
+/* Distance filter used by selfjoin_run. */
+enum sj_precision {
+    SJ_PREC_FP32 = 0 /* difference form (a-b)^2 summed in FP32 on the vector ALUs, with short-circuit */
+};
+
+typedef struct sj_index sj_index; /* opaque; owns every device buffer it uses */
+
+typedef struct sj_options {
+    uint32_t struct_size;   /* sizeof(sj_options), for ABI versioning */
+    int32_t  k;             /* indexed dimensions (Section 4.1); 0 = choose automatically in [k_min, k_max]; clamped to d */
+    uint32_t k_min, k_max;  /* automatic k range; defaults 4 and 8 */
+    uint32_t reorder;       /* 1 = order dimensions by descending sample variance (Section 4.2); 0 = index the first k input dimensions */
+    uint32_t shortc;        /* 1 = stop a distance once its partial sum exceeds the threshold (Section 4.4) */
+    uint32_t precision;     /* enum sj_precision */
+    uint64_t batch_pairs;   /* b_s of Section 3.2.2: maximum result pairs held on the device per batch; 0 = automatic (as many as fit) */
+    uint32_t min_batches;   /* minimum number of batches n_b (Section 3.2.2 uses >= 3); 0 or 1 = as few as possible */
+    uint32_t reserved0;
+    uint64_t mem_budget;    /* device bytes the result buffers may use; 0 = a default share of free device memory */
+} sj_options;
+
+/* Fills *opts with the defaults: k = 0 (auto, 4..8), reorder = 1,
+ * shortc = 1, precision = SJ_PREC_FP32, batch_pairs = 0, min_batches = 0,
+ * mem_budget = 0. */
+void selfjoin_default_options(sj_options *opts);
+
+/*
+ * Builds the grid index (Algorithm 1: reorderVariance, constructIndex).
+ *   points   host or device, row-major float32 [n][d], caller-owned; read
+ *            during the call only (the index keeps its own reordered copy).
+ *   n, d     point count (0 allowed: an empty result) and dimension count.
+ *   epsilon  search radius, finite and > 0.
+ *   opts     NULL for the defaults.
+ *   out      receives the new handle; release it with selfjoin_free.
+ * Errors: SJ_ERR_INVALID_ARG for bad arguments or non-finite coordinates,
+ * SJ_ERR_KEY_OVERFLOW when an explicit k cannot be linearised in 63 bits
+ * (automatic k lowers k instead), SJ_ERR_OUT_OF_MEMORY, SJ_ERR_DEVICE.
+ */
+int selfjoin_build_index(const float *points, uint64_t n, uint32_t d,
+                         double epsilon, const sj_options *opts, void *stream,
+                         sj_index **out);
+
+/*
+ * Runs the join (Algorithm 1: computeNumBatches and the batch loop of
+ * SelfJoinKernel; Section 3.2.2 batching).  On success *total_pairs = |R|.
+ * The sorted result stays owned by the handle (in device memory when it fits
+ * the budget, else in pinned host memory) until selfjoin_free.  Calling it
+ * again returns the same total without recomputing.
+ */
+int selfjoin_run(sj_index *idx, void *stream, uint64_t *total_pairs);
+
+/*
+ * Copies result pairs [first, first + max_pairs) of the sorted result.
+ *   out_i, out_j  host or device uint32 arrays of max_pairs entries, or NULL
+ *                 to skip that column.
+ *   out_dist      host or device float array, or NULL: the Euclidean
+ *                 distance of each pair recomputed in FP32 (difference form,
+ *                 caller's dimension order); relative error <= 1e-5.
+ *   n_written     receives min(max_pairs, |R| - first).
+ * Errors: SJ_ERR_STATE before a successful selfjoin_run, SJ_ERR_RANGE when
+ * first > |R|.
+ */
+int selfjoin_fetch_pairs(sj_index *idx, uint64_t first, uint64_t max_pairs,
+                         uint32_t *out_i, uint32_t *out_j, float *out_dist,
+                         uint64_t *n_written, void *stream);
+
+/* Counters and timings of the last build and run. */
+typedef struct sj_info {
+    uint32_t struct_size;     /* sizeof(sj_info) */
+    uint32_t d;
+    uint64_t n;
+    double   epsilon;
+    uint32_t k;               /* indexed dimensions used */
+    uint32_t precision;
+    uint64_t n_cells;         /* non-empty grid cells |G| */
+    uint64_t candidates;      /* ordered candidate pairs C: sum over points of the sizes of their adjacent non-empty cells */
+    uint64_t evaluated;       /* candidate pairs the distance kernel evaluated (each unordered pair once when tiles are symmetric) */
+    uint64_t rechecks;        /* pairs sent to the FP64 boundary recheck */
+    uint64_t pairs;           /* |R| (valid after run) */
+    uint32_t batches;         /* batches used by the last run */
+    uint32_t result_on_host;  /* 1 when the result was streamed to pinned host memory */
+    float    ms_build;        /* device time of the index build (events) */
+    float    ms_join;         /* device time of the distance kernels of the last run */
+    float    ms_sort;         /* device time of result sorting of the last run */
+    float    ms_run;          /* device time of the whole last run */
+    uint32_t join_launches;   /* launches of the distance kernel in the last run */
+    uint32_t reserved;
+} sj_info;
+
+/* info->struct_size must be set by the caller. */
+int selfjoin_get_info(const sj_index *idx, sj_info *info);
+
+/* perm[r] = caller dimension placed at position r by the variance reorder;
+ * writes min(cap, d) entries. */
+int selfjoin_get_perm(const sj_index *idx, uint32_t *perm, uint32_t cap);
+
+/* Releases the handle and all its memory.  NULL is ignored. */
+void selfjoin_free(sj_index *idx);
+
+/* Message of the calling thread's last error ("" if none). */
+const char *selfjoin_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SELFJOIN_H */

@@ -1,0 +1,930 @@
+// Host runtime and C ABI of libselfjoin (Algorithm 1, GPU-JOIN: reorder ->
+// constructIndex -> computeNumBatches -> batch loop).  All device work runs
+// on the caller's stream; results stay on the device when they fit the
+// memory budget, else batches are streamed to pinned host memory.
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "sj_index.hpp"
+#include "sj_internal.hpp"
+
+namespace sj {
+
+thread_local std::string g_last_error;
+
+[[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return;
+  const int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+                       ? SJ_ERR_OUT_OF_MEMORY
+                       : SJ_ERR_DEVICE;
+  fail(code, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+// Device allocation owned by a handle.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    reset();
+    if (b == 0) b = 256;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  void ensure(size_t b) {
+    if (b > bytes || !p) alloc(b);
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+struct PinnedBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf &) = delete;
+  PinnedBuf &operator=(const PinnedBuf &) = delete;
+  PinnedBuf(PinnedBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t b) {
+    if (b == 0) b = 64;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(SJ_ERR_OUT_OF_MEMORY, "pinned host allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+};
+
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() { SJ_HIP(hipEventCreate(&e)); }
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  Event(const Event &) = delete;
+  Event &operator=(const Event &) = delete;
+};
+
+float elapsed_ms(const Event &a, const Event &b) {
+  float ms = 0.0f;
+  SJ_HIP(hipEventElapsedTime(&ms, a.e, b.e));
+  return ms;
+}
+
+uint32_t bits_for(uint64_t v) {  // bits needed to represent v
+  uint32_t b = 0;
+  while (v) { ++b; v >>= 1; }
+  return b;
+}
+
+std::vector<int> digit_shifts(uint32_t lo_bits, uint32_t hi_bits) {
+  // 8-bit digits over bits [0, lo_bits) and [32, 32 + hi_bits)
+  std::vector<int> s;
+  for (uint32_t b = 0; b < lo_bits; b += 8) s.push_back((int)b);
+  for (uint32_t b = 0; b < hi_bits; b += 8) s.push_back(32 + (int)b);
+  return s;
+}
+
+bool is_device_pointer(const void *ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+#if HIP_VERSION_MAJOR >= 6
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+#else
+  return attr.memoryType == hipMemoryTypeDevice;
+#endif
+}
+
+// Grid geometry for one choice of k.
+struct Geometry {
+  uint32_t k = 0;
+  KeyParams kp{};
+  NbrParams np{};
+  uint32_t key_bits = 0;
+};
+
+double gamma_n(double m, double u) { return m * u / (1.0 - m * u); }
+
+}  // namespace
+}  // namespace sj
+
+using namespace sj;
+
+struct sj_index {
+  int device = 0;
+  uint64_t n = 0;
+  uint32_t d = 0, dp = 0, k = 0;
+  double eps = 0.0, eps2 = 0.0;
+  sj_options opt{};
+  std::vector<uint32_t> perm;
+  std::vector<uint16_t> inv_perm;
+  std::vector<double> dmin, dmax;
+  float lo32 = 0.0f, hi32 = 0.0f;
+
+  // index
+  DevBuf X, orig_id, pos_of, perm_d, inv_perm_d;
+  DevBuf cell_key, cell_start;
+  uint64_t ncell = 0;
+  DevBuf nbr_off, nbr_cell;
+  uint64_t n_nbr = 0;
+  DevBuf run_off_sym, runs_sym, run_off_full, runs_full;
+  uint64_t n_runs_sym = 0, n_runs_full = 0;
+  DevBuf wu;
+  uint64_t n_wu = 0;
+  uint32_t tq = 256, tc = 16384;
+  uint64_t candidates = 0, evaluated_sym = 0;
+  DevBuf counters;  // [0] cursor, [1] rechecks
+
+  // results
+  bool ran = false;
+  uint64_t total = 0;
+  DevBuf pairs;                     // sorted keys when device-resident
+  std::vector<PinnedBuf> host_res;  // sorted keys per batch when host-resident
+  std::vector<uint64_t> host_cnt;
+  bool on_host = false;
+  DevBuf fetch_stage;
+
+  sj_info info{};
+};
+
+namespace sj {
+namespace {
+
+constexpr double kWidthSlack = 1.0 + 1.0 / (1 << 20);  // cell side = eps * (1 + 2^-20)
+
+// Cost model for the automatic choice of k (Section 5.5 compares the memory
+// operations of index searches with those of distance calculations): one
+// unit per 3^k-offset lookup of each non-empty cell, one per evaluated pair.
+constexpr double kLookupsPerSec = 2.0e10;
+constexpr double kPairsPerSec = 1.5e12;
+
+bool make_geometry(const sj_index &ix, uint32_t k, Geometry &g) {
+  g = Geometry{};
+  g.k = k;
+  g.kp.k = k;
+  g.kp.w = ix.eps * kWidthSlack;
+  g.np.k = k;
+  unsigned __int128 prod = 1;
+  uint64_t m[kKeyMaxDims];
+  for (uint32_t r = 0; r < k; ++r) {
+    const uint32_t t = ix.perm[r];
+    g.kp.dim[r] = t;
+    g.kp.org[r] = ix.dmin[t];
+    // same arithmetic as the device: floor((x - org) / w) at x = max
+    const double cm = std::floor((ix.dmax[t] - ix.dmin[t]) / g.kp.w);
+    if (!(cm >= 0.0) || cm > 9.0e15) return false;
+    g.kp.cmax[r] = (uint64_t)cm;
+    m[r] = (uint64_t)cm + 1;
+    prod *= m[r];
+    if (prod > ((unsigned __int128)1 << 63)) return false;
+  }
+  uint64_t mult = 1;
+  for (int r = (int)k - 1; r >= 0; --r) {
+    g.kp.mult[r] = mult;
+    g.np.mult[r] = mult;
+    g.np.m[r] = m[r];
+    mult *= m[r];
+  }
+  g.key_bits = bits_for(mult - 1);
+  uint64_t noff = 1;
+  for (uint32_t r = 0; r < k; ++r) noff *= 3;
+  g.np.n_off = noff;
+  return true;
+}
+
+// Temporary buffers of one build.
+struct BuildTmp {
+  DevBuf keys[2], ids[2], flag, radix, scan, small;
+  DevBuf nbr_count, cand_sum, prod;
+};
+
+// Keys, sort, gather, compaction and neighbour counts for geometry g.
+// Returns the candidate count C and fills ncell.
+uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t, hipStream_t s,
+                    bool keep) {
+  const uint64_t n = ix.n;
+  launch_cellkey(P, n, ix.d, g.kp, t.keys[0].as<uint64_t>(), t.ids[0].as<uint32_t>(), s);
+  uint64_t *kb[2] = {t.keys[0].as<uint64_t>(), t.keys[1].as<uint64_t>()};
+  uint32_t *vb[2] = {t.ids[0].as<uint32_t>(), t.ids[1].as<uint32_t>()};
+  std::vector<int> shifts;
+  for (uint32_t b = 0; b < g.key_bits; b += 8) shifts.push_back((int)b);
+  radix_sort_u64(kb, vb, n, shifts.data(), (int)shifts.size(), t.radix.p, s);
+  if (keep) {
+    launch_gather(P, n, ix.d, ix.dp, ix.perm_d.as<uint32_t>(), vb[0], ix.X.as<float>(),
+                  ix.orig_id.as<uint32_t>(), ix.pos_of.as<uint32_t>(), s);
+  }
+  uint32_t *d_ncell = t.small.as<uint32_t>();
+  launch_compact(kb[0], n, t.flag.as<uint32_t>(), d_ncell, ix.cell_key.as<uint64_t>(),
+                 ix.cell_start.as<uint32_t>(), t.scan.p, s);
+  uint32_t h_ncell = 0;
+  SJ_HIP(hipMemcpyAsync(&h_ncell, d_ncell, 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  ix.ncell = h_ncell;
+  const uint64_t nc = ix.ncell;
+
+  NbrParams np = g.np;
+  const uint64_t kFence = 8192;
+  uint64_t fs = 1;
+  while ((nc + fs - 1) / fs > kFence) fs <<= 1;
+  np.fstride = (uint32_t)fs;
+  np.nfence = (uint32_t)((nc + fs - 1) / fs);
+  SJ_HIP(hipMemsetAsync(t.nbr_count.p, 0, (nc + 1) * 4, s));
+  launch_neighbors(0, ix.cell_key.as<uint64_t>(), ix.cell_start.as<uint32_t>(), nc, np,
+                   t.nbr_count.as<uint32_t>(), t.cand_sum.as<uint64_t>(), nullptr, nullptr, s);
+  launch_cell_products(nc, ix.cell_start.as<uint32_t>(), t.cand_sum.as<uint64_t>(),
+                       t.prod.as<uint64_t>(), s);
+  uint64_t *d_c = reinterpret_cast<uint64_t *>(t.small.as<char>() + 8);
+  exclusive_scan_u64(t.prod.as<uint64_t>(), t.prod.as<uint64_t>(), nc, d_c, t.scan.p, s);
+  uint64_t h_c = 0;
+  SJ_HIP(hipMemcpyAsync(&h_c, d_c, 8, hipMemcpyDeviceToHost, s));
+  if (keep) {
+    ix.nbr_off.alloc((nc + 1) * 4);
+    uint32_t *d_nn = reinterpret_cast<uint32_t *>(t.small.as<char>() + 16);
+    exclusive_scan_u32(t.nbr_count.as<uint32_t>(), ix.nbr_off.as<uint32_t>(), nc + 1, d_nn,
+                       t.scan.p, s);
+    uint32_t h_nn = 0;
+    SJ_HIP(hipMemcpyAsync(&h_nn, d_nn, 4, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    ix.n_nbr = h_nn;
+    ix.nbr_cell.alloc((uint64_t)h_nn * 4);
+    launch_neighbors(1, ix.cell_key.as<uint64_t>(), ix.cell_start.as<uint32_t>(), nc, np,
+                     nullptr, nullptr, ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(), s);
+  }
+  SJ_HIP(hipStreamSynchronize(s));
+  return h_c;
+}
+
+// Candidate runs (sym: only cells B >= A) into off/runs.
+uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &t, hipStream_t s) {
+  const uint64_t nc = ix.ncell;
+  DevBuf cnt;
+  cnt.alloc((nc + 1) * 4);
+  SJ_HIP(hipMemsetAsync(cnt.p, 0, (nc + 1) * 4, s));
+  launch_runs(0, sym, nc, ix.cell_start.as<uint32_t>(), ix.nbr_off.as<uint32_t>(),
+              ix.nbr_cell.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, s);
+  off.alloc((nc + 1) * 4);
+  uint32_t *d_tot = t.small.as<uint32_t>() + 8;
+  exclusive_scan_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), nc + 1, d_tot, t.scan.p, s);
+  uint32_t h_tot = 0;
+  SJ_HIP(hipMemcpyAsync(&h_tot, d_tot, 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  runs.alloc((uint64_t)h_tot * sizeof(uint2));
+  launch_runs(1, sym, nc, ix.cell_start.as<uint32_t>(), ix.nbr_off.as<uint32_t>(),
+              ix.nbr_cell.as<uint32_t>(), nullptr, off.as<uint32_t>(), runs.as<uint2>(), s);
+  return h_tot;
+}
+
+// Work units over the given runs; qlist == nullptr: contiguous queries.
+// Returns the number of units; *eval receives the evaluated pair count.
+uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
+                         const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
+                         DevBuf &out, uint64_t *eval, hipStream_t s) {
+  const uint64_t nc = ix.ncell;
+  DevBuf cnt, ev, scan;
+  cnt.alloc((nc + 1) * 4);
+  ev.alloc((nc + 1) * 8);
+  scan.alloc(scan_tmp_bytes(nc + 1) + 64);
+  SJ_HIP(hipMemsetAsync(cnt.p, 0, (nc + 1) * 4, s));
+  SJ_HIP(hipMemsetAsync(ev.p, 0, (nc + 1) * 8, s));
+  launch_workunits(0, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+                   run_off.as<uint32_t>(), runs.as<uint2>(), cnt.as<uint32_t>(),
+                   ev.as<uint64_t>(), nullptr, nullptr, s);
+  DevBuf tot;
+  tot.alloc(64);
+  exclusive_scan_u32(cnt.as<uint32_t>(), cnt.as<uint32_t>(), nc + 1, tot.as<uint32_t>(), scan.p, s);
+  exclusive_scan_u64(ev.as<uint64_t>(), ev.as<uint64_t>(), nc + 1, tot.as<uint64_t>() + 1, scan.p,
+                     s);
+  uint64_t h[2] = {0, 0};
+  SJ_HIP(hipMemcpyAsync(h, tot.p, 16, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  const uint64_t n_wu = (uint32_t)h[0];
+  *eval = h[1];
+  out.alloc(n_wu * sizeof(WorkUnit));
+  launch_workunits(1, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+                   run_off.as<uint32_t>(), runs.as<uint2>(), nullptr, nullptr,
+                   cnt.as<uint32_t>(), out.as<WorkUnit>(), s);
+  SJ_HIP(hipStreamSynchronize(s));
+  return n_wu;
+}
+
+// Candidate block length so a launch has enough work units to fill the chip.
+uint32_t choose_tc(uint64_t eval_pairs, uint32_t tq) {
+  const double target_units = 256.0 * 32.0;  // CUs x waves in flight, roughly
+  double tc = (double)eval_pairs / ((double)tq * target_units);
+  tc = std::max(256.0, std::min(16384.0, tc));
+  uint32_t t = 256;
+  while (t < tc) t <<= 1;
+  return t;
+}
+
+void compute_thresholds(sj_index &ix) {
+  const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+  const double g32 = gamma_n((double)ix.dp + 2.0, u32);
+  const double g64 = gamma_n((double)ix.d + 2.0, u64);
+  const double tiny = 2.0 * ((double)ix.dp + 2.0) * std::ldexp(1.0, -126);
+  const double margin = std::ldexp(1.0, -50);
+  double hi = ix.eps2 * (1.0 + g32) / (1.0 - g64) * (1.0 + margin) + tiny;
+  double lo = ix.eps2 * (1.0 - g32) / (1.0 + g64) * (1.0 - margin) - tiny;
+  if (!(hi < (double)FLT_MAX / 4.0)) {
+    ix.hi32 = __builtin_inff();
+    ix.lo32 = -1.0f;
+    return;
+  }
+  float h = (float)hi;
+  if ((double)h < hi) h = std::nextafter(h, __builtin_inff());
+  float l = (float)lo;
+  if ((double)l > lo) l = std::nextafter(l, -__builtin_inff());
+  if (lo <= 0.0) l = -1.0f;
+  ix.hi32 = h;
+  ix.lo32 = l;
+}
+
+void fill_defaults(sj_options *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(sj_options);
+  o->k = 0;
+  o->k_min = 4;
+  o->k_max = 8;
+  o->reorder = 1;
+  o->shortc = 1;
+  o->precision = SJ_PREC_FP32;
+}
+
+void build(sj_index &ix, const float *points, hipStream_t s) {
+  Event ev0, ev1;
+  SJ_HIP(hipEventRecord(ev0.e, s));
+  const uint64_t n = ix.n;
+  const uint32_t d = ix.d;
+  ix.dp = padded_dim(d);
+  ix.perm.resize(d);
+  ix.inv_perm.resize(d);
+  ix.dmin.assign(d, 0.0);
+  ix.dmax.assign(d, 0.0);
+  ix.counters.alloc(64);
+  compute_thresholds(ix);
+  if (n == 0) {
+    std::iota(ix.perm.begin(), ix.perm.end(), 0u);
+    for (uint32_t r = 0; r < d; ++r) ix.inv_perm[ix.perm[r]] = (uint16_t)r;
+    ix.k = 0;
+    SJ_HIP(hipEventRecord(ev1.e, s));
+    SJ_HIP(hipEventSynchronize(ev1.e));
+    ix.info.ms_build = elapsed_ms(ev0, ev1);
+    return;
+  }
+  // input on the device (copy host input once)
+  DevBuf staged;
+  const float *P = points;
+  if (!is_device_pointer(points)) {
+    staged.alloc(n * d * sizeof(float));
+    SJ_HIP(hipMemcpyAsync(staged.p, points, n * d * sizeof(float), hipMemcpyHostToDevice, s));
+    P = staged.as<float>();
+  }
+  // a1/a2: min/max, finiteness, sample variance
+  DevBuf stats;
+  stats.alloc(d * 16 + 256);
+  uint32_t *gmin = stats.as<uint32_t>();
+  uint32_t *gmax = gmin + d;
+  uint32_t *bad = gmax + d;
+  double *var = reinterpret_cast<double *>(stats.as<char>() + ((d * 8 + 8 + 63) / 64) * 64);
+  launch_minmax(P, n, d, gmin, gmax, bad, s);
+  const uint64_t stride = n <= 10000 ? 1 : 100;
+  const uint64_t m = (n + stride - 1) / stride;
+  launch_variance(P, d, stride, m, var, s);
+  std::vector<uint32_t> hmin(d), hmax(d);
+  uint32_t hbad = 0;
+  std::vector<double> hvar(d);
+  SJ_HIP(hipMemcpyAsync(hmin.data(), gmin, d * 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipMemcpyAsync(hmax.data(), gmax, d * 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipMemcpyAsync(hvar.data(), var, d * 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  if (hbad) fail(SJ_ERR_INVALID_ARG, "points contain NaN or Inf coordinates");
+  for (uint32_t t = 0; t < d; ++t) {
+    ix.dmin[t] = (double)ordered_to_float(hmin[t]);
+    ix.dmax[t] = (double)ordered_to_float(hmax[t]);
+  }
+  std::iota(ix.perm.begin(), ix.perm.end(), 0u);
+  if (ix.opt.reorder)
+    std::stable_sort(ix.perm.begin(), ix.perm.end(),
+                     [&](uint32_t a, uint32_t b) { return hvar[a] > hvar[b]; });
+  for (uint32_t r = 0; r < d; ++r) ix.inv_perm[ix.perm[r]] = (uint16_t)r;
+  ix.perm_d.alloc(d * 4);
+  ix.inv_perm_d.alloc(d * 2);
+  SJ_HIP(hipMemcpyAsync(ix.perm_d.p, ix.perm.data(), d * 4, hipMemcpyHostToDevice, s));
+  SJ_HIP(hipMemcpyAsync(ix.inv_perm_d.p, ix.inv_perm.data(), d * 2, hipMemcpyHostToDevice, s));
+
+  // buffers
+  BuildTmp t;
+  t.keys[0].alloc(n * 8);
+  t.keys[1].alloc(n * 8);
+  t.ids[0].alloc(n * 4);
+  t.ids[1].alloc(n * 4);
+  t.flag.alloc(n * 4);
+  t.radix.alloc(radix_tmp_bytes(n));
+  t.scan.alloc(scan_tmp_bytes(n + 1) + 256);
+  t.small.alloc(256);
+  t.nbr_count.alloc((n + 1) * 4);
+  t.cand_sum.alloc((n + 1) * 8);
+  t.prod.alloc((n + 1) * 8);
+  ix.cell_key.alloc((n + 1) * 8);
+  ix.cell_start.alloc((n + 1) * 4);
+  ix.X.alloc(n * ix.dp * 4);
+  ix.orig_id.alloc(n * 4);
+  ix.pos_of.alloc(n * 4);
+
+  // k: explicit or chosen by the cost model over [k_min, k_max]
+  const uint32_t kcap = std::min<uint32_t>(d, kKeyMaxDims);
+  Geometry g;
+  if (ix.opt.k > 0) {
+    const uint32_t k = std::min<uint32_t>((uint32_t)ix.opt.k, kcap);
+    if (!make_geometry(ix, k, g))
+      fail(SJ_ERR_KEY_OVERFLOW, "the cell id over k=" + std::to_string(k) +
+                                    " dimensions does not fit in 63 bits");
+  } else {
+    const uint32_t k0 = std::max<uint32_t>(1, std::min(ix.opt.k_min ? ix.opt.k_min : 4u, kcap));
+    const uint32_t k1 = std::max(k0, std::min(ix.opt.k_max ? ix.opt.k_max : 8u, kcap));
+    double best = 0.0;
+    bool have = false;
+    for (uint32_t k = k0; k <= k1; ++k) {
+      Geometry gk;
+      if (!make_geometry(ix, k, gk)) break;  // longer keys would overflow: stop
+      const uint64_t C = build_grid(ix, P, gk, t, s, false);
+      const double cost = (double)C * 0.5 / kPairsPerSec +
+                          (double)ix.ncell * (double)gk.np.n_off / kLookupsPerSec;
+      if (!have || cost < best * (1.0 - 1e-9)) {
+        best = cost;
+        g = gk;
+        have = true;
+      }
+    }
+    if (!have) {
+      if (!make_geometry(ix, 1, g)) fail(SJ_ERR_KEY_OVERFLOW, "no usable k");
+    }
+  }
+  ix.k = g.k;
+  ix.candidates = build_grid(ix, P, g, t, s, true);
+
+  // candidate runs and the work units of the symmetric full join
+  ix.n_runs_sym = build_runs(ix, 1, ix.run_off_sym, ix.runs_sym, t, s);
+  ix.n_runs_full = build_runs(ix, 0, ix.run_off_full, ix.runs_full, t, s);
+  ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp);
+  uint64_t ev = 0;
+  DevBuf probe;
+  build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s);
+  ix.tc = choose_tc(ev, ix.tq);
+  ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc, ix.wu,
+                            &ix.evaluated_sym, s);
+
+  SJ_HIP(hipEventRecord(ev1.e, s));
+  SJ_HIP(hipEventSynchronize(ev1.e));
+  ix.info.ms_build = elapsed_ms(ev0, ev1);
+}
+
+// One launch of the distance kernel over a set of work units.
+void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
+                 const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
+                 hipStream_t s, float *ms) {
+  JoinLaunch a{};
+  a.X = ix.X.as<float>();
+  a.orig_id = ix.orig_id.as<uint32_t>();
+  a.inv_perm = ix.inv_perm_d.as<uint16_t>();
+  a.wu = wu.as<WorkUnit>();
+  a.n_wu = n_wu;
+  a.runs = runs.as<uint2>();
+  a.qlist = qlist;
+  a.d = ix.d;
+  a.dp = ix.dp;
+  a.lo = ix.lo32;
+  a.hi = ix.hi32;
+  a.eps2 = ix.eps2;
+  a.symmetric = sym;
+  a.count_only = count_only;
+  a.shortc = ix.opt.shortc ? 1 : 0;
+  a.out = out;
+  a.capacity = cap;
+  a.cursor = ix.counters.as<unsigned long long>();
+  a.rechecks = ix.counters.as<unsigned long long>() + 1;
+  a.rq = fp32_rq_for(ix.dp);
+  Event e0, e1;
+  SJ_HIP(hipEventRecord(e0.e, s));
+  launch_join_fp32(a, s);
+  SJ_HIP(hipEventRecord(e1.e, s));
+  SJ_HIP(hipEventSynchronize(e1.e));
+  *ms += elapsed_ms(e0, e1);
+}
+
+uint64_t read_counter(sj_index &ix, int which, hipStream_t s) {
+  uint64_t v = 0;
+  SJ_HIP(hipMemcpyAsync(&v, ix.counters.as<uint64_t>() + which, 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// Estimate |R| from a strided sample of query positions (Section 3.2.2:
+// a count-only pass over a fraction of the points).  Counts pairs the FP32
+// filter cannot reject, so it is an upper-bound estimate.
+uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
+  const uint64_t n = ix.n;
+  const uint64_t target = 32768;
+  const uint64_t stride = n <= target ? 1 : n / target;
+  const uint64_t nq = (n + stride - 1) / stride;
+  DevBuf ql, wu;
+  ql.alloc(nq * 4);
+  launch_iota_strided(ql.as<uint32_t>(), nq, stride, s);
+  uint64_t ev = 0;
+  const uint32_t tq = ix.tq;
+  const uint64_t nwu = build_workunits(ix, 0, ql.as<uint32_t>(), nq, ix.run_off_full,
+                                       ix.runs_full, tq, 4096, wu, &ev, s);
+  SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
+  join_launch(ix, wu, nwu, ix.runs_full, ql.as<uint32_t>(), 0, 1, nullptr, 0, s, ms);
+  const uint64_t cnt = read_counter(ix, 0, s);
+  const double est = (double)cnt * (double)n / (double)nq;
+  return (uint64_t)std::ceil(est);
+}
+
+uint64_t default_budget() {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1ull << 32;
+  }
+  return (uint64_t)((double)fr * 0.7);
+}
+
+void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s) {
+  const uint32_t bits = bits_for(ix.n ? ix.n - 1 : 0);
+  std::vector<int> sh = digit_shifts(bits, bits);
+  DevBuf tmp;
+  tmp.alloc(radix_tmp_bytes(cnt));
+  uint64_t *kb[2] = {a.as<uint64_t>(), b.as<uint64_t>()};
+  radix_sort_u64(kb, nullptr, cnt, sh.data(), (int)sh.size(), tmp.p, s);
+}
+
+// Single batch: symmetric join of all work units into device memory.
+void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
+  uint64_t cap = est + est / 8 + (1u << 20);
+  float ms_join = 0.0f;
+  DevBuf other;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    ix.pairs.alloc(cap * 8);
+    SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
+    join_launch(ix, ix.wu, ix.n_wu, ix.runs_sym, nullptr, 1, 0, ix.pairs.as<uint64_t>(), cap, s,
+                &ms_join);
+    ix.info.join_launches++;
+    const uint64_t got = read_counter(ix, 0, s);
+    if (got <= cap) {
+      ix.total = got;
+      break;
+    }
+    cap = got;  // exact now
+    if (attempt == 2) fail(SJ_ERR_DEVICE, "result count did not settle");
+  }
+  ix.info.rechecks = read_counter(ix, 1, s);
+  ix.info.ms_join += ms_join;
+  Event e0, e1;
+  SJ_HIP(hipEventRecord(e0.e, s));
+  other.alloc(ix.total * 8);
+  sort_pairs(ix, ix.pairs, other, ix.total, s);
+  SJ_HIP(hipEventRecord(e1.e, s));
+  SJ_HIP(hipEventSynchronize(e1.e));
+  ix.info.ms_sort += elapsed_ms(e0, e1);
+  ix.info.batches = 1;
+  ix.info.evaluated = ix.evaluated_sym;
+  ix.on_host = false;
+}
+
+// Several batches over ranges of caller indices, each a one-directional join
+// of its queries against their adjacent cells, sorted and copied to pinned
+// host memory while the next batch computes (Section 3.2.2, Figure 5).
+void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) {
+  const uint64_t n = ix.n;
+  uint64_t nb = std::max<uint64_t>(1, (est + per_batch - 1) / per_batch);
+  nb = std::max<uint64_t>(nb, ix.opt.min_batches ? ix.opt.min_batches : 1);
+  nb = std::min<uint64_t>(nb, n);
+  hipStream_t cs = nullptr;
+  SJ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  struct Slot {
+    DevBuf keys, tmp2;
+    Event done_copy;
+    bool busy = false;
+  } slots[2];
+  ix.host_res.clear();
+  ix.host_cnt.clear();
+  ix.total = 0;
+  ix.info.rechecks = 0;
+  uint64_t evaluated = 0;
+  float ms_join = 0.0f;
+  std::vector<std::pair<uint64_t, uint64_t>> ranges;
+  for (uint64_t b = 0; b < nb; ++b) ranges.push_back({n * b / nb, n * (b + 1) / nb});
+  const uint32_t bits = bits_for(n - 1);
+  uint64_t slot = 0;
+  for (size_t bi = 0; bi < ranges.size(); ++bi) {
+    const uint64_t i0 = ranges[bi].first, i1 = ranges[bi].second;
+    if (i1 <= i0) continue;
+    const uint64_t nq = i1 - i0;
+    // positions of the batch's queries, ascending
+    DevBuf qk[2], rt;
+    qk[0].alloc(nq * 8);
+    qk[1].alloc(nq * 8);
+    {
+      // positions of the caller indices [i0, i1), sorted on the device
+      std::vector<int> sh;
+      for (uint32_t b = 0; b < bits; b += 8) sh.push_back((int)b);
+      DevBuf p32;
+      p32.alloc(nq * 4);
+      launch_widen(ix.pos_of.as<uint32_t>() + i0, qk[0].as<uint64_t>(), nq, s);
+      rt.alloc(radix_tmp_bytes(nq));
+      uint64_t *kb[2] = {qk[0].as<uint64_t>(), qk[1].as<uint64_t>()};
+      radix_sort_u64(kb, nullptr, nq, sh.data(), (int)sh.size(), rt.p, s);
+      launch_narrow(kb[0], p32.as<uint32_t>(), nq, s);
+      DevBuf wu;
+      uint64_t ev = 0;
+      const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
+                                           ix.runs_full, ix.tq, ix.tc, wu, &ev, s);
+      evaluated += ev;
+      Slot &sl = slots[slot & 1];
+      if (sl.busy) {
+        SJ_HIP(hipEventSynchronize(sl.done_copy.e));
+        sl.busy = false;
+      }
+      uint64_t cap = per_batch + per_batch / 8 + (1u << 16);
+      uint64_t got = 0;
+      for (int attempt = 0; attempt < 3; ++attempt) {
+        sl.keys.ensure(cap * 8);
+        SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
+        join_launch(ix, wu, nwu, ix.runs_full, p32.as<uint32_t>(), 0, 0, sl.keys.as<uint64_t>(),
+                    cap, s, &ms_join);
+        ix.info.join_launches++;
+        got = read_counter(ix, 0, s);
+        if (got <= cap) break;
+        cap = got;
+      }
+      ix.info.rechecks += read_counter(ix, 1, s);
+      sl.tmp2.ensure(std::max<uint64_t>(got, 1) * 8);
+      Event e0, e1;
+      SJ_HIP(hipEventRecord(e0.e, s));
+      sort_pairs(ix, sl.keys, sl.tmp2, got, s);
+      SJ_HIP(hipEventRecord(e1.e, s));
+      PinnedBuf hb;
+      hb.alloc(std::max<uint64_t>(got, 1) * 8);
+      Event ready;
+      SJ_HIP(hipEventRecord(ready.e, s));
+      SJ_HIP(hipStreamWaitEvent(cs, ready.e, 0));
+      SJ_HIP(hipMemcpyAsync(hb.p, sl.keys.p, got * 8, hipMemcpyDeviceToHost, cs));
+      SJ_HIP(hipEventRecord(sl.done_copy.e, cs));
+      sl.busy = true;
+      SJ_HIP(hipEventSynchronize(e1.e));
+      ix.info.ms_sort += elapsed_ms(e0, e1);
+      ix.host_res.push_back(std::move(hb));
+      ix.host_cnt.push_back(got);
+      ix.total += got;
+      ++slot;
+    }
+  }
+  SJ_HIP(hipStreamSynchronize(cs));
+  SJ_HIP(hipStreamDestroy(cs));
+  ix.info.ms_join += ms_join;
+  ix.info.batches = (uint32_t)ix.host_res.size();
+  ix.info.evaluated = evaluated;
+  ix.on_host = true;
+}
+
+void run(sj_index &ix, hipStream_t s) {
+  ix.info.ms_join = 0.0f;
+  ix.info.ms_sort = 0.0f;
+  ix.info.join_launches = 0;
+  Event e0, e1;
+  SJ_HIP(hipEventRecord(e0.e, s));
+  ix.pairs.reset();
+  ix.host_res.clear();
+  ix.host_cnt.clear();
+  if (ix.n == 0) {
+    ix.total = 0;
+    ix.info.batches = 0;
+  } else {
+    float ms_est = 0.0f;
+    const uint64_t est = estimate_pairs(ix, s, &ms_est);
+    const uint64_t budget = ix.opt.mem_budget ? ix.opt.mem_budget : default_budget();
+    // a single batch holds the keys twice (sort ping-pong) plus sort scratch
+    const uint64_t fit = budget / 20;
+    uint64_t per_batch = ix.opt.batch_pairs ? ix.opt.batch_pairs : fit;
+    per_batch = std::min(per_batch, fit);
+    per_batch = std::min<uint64_t>(per_batch, 0xF0000000ull);
+    const uint32_t min_b = ix.opt.min_batches;
+    if (est + est / 8 <= per_batch && min_b <= 1)
+      run_single(ix, est, s);
+    else
+      run_batched(ix, est, std::max<uint64_t>(per_batch, 1), s);
+  }
+  SJ_HIP(hipEventRecord(e1.e, s));
+  SJ_HIP(hipEventSynchronize(e1.e));
+  ix.info.ms_run = elapsed_ms(e0, e1);
+  ix.info.pairs = ix.total;
+  ix.info.result_on_host = ix.on_host ? 1u : 0u;
+  ix.ran = true;
+}
+
+void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint32_t *oj,
+           float *od, uint64_t *n_written, hipStream_t s) {
+  if (!ix.ran) fail(SJ_ERR_STATE, "fetch before a successful run");
+  if (first > ix.total) fail(SJ_ERR_RANGE, "first is beyond the result");
+  const uint64_t cnt = std::min(max_pairs, ix.total - first);
+  const bool dev_i = !oi || is_device_pointer(oi);
+  const bool dev_j = !oj || is_device_pointer(oj);
+  const bool dev_d = !od || is_device_pointer(od);
+  const bool all_dev = dev_i && dev_j && dev_d;
+  const uint64_t chunk = 1ull << 24;
+  DevBuf keys_stage, si, sj2, sd;
+  uint64_t done = 0;
+  while (done < cnt) {
+    const uint64_t c = std::min(chunk, cnt - done);
+    const uint64_t g = first + done;  // global index of the chunk's first pair
+    const uint64_t *src = nullptr;
+    if (!ix.on_host) {
+      src = ix.pairs.as<uint64_t>() + g;
+    } else {
+      // locate the batch holding pair g, copy up to c keys from host storage
+      keys_stage.ensure(c * 8);
+      uint64_t off = 0, copied = 0, gg = g;
+      for (size_t b = 0; b < ix.host_res.size() && copied < c; ++b) {
+        const uint64_t bc = ix.host_cnt[b];
+        if (gg >= off + bc) { off += bc; continue; }
+        const uint64_t from = gg - off;
+        const uint64_t take = std::min(bc - from, c - copied);
+        SJ_HIP(hipMemcpyAsync(keys_stage.as<uint64_t>() + copied,
+                              static_cast<uint64_t *>(ix.host_res[b].p) + from, take * 8,
+                              hipMemcpyHostToDevice, s));
+        copied += take;
+        gg += take;
+        off += bc;
+      }
+      src = keys_stage.as<uint64_t>();
+    }
+    if (all_dev) {
+      launch_unpack(src, c, oi ? oi + done : nullptr, oj ? oj + done : nullptr,
+                    od ? od + done : nullptr, ix.X.as<float>(), ix.pos_of.as<uint32_t>(),
+                    ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s);
+    } else {
+      si.ensure(c * 4);
+      sj2.ensure(c * 4);
+      sd.ensure(c * 4);
+      launch_unpack(src, c, oi ? si.as<uint32_t>() : nullptr, oj ? sj2.as<uint32_t>() : nullptr,
+                    od ? sd.as<float>() : nullptr, ix.X.as<float>(), ix.pos_of.as<uint32_t>(),
+                    ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s);
+      if (oi) SJ_HIP(hipMemcpyAsync(oi + done, si.p, c * 4, hipMemcpyDefault, s));
+      if (oj) SJ_HIP(hipMemcpyAsync(oj + done, sj2.p, c * 4, hipMemcpyDefault, s));
+      if (od) SJ_HIP(hipMemcpyAsync(od + done, sd.p, c * 4, hipMemcpyDefault, s));
+    }
+    SJ_HIP(hipStreamSynchronize(s));
+    done += c;
+  }
+  SJ_HIP(hipStreamSynchronize(s));
+  *n_written = cnt;
+}
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    f();
+    return SJ_OK;
+  } catch (const Error &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return SJ_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return SJ_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+}  // namespace sj
+
+extern "C" {
+
+void selfjoin_default_options(sj_options *opts) {
+  if (opts) sj::fill_defaults(opts);
+}
+
+int selfjoin_build_index(const float *points, uint64_t n, uint32_t d, double epsilon,
+                         const sj_options *opts, void *stream, sj_index **out) {
+  return sj::guarded([&] {
+    if (!out) fail(SJ_ERR_INVALID_ARG, "out is NULL");
+    if (d == 0 || d > SJ_MAX_DIM)
+      fail(SJ_ERR_INVALID_ARG, "d must be in [1, " + std::to_string(SJ_MAX_DIM) + "]");
+    if (n > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "n must be below 2^32");
+    if (n > 0 && !points) fail(SJ_ERR_INVALID_ARG, "points is NULL");
+    if (!std::isfinite(epsilon) || !(epsilon > 0.0))
+      fail(SJ_ERR_INVALID_ARG, "epsilon must be finite and > 0");
+    const double eps2 = epsilon * epsilon;
+    if (!std::isfinite(eps2)) fail(SJ_ERR_INVALID_ARG, "epsilon^2 overflows");
+    sj_options o;
+    sj::fill_defaults(&o);
+    if (opts) {
+      if (opts->struct_size < offsetof(sj_options, reserved0) || opts->struct_size > sizeof(o))
+        fail(SJ_ERR_INVALID_ARG, "sj_options.struct_size is not a known size");
+      std::memcpy(&o, opts, opts->struct_size);
+      o.struct_size = sizeof(o);
+    }
+    if (o.precision != SJ_PREC_FP32) fail(SJ_ERR_INVALID_ARG, "unknown precision");
+    if (o.k < 0) fail(SJ_ERR_INVALID_ARG, "k must be >= 0");
+    std::unique_ptr<sj_index> ix(new sj_index());
+    SJ_HIP(hipGetDevice(&ix->device));
+    ix->n = n;
+    ix->d = d;
+    ix->eps = epsilon;
+    ix->eps2 = eps2;
+    ix->opt = o;
+    ix->info.struct_size = sizeof(sj_info);
+    sj::build(*ix, points, static_cast<hipStream_t>(stream));
+    *out = ix.release();
+  });
+}
+
+int selfjoin_run(sj_index *idx, void *stream, uint64_t *total_pairs) {
+  return sj::guarded([&] {
+    if (!idx || !total_pairs) fail(SJ_ERR_INVALID_ARG, "NULL argument");
+    if (!idx->ran) sj::run(*idx, static_cast<hipStream_t>(stream));
+    *total_pairs = idx->total;
+  });
+}
+
+int selfjoin_fetch_pairs(sj_index *idx, uint64_t first, uint64_t max_pairs, uint32_t *out_i,
+                         uint32_t *out_j, float *out_dist, uint64_t *n_written, void *stream) {
+  return sj::guarded([&] {
+    if (!idx || !n_written) fail(SJ_ERR_INVALID_ARG, "NULL argument");
+    sj::fetch(*idx, first, max_pairs, out_i, out_j, out_dist, n_written,
+              static_cast<hipStream_t>(stream));
+  });
+}
+
+int selfjoin_get_info(const sj_index *idx, sj_info *info) {
+  return sj::guarded([&] {
+    if (!idx || !info) fail(SJ_ERR_INVALID_ARG, "NULL argument");
+    if (info->struct_size < sizeof(uint32_t) || info->struct_size > sizeof(sj_info))
+      fail(SJ_ERR_INVALID_ARG, "sj_info.struct_size is not a known size");
+    sj_info x = idx->info;
+    x.struct_size = info->struct_size;
+    x.d = idx->d;
+    x.n = idx->n;
+    x.epsilon = idx->eps;
+    x.k = idx->k;
+    x.precision = idx->opt.precision;
+    x.n_cells = idx->ncell;
+    x.candidates = idx->candidates;
+    if (!idx->ran) x.evaluated = idx->evaluated_sym;
+    std::memcpy(info, &x, info->struct_size);
+  });
+}
+
+int selfjoin_get_perm(const sj_index *idx, uint32_t *perm, uint32_t cap) {
+  return sj::guarded([&] {
+    if (!idx || (!perm && cap)) fail(SJ_ERR_INVALID_ARG, "NULL argument");
+    for (uint32_t r = 0; r < std::min<uint32_t>(cap, idx->d); ++r) perm[r] = idx->perm[r];
+  });
+}
+
+void selfjoin_free(sj_index *idx) { delete idx; }
+
+const char *selfjoin_last_error(void) { return sj::g_last_error.c_str(); }
+
+}  // extern "C"

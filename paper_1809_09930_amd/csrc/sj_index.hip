@@ -1,0 +1,469 @@
+// Grid index build on the device (Section 3.2.1 grid index, Section 4.1
+// indexing k of the n dimensions, Section 4.2 variance reorder):
+//   ingest/validate -> per-dimension min/max, sample variance -> cell keys
+//   over the first k reordered dimensions -> radix sort by key -> gather the
+//   points in cell order (reordered, zero-padded rows) -> compact the
+//   non-empty cells -> adjacent cells by binary search in an LDS-staged key
+//   table -> candidate runs -> work units for the distance kernels.
+#include "sj_index.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace sj {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// a1: per-dimension min/max of the caller's rows and a non-finite flag.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_minmax(const float *__restrict__ P, uint64_t total,
+                                                   uint32_t d, uint32_t *__restrict__ gmin,
+                                                   uint32_t *__restrict__ gmax,
+                                                   uint32_t *__restrict__ bad) {
+  __shared__ uint32_t smin[SJ_MAX_DIM], smax[SJ_MAX_DIM];
+  __shared__ uint32_t sbad;
+  for (uint32_t t = threadIdx.x; t < d; t += kBlock) {
+    smin[t] = 0xffffffffu;
+    smax[t] = 0u;
+  }
+  if (threadIdx.x == 0) sbad = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint32_t step = (uint32_t)(stride % d);
+  uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t t = (uint32_t)(e % d);
+  uint32_t lmin = 0xffffffffu, lmax = 0u;
+  uint32_t lt = t;  // dimension the local min/max belongs to (only when step == 0)
+  for (; e < total; e += stride) {
+    const float v = P[e];
+    if (!__builtin_isfinite(v)) {
+      sbad = 1;
+    } else {
+      const uint32_t u = float_to_ordered(v);
+      if (step == 0) {
+        lmin = min(lmin, u);
+        lmax = max(lmax, u);
+      } else {
+        atomicMin(&smin[t], u);
+        atomicMax(&smax[t], u);
+      }
+    }
+    t += step;
+    if (t >= d) t -= d;
+  }
+  if (step == 0 && lmax != 0u) {
+    atomicMin(&smin[lt], lmin);
+    atomicMax(&smax[lt], lmax);
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < d; q += kBlock) {
+    if (smax[q] != 0u) {
+      atomicMin(&gmin[q], smin[q]);
+      atomicMax(&gmax[q], smax[q]);
+    }
+  }
+  if (threadIdx.x == 0 && sbad) atomicOr(bad, 1u);
+}
+
+__global__ void k_init_minmax(uint32_t *gmin, uint32_t *gmax, uint32_t *bad, uint32_t d) {
+  for (uint32_t t = threadIdx.x; t < d; t += blockDim.x) {
+    gmin[t] = 0xffffffffu;
+    gmax[t] = 0u;
+  }
+  if (threadIdx.x == 0) *bad = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// a2: variance of every dimension over a strided sample (one workgroup per
+// dimension, fixed-order reductions: deterministic).
+// ---------------------------------------------------------------------------
+__device__ double block_sum_f64(double v) {
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_variance(const float *__restrict__ P, uint32_t d,
+                                                     uint64_t stride, uint64_t m,
+                                                     double *__restrict__ var) {
+  const uint32_t t = blockIdx.x;
+  double s = 0.0;
+  for (uint64_t i = threadIdx.x; i < m; i += kBlock) s += (double)P[i * stride * d + t];
+  const double mean = block_sum_f64(s) / (double)m;
+  double q = 0.0;
+  for (uint64_t i = threadIdx.x; i < m; i += kBlock) {
+    const double x = (double)P[i * stride * d + t] - mean;
+    q += x * x;
+  }
+  const double ss = block_sum_f64(q);
+  if (threadIdx.x == 0) var[t] = m > 1 ? ss / (double)(m - 1) : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// a3: linearised cell key over the first k reordered dimensions.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_cellkey(const float *__restrict__ P, uint64_t n,
+                                                    uint32_t d, KeyParams kp,
+                                                    uint64_t *__restrict__ keys,
+                                                    uint32_t *__restrict__ ids) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint64_t key = 0;
+  for (uint32_t r = 0; r < kp.k; ++r) {
+    const double x = (double)P[i * d + kp.dim[r]];
+    double c = floor((x - kp.org[r]) / kp.w);
+    c = c < 0.0 ? 0.0 : c;
+    uint64_t ci = (uint64_t)c;
+    ci = ci > kp.cmax[r] ? kp.cmax[r] : ci;
+    key += ci * kp.mult[r];
+  }
+  keys[i] = key;
+  ids[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// a4: gather rows in cell order: X[p][r] = P[id_p][perm[r]], zero padded.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ P, uint64_t n,
+                                                   uint32_t d, uint32_t dp,
+                                                   const uint32_t *__restrict__ perm,
+                                                   const uint32_t *__restrict__ sorted_ids,
+                                                   float *__restrict__ X,
+                                                   uint32_t *__restrict__ orig_id,
+                                                   uint32_t *__restrict__ pos_of) {
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n * dp) return;
+  const uint64_t p = e / dp;
+  const uint32_t r = (uint32_t)(e - p * dp);
+  const uint32_t id = sorted_ids[p];
+  X[e] = r < d ? P[(uint64_t)id * d + perm[r]] : 0.0f;
+  if (r == 0) {
+    orig_id[p] = id;
+    pos_of[id] = (uint32_t)p;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5: compaction of the non-empty cells.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_cell_flags(const uint64_t *__restrict__ keys,
+                                                       uint64_t n, uint32_t *__restrict__ flag) {
+  const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  flag[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_write(const uint64_t *__restrict__ keys,
+                                                       uint64_t n,
+                                                       const uint32_t *__restrict__ cidx,
+                                                       uint64_t *__restrict__ cell_key,
+                                                       uint32_t *__restrict__ cell_start) {
+  const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n) return;
+  const bool first = (p == 0 || keys[p] != keys[p - 1]);
+  if (first) {
+    cell_key[cidx[p]] = keys[p];
+    cell_start[cidx[p]] = (uint32_t)p;
+  }
+  // cell index of p is cidx[p] when p starts a cell, else cidx[p] - 1
+  if (p == n - 1) cell_start[cidx[p] + (first ? 1u : 0u)] = (uint32_t)n;
+}
+
+// ---------------------------------------------------------------------------
+// a6: adjacent non-empty cells (Section 3.2.1: only the 3^k cells around a
+// query cell can hold its neighbours; Section 5.5: each is found by binary
+// search over the non-empty cell ids).  One wave per query cell, 64 offsets
+// per step; the cell-key table is staged in LDS, whole when it fits, else
+// as a fence of every stride-th key that narrows the search to a short
+// stretch of the table in global memory.
+// ---------------------------------------------------------------------------
+constexpr int kFenceMax = 8192;  // 64 KiB of u64 keys in LDS
+
+__device__ __forceinline__ int64_t find_cell(uint64_t key, const uint64_t *__restrict__ fence,
+                                             uint32_t nfence, uint32_t fstride,
+                                             const uint64_t *__restrict__ cell_key,
+                                             uint64_t ncell) {
+  // last fence entry <= key
+  uint32_t lo = 0, hi = nfence;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (fence[mid] <= key) lo = mid + 1; else hi = mid;
+  }
+  if (lo == 0) return -1;
+  const uint32_t f = lo - 1;
+  if (fstride == 1) return fence[f] == key ? (int64_t)f : -1;
+  uint64_t a = (uint64_t)f * fstride, b = a + fstride;
+  if (b > ncell) b = ncell;
+  while (a < b) {
+    const uint64_t mid = (a + b) >> 1;
+    if (cell_key[mid] < key) a = mid + 1; else b = mid;
+  }
+  return (a < ncell && cell_key[a] == key) ? (int64_t)a : -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_neighbors(
+    int pass, const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ cell_start,
+    uint64_t ncell, NbrParams np, uint32_t *__restrict__ nbr_count,
+    uint64_t *__restrict__ cand_sum, const uint32_t *__restrict__ nbr_off,
+    uint32_t *__restrict__ nbr_cell) {
+  __shared__ uint64_t fence[kFenceMax];
+  for (uint32_t i = threadIdx.x; i < np.nfence; i += kBlock)
+    fence[i] = cell_key[(uint64_t)i * np.fstride];
+  __syncthreads();
+  const uint32_t l = lane_id();
+  const uint64_t wid = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  const uint64_t nw = (uint64_t)gridDim.x * kWavesPerBlock;
+  for (uint64_t A = wid; A < ncell; A += nw) {
+    const uint64_t keyA = cell_key[A];
+    int64_t cA[kKeyMaxDims];
+    for (uint32_t r = 0; r < np.k; ++r) cA[r] = (int64_t)((keyA / np.mult[r]) % np.m[r]);
+    uint32_t count = 0, wpos = (pass == 1) ? nbr_off[A] : 0u;
+    uint64_t csum = 0;
+    for (uint64_t base = 0; base < np.n_off; base += kWave) {
+      const uint64_t o = base + l;
+      bool ok = o < np.n_off;
+      uint64_t keyB = keyA;
+      uint64_t rem = o;
+      for (int r = (int)np.k - 1; r >= 0; --r) {  // dimension 0 is the most significant digit
+        const int64_t delta = (int64_t)(rem % 3) - 1;
+        rem /= 3;
+        const int64_t c = cA[r] + delta;
+        ok = ok && c >= 0 && c < (int64_t)np.m[r];
+        keyB += (uint64_t)delta * np.mult[r];
+      }
+      int64_t B = -1;
+      if (ok) B = find_cell(keyB, fence, np.nfence, np.fstride, cell_key, ncell);
+      const bool found = B >= 0;
+      const uint64_t m = ballot(found);
+      if (pass == 0) {
+        count += (uint32_t)__builtin_popcountll(m);
+        if (found) csum += (uint64_t)(cell_start[B + 1] - cell_start[B]);
+      } else {
+        if (found) nbr_cell[wpos + lanes_below(m)] = (uint32_t)B;
+        wpos += (uint32_t)__builtin_popcountll(m);
+      }
+    }
+    if (pass == 0) {
+      // wave-wide sum of the candidate counts
+      for (int off = 32; off > 0; off >>= 1) csum += __shfl_xor(csum, off);
+      if (l == 0) {
+        nbr_count[A] = count;
+        cand_sum[A] = csum;
+      }
+    }
+  }
+}
+
+// Candidate runs: maximal stretches of consecutive cell indices in A's
+// (sorted) neighbour list, as position ranges.  sym = 1 keeps only B >= A.
+__global__ __launch_bounds__(kBlock) void k_runs(int pass, int sym, uint64_t ncell,
+                                                 const uint32_t *__restrict__ cell_start,
+                                                 const uint32_t *__restrict__ nbr_off,
+                                                 const uint32_t *__restrict__ nbr_cell,
+                                                 uint32_t *__restrict__ run_count,
+                                                 const uint32_t *__restrict__ run_off,
+                                                 uint2 *__restrict__ runs) {
+  const uint64_t A = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (A >= ncell) return;
+  const uint32_t b0 = nbr_off[A], b1 = nbr_off[A + 1];
+  uint32_t cnt = 0, w = pass ? run_off[A] : 0u;
+  uint32_t i = b0;
+  while (i < b1) {
+    uint32_t B = nbr_cell[i];
+    if (sym && B < A) { ++i; continue; }
+    uint32_t last = B;
+    ++i;
+    while (i < b1 && nbr_cell[i] == last + 1) { last = nbr_cell[i]; ++i; }
+    if (pass) runs[w++] = make_uint2(cell_start[B], cell_start[last + 1]);
+    ++cnt;
+  }
+  if (!pass) run_count[A] = cnt;
+}
+
+// Work units (see WorkUnit).  Query slots of cell A are [qa, qb): positions
+// in contiguous mode, indices into the sorted query list in list mode.
+// In symmetric mode the first run of A starts at A itself and each query
+// block only looks at candidates from its own first query onwards.
+__device__ __forceinline__ void cell_query_slots(uint64_t A, const uint32_t *__restrict__ cell_start,
+                                                 const uint32_t *__restrict__ qlist, uint64_t nq,
+                                                 uint32_t *qa, uint32_t *qb) {
+  const uint32_t s = cell_start[A], e = cell_start[A + 1];
+  if (!qlist) {
+    *qa = s;
+    *qb = e;
+    return;
+  }
+  uint64_t lo = 0, hi = nq;
+  while (lo < hi) { uint64_t m = (lo + hi) >> 1; if (qlist[m] < s) lo = m + 1; else hi = m; }
+  *qa = (uint32_t)lo;
+  hi = nq;
+  while (lo < hi) { uint64_t m = (lo + hi) >> 1; if (qlist[m] < e) lo = m + 1; else hi = m; }
+  *qb = (uint32_t)lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_workunits(
+    int pass, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+    const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qlist, uint64_t nq,
+    const uint32_t *__restrict__ run_off, const uint2 *__restrict__ runs,
+    uint32_t *__restrict__ wu_count, uint64_t *__restrict__ eval, const uint32_t *__restrict__ wu_off,
+    WorkUnit *__restrict__ wu) {
+  const uint64_t A = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (A >= ncell) return;
+  uint32_t qa, qb;
+  cell_query_slots(A, cell_start, qlist, nq, &qa, &qb);
+  const uint32_t r0 = run_off[A], r1 = run_off[A + 1];
+  uint64_t total = 0;
+  for (uint32_t r = r0; r < r1; ++r) total += runs[r].y - runs[r].x;
+  uint32_t units = 0;
+  uint64_t ev = 0;
+  uint32_t w = pass ? wu_off[A] : 0u;
+  for (uint32_t q0 = qa; q0 < qb; q0 += tq) {
+    const uint32_t q1 = min(q0 + tq, qb);
+    // symmetric: the first run starts at A; skip candidates before q0
+    const uint32_t skip = (sym && r1 > r0) ? (q0 - runs[r0].x) : 0u;
+    const uint64_t L = total - skip;
+    if (L == 0) continue;
+    const uint32_t nu = (uint32_t)((L + tc - 1) / tc);
+    units += nu;
+    ev += (uint64_t)(q1 - q0) * L;
+    if (pass) {
+      uint32_t r = r0;
+      uint32_t c = runs[r0].x + skip;
+      for (uint32_t u = 0; u < nu; ++u) {
+        WorkUnit x;
+        x.q0 = q0;
+        x.q1 = q1;
+        x.cell = (uint32_t)A;
+        x.pad = 0;
+        x.run_first = r;
+        x.c_begin = c;
+        uint32_t need = tc;
+        for (;;) {
+          const uint32_t avail = runs[r].y - c;
+          if (avail > need) { c += need; break; }
+          need -= avail;
+          if (r + 1 == r1 || need == 0) { c = runs[r].y; break; }
+          ++r;
+          c = runs[r].x;
+        }
+        x.run_last = r;
+        x.c_end = c;
+        wu[w++] = x;
+        if (c == runs[r].y && r + 1 < r1) { ++r; c = runs[r].x; }
+      }
+    }
+  }
+  if (!pass) {
+    wu_count[A] = units;
+    eval[A] = ev;
+  }
+}
+
+__global__ void k_cell_products(uint64_t ncell, const uint32_t *__restrict__ cell_start,
+                                const uint64_t *__restrict__ cand_sum, uint64_t *__restrict__ out) {
+  const uint64_t A = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (A >= ncell) return;
+  out[A] = (uint64_t)(cell_start[A + 1] - cell_start[A]) * cand_sum[A];
+}
+
+inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host-side launchers
+// ---------------------------------------------------------------------------
+void launch_minmax(const float *P, uint64_t n, uint32_t d, uint32_t *gmin, uint32_t *gmax,
+                   uint32_t *bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_minmax, dim3(1), dim3(kBlock), 0, s, gmin, gmax, bad, d);
+  SJ_HIP(hipGetLastError());
+  const uint64_t total = n * d;
+  if (total == 0) return;
+  uint32_t grid = (uint32_t)std::min<uint64_t>((total + kBlock - 1) / kBlock, 2048);
+  hipLaunchKernelGGL(k_minmax, dim3(grid), dim3(kBlock), 0, s, P, total, d, gmin, gmax, bad);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_variance(const float *P, uint32_t d, uint64_t stride, uint64_t m, double *var,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_variance, dim3(d), dim3(kBlock), 0, s, P, d, stride, m, var);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_cellkey(const float *P, uint64_t n, uint32_t d, const KeyParams &kp, uint64_t *keys,
+                    uint32_t *ids, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cellkey, dim3(blocks_for(n)), dim3(kBlock), 0, s, P, n, d, kp, keys, ids);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const uint32_t *perm,
+                   const uint32_t *sorted_ids, float *X, uint32_t *orig_id, uint32_t *pos_of,
+                   hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n * dp)), dim3(kBlock), 0, s, P, n, d, dp, perm,
+                     sorted_ids, X, orig_id, pos_of);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_compact(const uint64_t *keys, uint64_t n, uint32_t *flag_tmp, uint32_t *d_ncell,
+                    uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_cell_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, keys, n, flag_tmp);
+  SJ_HIP(hipGetLastError());
+  exclusive_scan_u32(flag_tmp, flag_tmp, n, d_ncell, scan_tmp, s);
+  hipLaunchKernelGGL(k_cell_write, dim3(blocks_for(n)), dim3(kBlock), 0, s, keys, n, flag_tmp,
+                     cell_key, cell_start);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_neighbors(int pass, const uint64_t *cell_key, const uint32_t *cell_start,
+                      uint64_t ncell, const NbrParams &np, uint32_t *nbr_count, uint64_t *cand_sum,
+                      const uint32_t *nbr_off, uint32_t *nbr_cell, hipStream_t s) {
+  if (!ncell) return;
+  const uint64_t waves = ncell;
+  uint32_t grid = (uint32_t)std::min<uint64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 4096);
+  hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(kBlock), 0, s, pass, cell_key, cell_start,
+                     ncell, np, nbr_count, cand_sum, nbr_off, nbr_cell);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
+                 const uint32_t *nbr_off, const uint32_t *nbr_cell, uint32_t *run_count,
+                 const uint32_t *run_off, uint2 *runs, hipStream_t s) {
+  if (!ncell) return;
+  hipLaunchKernelGGL(k_runs, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, pass, sym, ncell,
+                     cell_start, nbr_off, nbr_cell, run_count, run_off, runs);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_workunits(int pass, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+                      const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
+                      const uint32_t *run_off, const uint2 *runs, uint32_t *wu_count,
+                      uint64_t *eval, const uint32_t *wu_off, WorkUnit *wu, hipStream_t s) {
+  if (!ncell) return;
+  hipLaunchKernelGGL(k_workunits, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, pass, sym, ncell,
+                     tq, tc, cell_start, qlist, nq, run_off, runs, wu_count, eval, wu_off, wu);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
+                          uint64_t *out, hipStream_t s) {
+  if (!ncell) return;
+  hipLaunchKernelGGL(k_cell_products, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, ncell,
+                     cell_start, cand_sum, out);
+  SJ_HIP(hipGetLastError());
+}
+
+}  // namespace sj

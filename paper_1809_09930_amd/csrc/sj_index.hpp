@@ -1,0 +1,55 @@
+// Index-build launchers (sj_index.hip).
+#pragma once
+
+#include "sj_internal.hpp"
+
+namespace sj {
+
+constexpr int kKeyMaxDims = 16;  // most dimensions one linearised cell key covers
+
+// Cell key of a point: sum over r < k of c_r * mult[r], with
+// c_r = clamp(floor(((double)x[dim[r]] - org[r]) / w), 0, cmax[r]).
+struct KeyParams {
+  uint32_t k;
+  uint32_t dim[kKeyMaxDims];
+  double org[kKeyMaxDims];
+  uint64_t mult[kKeyMaxDims];
+  uint64_t cmax[kKeyMaxDims];
+  double w;
+};
+
+// Decoding and neighbour search over the cell-key table.
+struct NbrParams {
+  uint32_t k;
+  uint64_t mult[kKeyMaxDims];
+  uint64_t m[kKeyMaxDims];  // cells along each indexed dimension
+  uint64_t n_off;           // 3^k
+  uint32_t nfence;          // LDS fence entries
+  uint32_t fstride;         // table entries per fence entry (1: whole table in LDS)
+};
+
+void launch_minmax(const float *P, uint64_t n, uint32_t d, uint32_t *gmin, uint32_t *gmax,
+                   uint32_t *bad, hipStream_t s);
+void launch_variance(const float *P, uint32_t d, uint64_t stride, uint64_t m, double *var,
+                     hipStream_t s);
+void launch_cellkey(const float *P, uint64_t n, uint32_t d, const KeyParams &kp, uint64_t *keys,
+                    uint32_t *ids, hipStream_t s);
+void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const uint32_t *perm,
+                   const uint32_t *sorted_ids, float *X, uint32_t *orig_id, uint32_t *pos_of,
+                   hipStream_t s);
+void launch_compact(const uint64_t *keys, uint64_t n, uint32_t *flag_tmp, uint32_t *d_ncell,
+                    uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp, hipStream_t s);
+void launch_neighbors(int pass, const uint64_t *cell_key, const uint32_t *cell_start,
+                      uint64_t ncell, const NbrParams &np, uint32_t *nbr_count, uint64_t *cand_sum,
+                      const uint32_t *nbr_off, uint32_t *nbr_cell, hipStream_t s);
+void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
+                 const uint32_t *nbr_off, const uint32_t *nbr_cell, uint32_t *run_count,
+                 const uint32_t *run_off, uint2 *runs, hipStream_t s);
+void launch_workunits(int pass, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+                      const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
+                      const uint32_t *run_off, const uint2 *runs, uint32_t *wu_count,
+                      uint64_t *eval, const uint32_t *wu_off, WorkUnit *wu, hipStream_t s);
+void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
+                          uint64_t *out, hipStream_t s);
+
+}  // namespace sj

@@ -1,0 +1,145 @@
+// Internal declarations shared by the translation units of libselfjoin.
+// Everything here is gfx950 (CDNA4, wave64) code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "../../include/selfjoin.h"
+
+namespace sj {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;            // 4 waves per workgroup everywhere
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// A library error carried as an exception inside the library only; the C ABI
+// converts it into a return code plus the thread-local message.
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define SJ_HIP(call) ::sj::check_hip((call), #call)
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Number of set bits of `mask` in lanes below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  uint32_t lo = uniform_u32((uint32_t)v), hi = uniform_u32((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// float <-> order-preserving uint32 (for atomic min/max of finite floats)
+__device__ __host__ __forceinline__ uint32_t float_to_ordered(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __host__ __forceinline__ float ordered_to_float(uint32_t u) {
+  uint32_t b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+  return __builtin_bit_cast(float, b);
+}
+
+// ---------------------------------------------------------------------------
+// Work units of the distance kernels.
+//
+// A work unit pairs a block of up to 64*RQ query points of one cell A with a
+// stretch of A's candidate runs.  A run is a maximal range of consecutive
+// non-empty cells adjacent to A; since points are stored grouped by cell in
+// cell order, a run is one contiguous range of point positions [c0, c1).
+// The unit covers runs run_first..run_last, starting at c_begin inside the
+// first and ending at c_end inside the last.
+// ---------------------------------------------------------------------------
+struct WorkUnit {
+  uint32_t q0, q1;          // query slots [q0, q1): positions, or indices into a query list
+  uint32_t run_first, run_last;
+  uint32_t c_begin, c_end;  // candidate position bounds inside the first / last run
+  uint32_t cell;            // query cell A
+  uint32_t pad;
+};
+static_assert(sizeof(WorkUnit) == 32, "WorkUnit layout");
+
+// ---------------------------------------------------------------------------
+// Primitives (sj_prims.hip)
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum of n values in place-or-out; returns the total through
+// *d_total (device) when non-null.  `tmp` is scratch from scan_tmp_bytes().
+size_t scan_tmp_bytes(uint64_t n);
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n,
+                        uint32_t *d_total, void *tmp, hipStream_t s);
+void exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t n,
+                        uint64_t *d_total, void *tmp, hipStream_t s);
+
+// Stable LSD radix sort of 64-bit keys (optionally with 32-bit values) over
+// the bit ranges listed in `shifts` (8-bit digits at each shift).  Sorted
+// output ends in keys[0]/vals[0]; keys[1]/vals[1] are the ping-pong buffers.
+size_t radix_tmp_bytes(uint64_t n);
+void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n,
+                    const int *shifts, int n_passes, void *tmp, hipStream_t s);
+
+// out[i] = i * stride; widen u32 -> u64; narrow u64 -> u32 (low half).
+void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, hipStream_t s);
+void launch_widen(const uint32_t *in, uint64_t *out, uint64_t count, hipStream_t s);
+void launch_narrow(const uint64_t *in, uint32_t *out, uint64_t count, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Index build (sj_index.hip)
+// ---------------------------------------------------------------------------
+struct DeviceIndex;  // defined in sj_index.hip
+
+// ---------------------------------------------------------------------------
+// Distance kernels (sj_join.hip)
+// ---------------------------------------------------------------------------
+struct JoinLaunch {
+  const float *X;           // [n][dp] points in cell order, reordered dims, zero padded
+  const uint32_t *orig_id;  // [n] position -> caller index
+  const uint16_t *inv_perm; // [d] caller dim t -> reordered position
+  const WorkUnit *wu;
+  uint64_t n_wu;
+  const uint2 *runs;
+  const uint32_t *qlist;    // query positions (indirect mode) or null
+  uint32_t d, dp;
+  float lo, hi;             // FP32 accept / reject thresholds (band between them)
+  double eps2;              // canonical threshold
+  int symmetric;            // 1: emit both orders, only qpos <= cpos
+  int count_only;           // 1: count pairs with s <= hi, emit nothing
+  int shortc;
+  uint64_t *out;            // pair keys (i << 32 | j)
+  uint64_t capacity;
+  unsigned long long *cursor;    // pairs produced (may exceed capacity)
+  unsigned long long *rechecks;  // FP64 rechecks performed
+  int rq;                   // queries per lane (1, 2 or 4); units hold 64*rq queries
+};
+
+// Queries per lane the FP32 kernel uses for padded dimension dp.
+int fp32_rq_for(uint32_t dp);
+// Padded dimension count the kernels support for d (0 if unsupported).
+uint32_t padded_dim(uint32_t d);
+void launch_join_fp32(const JoinLaunch &a, hipStream_t s);
+
+// Unpack sorted keys [first, first+count) to (i, j) columns and optionally
+// recompute FP32 distances.
+void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i,
+                   uint32_t *out_j, float *out_dist, const float *X,
+                   const uint32_t *pos_of, const uint16_t *inv_perm,
+                   uint32_t d, uint32_t dp, hipStream_t s);
+
+}  // namespace sj

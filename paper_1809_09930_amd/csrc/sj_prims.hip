@@ -1,0 +1,319 @@
+// Device-wide primitives: exclusive prefix sum and stable LSD radix sort.
+// Both are plain gfx950 kernels (wave64, 256-thread workgroups, LDS staging).
+#include "sj_internal.hpp"
+
+#include <vector>
+
+namespace sj {
+
+namespace {
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;  // 2048 values per workgroup
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    T u = __shfl_up(v, off);
+    if (l >= (uint32_t)off) v += u;
+  }
+  return v;
+}
+
+// Exclusive scan of one value per thread over the workgroup; *total gets
+// the workgroup sum.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *total) {
+  __shared__ T wsum[kWavesPerBlock];
+  const int w = threadIdx.x / kWave;
+  T inc = wave_inclusive_scan(v);
+  if (lane_id() == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < kWavesPerBlock; ++i) {
+    if (i < w) before += wsum[i];
+    all += wsum[i];
+  }
+  __syncthreads();
+  *total = all;
+  return before + inc - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T *__restrict__ in,
+                                                        uint64_t n,
+                                                        T *__restrict__ sums) {
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  T acc = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+    if (idx < n) acc += in[idx];
+  }
+  T total;
+  (void)block_exclusive_scan(acc, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of a 2048-value tile per workgroup, plus the workgroup's
+// offset (offsets[blockIdx.x], or 0).  The last workgroup writes the grand
+// total when `total` is non-null.  in == out is allowed.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_tile(const T *in, T *out, uint64_t n,
+                                                      const T *__restrict__ offsets,
+                                                      T *__restrict__ total) {
+  __shared__ T tile[kScanTile];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+    tile[i * kBlock + threadIdx.x] = idx < n ? in[idx] : T(0);
+  }
+  __syncthreads();
+  T v[kScanItems];
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    T t = tile[threadIdx.x * kScanItems + i];
+    v[i] = s;
+    s += t;
+  }
+  T btotal;
+  T excl = block_exclusive_scan(s, &btotal);
+  const T off = offsets ? offsets[blockIdx.x] : T(0);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) tile[threadIdx.x * kScanItems + i] = v[i] + excl + off;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+    if (idx < n) out[idx] = tile[i * kBlock + threadIdx.x];
+  }
+  if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + btotal;
+}
+
+template <typename T>
+size_t scan_levels_bytes(uint64_t n) {
+  size_t bytes = 0;
+  while (n > (uint64_t)kScanTile) {
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    bytes += ((nb * sizeof(T) + 255) / 256) * 256;
+    n = nb;
+  }
+  return bytes + 256;
+}
+
+template <typename T>
+void scan_impl(const T *in, T *out, uint64_t n, T *d_total, char *tmp, hipStream_t s) {
+  if (n == 0) {
+    if (d_total) SJ_HIP(hipMemsetAsync(d_total, 0, sizeof(T), s));
+    return;
+  }
+  if (n <= (uint64_t)kScanTile) {
+    hipLaunchKernelGGL(k_scan_tile<T>, dim3(1), dim3(kBlock), 0, s, in, out, n,
+                       (const T *)nullptr, d_total);
+    SJ_HIP(hipGetLastError());
+    return;
+  }
+  const uint64_t nb = (n + kScanTile - 1) / kScanTile;
+  T *sums = reinterpret_cast<T *>(tmp);
+  char *rest = tmp + ((nb * sizeof(T) + 255) / 256) * 256;
+  hipLaunchKernelGGL(k_scan_reduce<T>, dim3((uint32_t)nb), dim3(kBlock), 0, s, in, n, sums);
+  SJ_HIP(hipGetLastError());
+  scan_impl<T>(sums, sums, nb, (T *)nullptr, rest, s);
+  hipLaunchKernelGGL(k_scan_tile<T>, dim3((uint32_t)nb), dim3(kBlock), 0, s, in, out, n,
+                     (const T *)sums, d_total);
+  SJ_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort: 8-bit digits, 4096 keys per workgroup (4 waves x 16 rounds of
+// 64 consecutive keys).  Ranks inside a workgroup are found with the wave
+// "multisplit": eight ballots give each lane the mask of lanes holding the
+// same digit, so equal digits keep their input order (stable).
+// ---------------------------------------------------------------------------
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRsRounds = 16;
+constexpr int kRsTile = kBlock * kRsRounds;  // 4096
+
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys,
+                                                    uint64_t n, int shift,
+                                                    uint32_t *__restrict__ hist,
+                                                    uint32_t nblocks) {
+  __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
+  const int w = threadIdx.x / kWave;
+  for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock)
+    (&cnt[0][0])[i] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+  for (int r = 0; r < kRsRounds; ++r) {
+    uint64_t idx = base + (uint64_t)r * kBlock + threadIdx.x;
+    if (idx < n) {
+      uint32_t dg = (uint32_t)(keys[idx] >> shift) & (kRadixBins - 1);
+      atomicAdd(&cnt[w][dg], 1u);
+    }
+  }
+  __syncthreads();
+  for (int dg = threadIdx.x; dg < kRadixBins; dg += kBlock) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) t += cnt[i][dg];
+    hist[(uint64_t)dg * nblocks + blockIdx.x] = t;
+  }
+}
+
+template <bool kVals>
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n, int shift,
+    const uint32_t *__restrict__ offs, uint32_t nblocks) {
+  __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
+  const int w = threadIdx.x / kWave;
+  const uint32_t l = lane_id();
+  for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock)
+    (&cnt[0][0])[i] = 0;
+  __syncthreads();
+
+  const uint64_t base = (uint64_t)blockIdx.x * kRsTile + (uint64_t)w * (kRsTile / kWavesPerBlock);
+  uint64_t key[kRsRounds];
+  uint32_t val[kRsRounds];
+  uint32_t rank[kRsRounds];
+#pragma unroll
+  for (int r = 0; r < kRsRounds; ++r) {
+    const uint64_t idx = base + (uint64_t)r * kWave + l;
+    const bool valid = idx < n;
+    key[r] = valid ? kin[idx] : 0ull;
+    if (kVals) val[r] = valid ? vin[idx] : 0u;
+    const uint32_t dg = (uint32_t)(key[r] >> shift) & (kRadixBins - 1);
+    uint64_t peers = ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t m = ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t below = lanes_below(peers);
+    uint32_t before = 0;
+    if (valid) before = cnt[w][dg];
+    rank[r] = before + below;
+    // all lanes of the wave have read the counter before its leader
+    // (lowest lane of the digit group) updates it
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) cnt[w][dg] = before + (uint32_t)__builtin_popcountll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // digit-major: workgroup-local offset of each wave's share of each digit
+  __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];
+  for (int dg = threadIdx.x; dg < kRadixBins; dg += kBlock) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+      woff[i][dg] = s;
+      s += cnt[i][dg];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsRounds; ++r) {
+    const uint64_t idx = base + (uint64_t)r * kWave + l;
+    if (idx < n) {
+      const uint32_t dg = (uint32_t)(key[r] >> shift) & (kRadixBins - 1);
+      const uint64_t pos = (uint64_t)offs[(uint64_t)dg * nblocks + blockIdx.x] + woff[w][dg] + rank[r];
+      kout[pos] = key[r];
+      if (kVals) vout[pos] = val[r];
+    }
+  }
+}
+
+__global__ void k_iota_strided(uint32_t *out, uint64_t count, uint64_t stride) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) out[i] = (uint32_t)(i * stride);
+}
+__global__ void k_widen(const uint32_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t count) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) out[i] = in[i];
+}
+__global__ void k_narrow(const uint64_t *__restrict__ in, uint32_t *__restrict__ out, uint64_t count) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) out[i] = (uint32_t)in[i];
+}
+
+}  // namespace
+
+void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_iota_strided, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, out, count, stride);
+  SJ_HIP(hipGetLastError());
+}
+void launch_widen(const uint32_t *in, uint64_t *out, uint64_t count, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_widen, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     in, out, count);
+  SJ_HIP(hipGetLastError());
+}
+void launch_narrow(const uint64_t *in, uint32_t *out, uint64_t count, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_narrow, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     in, out, count);
+  SJ_HIP(hipGetLastError());
+}
+
+size_t scan_tmp_bytes(uint64_t n) { return scan_levels_bytes<uint64_t>(n); }
+
+void exclusive_scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *d_total,
+                        void *tmp, hipStream_t s) {
+  scan_impl<uint32_t>(in, out, n, d_total, static_cast<char *>(tmp), s);
+}
+
+void exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *d_total,
+                        void *tmp, hipStream_t s) {
+  scan_impl<uint64_t>(in, out, n, d_total, static_cast<char *>(tmp), s);
+}
+
+size_t radix_tmp_bytes(uint64_t n) {
+  const uint64_t nb = (n + kRsTile - 1) / kRsTile;
+  const uint64_t hist = (uint64_t)kRadixBins * (nb ? nb : 1);
+  return ((hist * 4 + 255) / 256) * 256 + scan_levels_bytes<uint32_t>(hist);
+}
+
+void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int *shifts,
+                    int n_passes, void *tmp, hipStream_t s) {
+  if (n <= 1 || n_passes == 0) return;
+  if (n > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "radix sort of more than 2^32-1 keys");
+  const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
+  const uint64_t nhist = (uint64_t)kRadixBins * nb;
+  uint32_t *hist = static_cast<uint32_t *>(tmp);
+  char *scan_tmp = static_cast<char *>(tmp) + ((nhist * 4 + 255) / 256) * 256;
+  int cur = 0;
+  for (int p = 0; p < n_passes; ++p) {
+    const int sh = shifts[p];
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kBlock), 0, s, keys[cur], n, sh, hist, nb);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan_u32(hist, hist, nhist, nullptr, scan_tmp, s);
+    if (vals) {
+      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, sh, hist, nb);
+    } else {
+      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
+                         (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n,
+                         sh, hist, nb);
+    }
+    SJ_HIP(hipGetLastError());
+    cur ^= 1;
+  }
+  if (cur == 1) {
+    // odd number of passes: move the result into buffer 0
+    SJ_HIP(hipMemcpyAsync(keys[0], keys[1], n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    if (vals)
+      SJ_HIP(hipMemcpyAsync(vals[0], vals[1], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+}  // namespace sj

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP self-join against the CPU oracle, through the C ABI.
+
+Pair lists must match the oracle bit-exactly (same pairs, same sorted
+order); distances are checked at 1e-5 relative against the oracle's FP64
+distances.  Sizes span several work units, ragged tails and the edge cases
+(empty input, one point, duplicates, d = 1 .. 128)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from conftest import load_matrix, load_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def gpu_join(P, eps, with_dist=True, host_input=False, **opts):
+    from paper_1809_09930_amd import selfjoin as sj
+    t = torch.from_numpy(np.ascontiguousarray(P, dtype=np.float32))
+    if not host_input:
+        t = t.cuda()
+    h = sj.selfjoin_build_index(t, eps, **opts)
+    try:
+        total = sj.selfjoin_run(h)
+        oi = torch.empty(total, dtype=torch.int32, device="cuda")
+        oj = torch.empty(total, dtype=torch.int32, device="cuda")
+        od = torch.empty(total, dtype=torch.float32, device="cuda") if with_dist else None
+        if total:
+            assert sj.selfjoin_fetch_pairs(h, 0, oi, oj, od, max_pairs=total) == total
+        info = sj.selfjoin_get_info(h)
+        torch.cuda.synchronize()
+        res = (oi.cpu().numpy().view(np.uint32), oj.cpu().numpy().view(np.uint32),
+               od.cpu().numpy() if with_dist else None, info)
+    finally:
+        sj.selfjoin_free(h)
+    return res
+
+
+def assert_same_as_oracle(P, eps, **opts):
+    gi, gj, gd, info = gpu_join(P, eps, **opts)
+    oi, oj, os_ = oracle.bruteforce(P, eps, with_dist=True)
+    assert len(gi) == len(oi), (len(gi), len(oi))
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+    ref = np.sqrt(os_)
+    np.testing.assert_allclose(gd, ref, rtol=1e-5, atol=1e-30)
+    assert info["pairs"] == len(oi)
+    return info
+
+
+def calibrated(P, target, stride=3):
+    eps, _ = oracle.calibrate_eps(P, target, np.arange(0, len(P), stride))
+    return eps
+
+
+# --------------------------------------------------------------------------
+def test_fig1_worked_example():
+    P = load_matrix("fig1_points.txt", np.float32)
+    want = {(p, p) for p in range(len(P))}
+    for a, b, _ in load_rows("fig1_pairs.txt"):
+        want |= {(int(a), int(b)), (int(b), int(a))}
+    gi, gj, gd, info = gpu_join(P, 1.0)
+    assert set(zip(gi.tolist(), gj.tolist())) == want
+    assert_same_as_oracle(P, 1.0)
+
+
+@pytest.mark.parametrize("n,d,seed,target", [
+    (3000, 16, 1, 32), (2500, 8, 2, 20), (1999, 18, 3, 40), (1500, 64, 4, 16),
+    (777, 90, 5, 12), (640, 128, 6, 10), (1000, 1, 7, 5), (1234, 3, 8, 25),
+    (4097, 16, 9, 3)])
+def test_uniform_matches_oracle(n, d, seed, target):
+    P = datagen.uniform_grid(n, d, seed)
+    assert_same_as_oracle(P, calibrated(P, target))
+
+
+@pytest.mark.parametrize("n,d,seed", [(5000, 18, 11), (3000, 12, 12), (2000, 32, 13)])
+def test_clustered_many_cells_matches_oracle(n, d, seed):
+    std = datagen.decaying_std(d, 0.2, 0.002, seed)
+    P = datagen.gaussian_mixture(n, d, 20, std, seed)
+    eps = calibrated(P, 30)
+    info = assert_same_as_oracle(P, eps)
+    assert info["n_cells"] > 1
+    assert info["candidates"] < n * n
+
+
+def test_empty_single_and_duplicates():
+    gi, gj, gd, info = gpu_join(np.zeros((0, 5), np.float32), 0.5)
+    assert len(gi) == 0 and info["pairs"] == 0
+    gi, gj, gd, _ = gpu_join(np.array([[0.5, 0.25, 0.125]], np.float32), 1e-3)
+    assert gi.tolist() == [0] and gj.tolist() == [0] and gd.tolist() == [0.0]
+    P = np.repeat(datagen.uniform_grid(40, 6, 21), 3, axis=0)
+    assert_same_as_oracle(P, 0.05)
+    # all points identical: one cell, every pair at distance 0
+    assert_same_as_oracle(np.full((300, 4), 0.375, np.float32), 1e-6)
+
+
+def test_ties_exactly_at_epsilon():
+    u = 2.0 ** -24
+    base = datagen.uniform_grid(500, 4, 31)
+    extra = np.array([[0, 0, 0, 0], [3000 * u, 4000 * u, 0, 0],
+                      [3000 * u, 3999 * u, 89 * u, 0], [3000 * u, 4000 * u, u, 0]],
+                     dtype=np.float32)
+    P = np.concatenate([extra, base])
+    eps = 5000 * u  # eps^2 equals the squared distance of points 0 and 1
+    gi, gj, _, _ = gpu_join(P, eps)
+    s = set(zip(gi.tolist(), gj.tolist()))
+    assert (0, 1) in s and (1, 0) in s and (0, 2) in s and (0, 3) not in s
+    assert_same_as_oracle(P, eps)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(k=1), dict(k=2), dict(k=6), dict(k=8), dict(reorder=False), dict(shortc=False),
+    dict(k=3, reorder=False, shortc=False)])
+def test_filters_do_not_change_the_result(opts):
+    std = datagen.uniform_std(10, 0.01, 0.3, 41)
+    P = datagen.gaussian_mixture(3000, 10, 8, std, 41)
+    assert_same_as_oracle(P, calibrated(P, 25), **opts)
+
+
+@pytest.mark.parametrize("opts", [dict(batch_pairs=5000), dict(min_batches=3),
+                                  dict(batch_pairs=777, min_batches=5)])
+def test_batched_results_equal_single_batch(opts):
+    P = datagen.uniform_grid(2500, 16, 51)
+    eps = calibrated(P, 30)
+    info = assert_same_as_oracle(P, eps, **opts)
+    assert info["batches"] >= 3 and info["result_on_host"] == 1
+
+
+def test_host_input_and_host_outputs():
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.uniform_grid(1500, 8, 61)
+    eps = calibrated(P, 20)
+    oi, oj, os_ = oracle.bruteforce(P, eps, with_dist=True)
+    h = sj.selfjoin_build_index(torch.from_numpy(P), eps)
+    try:
+        total = sj.selfjoin_run(h)
+        assert total == len(oi)
+        ci = torch.empty(total, dtype=torch.int32)
+        cj = torch.empty(total, dtype=torch.int32)
+        cd = torch.empty(total, dtype=torch.float32)
+        assert sj.selfjoin_fetch_pairs(h, 0, ci, cj, cd, max_pairs=total) == total
+        assert np.array_equal(ci.numpy().view(np.uint32), oi)
+        assert np.array_equal(cj.numpy().view(np.uint32), oj)
+        np.testing.assert_allclose(cd.numpy(), np.sqrt(os_), rtol=1e-5)
+        # partial fetch from an offset, and the end of the result
+        part = torch.empty(100, dtype=torch.int32)
+        assert sj.selfjoin_fetch_pairs(h, total - 40, None, part, None, max_pairs=100) == 40
+        assert np.array_equal(part.numpy()[:40].view(np.uint32), oj[-40:])
+        assert sj.selfjoin_fetch_pairs(h, total, None, part, None, max_pairs=100) == 0
+        with pytest.raises(sj.SelfJoinError) as e:
+            sj.selfjoin_fetch_pairs(h, total + 1, None, part, None, max_pairs=1)
+        assert e.value.code == sj.SJ_ERR_RANGE
+    finally:
+        sj.selfjoin_free(h)
+
+
+def test_state_and_input_errors():
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.uniform_grid(100, 4, 71)
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), 0.1)
+    try:
+        out = torch.empty(4, dtype=torch.int32, device="cuda")
+        with pytest.raises(sj.SelfJoinError) as e:
+            sj.selfjoin_fetch_pairs(h, 0, out, None, None, max_pairs=4)
+        assert e.value.code == sj.SJ_ERR_STATE
+    finally:
+        sj.selfjoin_free(h)
+    bad = torch.from_numpy(P).cuda()
+    bad[17, 2] = float("nan")
+    with pytest.raises(sj.SelfJoinError) as e:
+        sj.selfjoin_build_index(bad, 0.1)
+    assert e.value.code == sj.SJ_ERR_INVALID_ARG
+    bad[17, 2] = float("inf")
+    with pytest.raises(sj.SelfJoinError) as e:
+        sj.selfjoin_build_index(bad, 0.1)
+    assert e.value.code == sj.SJ_ERR_INVALID_ARG
+
+
+def test_reorder_permutation_matches_oracle():
+    from paper_1809_09930_amd import selfjoin as sj
+    std = np.array([0.01, 0.3, 0.05, 0.2, 0.002, 0.1])
+    P = datagen.gaussian_mixture(20000, 6, 5, std, 81)
+    perm_ref, var = oracle.reorder_perm(P)
+    # the sample variances here are far apart, so the order is unambiguous
+    assert np.min(np.diff(np.sort(var))) > 1e-4
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), 0.05)
+    try:
+        assert sj.selfjoin_get_perm(h, 6) == perm_ref.tolist()
+    finally:
+        sj.selfjoin_free(h)
+
+
+def test_uniform_20k_d16_full_result():
+    """The 20,000 x 16 uniform workload at its calibrated epsilon (mean
+    neighbours ~ 32): the whole pair list against the oracle."""
+    P = datagen.make_workload("uniform_20k_d16")
+    rows = datagen.calibration_rows(len(P), datagen.WORKLOADS["uniform_20k_d16"]["seed"])
+    eps, _ = oracle.calibrate_eps(P, 32, rows)
+    info = assert_same_as_oracle(P, eps)
+    assert info["candidates"] == len(P) ** 2  # uniform data: every cell is adjacent
+
+
+def test_uniform_2m_d16_sampled_rows_and_symmetry():
+    """The 2,000,000 x 16 workload in the benchmark's configuration (auto k,
+    one symmetric batch): sampled full rows against the oracle, plus the
+    symmetry and self-pair invariants over the whole result."""
+    import json
+    import os
+    from conftest import GOLDEN
+    with open(os.path.join(GOLDEN, "eps.json")) as f:
+        table = json.load(f)
+    eps = float.fromhex(table["uniform_2m_d16"]["eps"]["64"]["hex"])
+    P = datagen.make_workload("uniform_2m_d16")
+    from paper_1809_09930_amd import selfjoin as sj
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps)
+    try:
+        total = sj.selfjoin_run(h)
+        oi = torch.empty(total, dtype=torch.int32, device="cuda")
+        oj = torch.empty(total, dtype=torch.int32, device="cuda")
+        sj.selfjoin_fetch_pairs(h, 0, oi, oj, None, max_pairs=total)
+        info = sj.selfjoin_get_info(h)
+    finally:
+        sj.selfjoin_free(h)
+    n = len(P)
+    key = (oi.to(torch.int64) << 32) | oj.to(torch.int64)
+    assert bool((key[1:] > key[:-1]).all())  # strictly sorted, unique
+    rkey = (oj.to(torch.int64) << 32) | oi.to(torch.int64)
+    assert bool(torch.equal(torch.sort(rkey).values, key))  # symmetric
+    self_pairs = (oi == oj)
+    assert int(self_pairs.sum()) == n
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(n, size=48, replace=False))
+    cnt, js = oracle.rows(P, eps, rows)
+    starts = torch.searchsorted(oi, torch.from_numpy(rows.astype(np.int32)).cuda())
+    off = 0
+    for r, c, st in zip(rows, cnt, starts.tolist()):
+        got = oj[st:st + int(c)].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, js[off:off + c]), r
+        if st + int(c) < total:
+            assert int(oi[st + int(c)]) != r
+        off += int(c)
+    assert info["candidates"] == n * n
+    sd = (total - n) / n
+    assert 40 < sd < 90
