@@ -30,6 +30,15 @@ JOIN_SRC = os.path.join(ROOT, "paper_1809_09930_amd", "csrc", "sj_join.hip")
 # instructions/s; an FMA counts 2 flops -> 78.6 TFLOP/s without packed FP32
 # (packed FP32 math is disabled in this build).
 PEAK_FP32_VALU_TFLOPS = 78.6
+# Dense FP16/BF16 matrix-core peak of MI355X.
+PEAK_MFMA_16BIT_TFLOPS = 2500.0
+
+
+def mfma_k(d, precision):
+    """K (padded reduction length) of the matrix-core tiles: d coordinates
+    plus 2 (FP16) or 3 (BF16) norm pieces, rounded up to 16."""
+    pieces = 2 if precision == 1 else 3
+    return (d + pieces + 15) // 16 * 16
 
 
 def parse():
@@ -42,6 +51,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0,
                     help="query rows for the CPU oracle sample (0: sized to ~15 s)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="distance filter of the headline line")
+    ap.add_argument("--compare", default="fp16",
+                    help="comma list of other precisions timed on the same workload ('' = none)")
     return ap.parse_args()
 
 
@@ -122,9 +135,9 @@ def main():
     Pd = torch.from_numpy(P).cuda()
     torch.cuda.synchronize()
 
-    def step(record):
+    def step(record, precision):
         for t, eps in zip(targets, eps_list):
-            h = sj.selfjoin_build_index(Pd, eps)
+            h = sj.selfjoin_build_index(Pd, eps, precision=precision)
             total = sj.selfjoin_run(h)
             info = sj.selfjoin_get_info(h)
             perm = sj.selfjoin_get_perm(h, d)
@@ -132,42 +145,49 @@ def main():
             if record is not None:
                 record.append((t, eps, total, info, perm))
 
-    for _ in range(a.warmup):
-        step(None)
-    torch.cuda.synchronize()
-    recs = []
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        step(recs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1e3 / a.steps
+    def timed(precision):
+        for _ in range(a.warmup):
+            step(None, precision)
+        torch.cuda.synchronize()
+        recs = []
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            step(recs, precision)
+        torch.cuda.synchronize()
+        return recs, time.perf_counter() - t0
 
+    def per_eps_table(recs, with_prefix):
+        per_eps, flops_total, time_total = {}, 0.0, 0.0
+        for t, eps, total, info, perm in recs[:len(targets)]:
+            ms = info["ms_join"] / max(info["join_launches"], 1)
+            row = {"eps": eps, "pairs": total, "sd": (total - n) / n, "k": info["k"],
+                   "cells": info["n_cells"], "candidates": info["candidates"],
+                   "evaluated": info["evaluated"], "rechecks": info["rechecks"],
+                   "ms_build": round(info["ms_build"], 3), "ms_join": round(ms, 3),
+                   "ms_sort": round(info["ms_sort"], 3), "ms_run": round(info["ms_run"], 3)}
+            if with_prefix:
+                pbar = shortc_prefix_mean(P, perm, eps * eps)
+                row["shortc_prefix_mean"] = round(pbar, 3)
+                flops_total += 3.0 * pbar * (info["candidates"] + n) / 2.0
+            else:
+                # algorithmic: one d-long dot product per unordered pair
+                flops_total += 2.0 * d * (info["candidates"] + n) / 2.0
+            time_total += ms / 1e3
+            per_eps[t] = row
+        return per_eps, flops_total, time_total
+
+    recs, elapsed = timed(a.precision)
+    ms_per_step = elapsed * 1e3 / a.steps
     cand = sum(r[3]["candidates"] for r in recs)
     pairs = sum(r[2] for r in recs)
     value = cand / elapsed
-
-    # dominant kernel: the FP32 distance kernel (one main launch per epsilon)
     join_ms = [r[3]["ms_join"] / max(r[3]["join_launches"], 1) for r in recs]
-    per_eps = {}
-    flops_total, time_total = 0.0, 0.0
-    for t, eps, total, info, perm in recs[:len(targets)]:
-        pbar = shortc_prefix_mean(P, perm, eps * eps)
-        unordered = (info["candidates"] + n) / 2.0
-        flops = 3.0 * pbar * unordered
-        ms = info["ms_join"] / max(info["join_launches"], 1)
-        flops_total += flops
-        time_total += ms / 1e3
-        per_eps[t] = {"eps": eps, "pairs": total, "sd": (total - n) / n, "k": info["k"],
-                      "cells": info["n_cells"], "candidates": info["candidates"],
-                      "evaluated": info["evaluated"], "rechecks": info["rechecks"],
-                      "shortc_prefix_mean": round(pbar, 3),
-                      "ms_build": round(info["ms_build"], 3), "ms_join": round(ms, 3),
-                      "ms_sort": round(info["ms_sort"], 3), "ms_run": round(info["ms_run"], 3)}
+    fp32 = a.precision == "fp32"
+    per_eps, flops_total, time_total = per_eps_table(recs, fp32)
     achieved = flops_total / time_total / 1e12 if time_total > 0 else 0.0
-    traffic = traffic_for_join()
+    peak = PEAK_FP32_VALU_TFLOPS if fp32 else PEAK_MFMA_16BIT_TFLOPS
     out = {
-        "metric": "candidate distance evals/s (exact pair set, plain FP32 grid join)",
+        "metric": "candidate distance evals/s (exact pair set)",
         "value": value,
         "unit": "candidate distance evals/s",
         "n_gpus": 1,
@@ -177,18 +197,36 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if fp32 else a.precision,
         "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "d": d, "distribution": w["kind"],
                    "target_mean_neighbours": [int(t) for t in targets],
-                   "path": "plain FP32 grid join, k auto in 4..8, symmetric tiles"},
+                   "path": ("plain FP32 grid join" if fp32 else
+                            "%s matrix-core join with FP64 band recheck" % a.precision)
+                   + ", k auto in 4..8, symmetric tiles"},
         "result_pairs_per_s": pairs / elapsed,
         "per_epsilon": per_eps,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": traffic,
-                     "kernel": "k_join_fp32", "mean_launch_ms": float(np.mean(join_ms))},
+        "roofline": {"bound": "alu" if fp32 else "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic_for_join(),
+                     "kernel": "k_join_fp32" if fp32 else "k_join_mfma",
+                     "mean_launch_ms": float(np.mean(join_ms))},
     }
+    compare = {}
+    for prec in [x.strip() for x in a.compare.split(",") if x.strip() and x.strip() != a.precision]:
+        crecs, celapsed = timed(prec)
+        ccand = sum(r[3]["candidates"] for r in crecs)
+        cper, cfl, ctime = per_eps_table(crecs, prec == "fp32")
+        cach = cfl / ctime / 1e12 if ctime > 0 else 0.0
+        cpeak = PEAK_FP32_VALU_TFLOPS if prec == "fp32" else PEAK_MFMA_16BIT_TFLOPS
+        compare[prec] = {"value": ccand / celapsed, "ms_per_step": celapsed * 1e3 / a.steps,
+                         "speedup_vs_headline": (ccand / celapsed) / value,
+                         "result_pairs_per_s": sum(r[2] for r in crecs) / celapsed,
+                         "per_epsilon": cper,
+                         "kernel_achieved_tflops": cach, "kernel_peak_tflops": cpeak,
+                         "kernel_frac": cach / cpeak}
+    if compare:
+        out["compare"] = compare
     if not a.no_cpu_baseline:
         mid = eps_list[len(eps_list) // 2]
         out["cpu_baseline"] = cpu_baseline(P, mid, a.cpu_rows)

@@ -65,7 +65,11 @@ extern "C" {
 
 /* Distance filter used by selfjoin_run. */
 enum sj_precision {
-    SJ_PREC_FP32 = 0 /* difference form (a-b)^2 summed in FP32 on the vector ALUs, with short-circuit */
+    SJ_PREC_FP32 = 0, /* difference form (a-b)^2 summed in FP32 on the vector ALUs, with short-circuit */
+    SJ_PREC_FP16 = 1, /* |a|^2+|b|^2-2a.b on the matrix cores, FP16 operands, FP32 accumulation,
+                         FP64 recheck of the error band; falls back to BF16 when the centred data
+                         exceed the FP16 range */
+    SJ_PREC_BF16 = 2  /* as SJ_PREC_FP16 with BF16 operands */
 };
 
 typedef struct sj_index sj_index; /* opaque; owns every device buffer it uses */

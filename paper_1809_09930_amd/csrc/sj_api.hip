@@ -15,6 +15,7 @@
 
 #include "sj_index.hpp"
 #include "sj_internal.hpp"
+#include "sj_mfma.hpp"
 
 namespace sj {
 
@@ -171,6 +172,16 @@ struct sj_index {
   uint64_t candidates = 0, evaluated_sym = 0;
   DevBuf counters;  // [0] cursor, [1] rechecks
 
+  // matrix-core path
+  uint32_t prec = SJ_PREC_FP32;  // precision actually used
+  int fmt = 0;
+  uint32_t kp = 0;
+  uint64_t n_pad = 0;
+  DevBuf XA, XB, thi, tlo;
+  DevBuf wu_m;
+  uint64_t n_wu_m = 0, evaluated_sym_m = 0;
+  uint32_t tq_m = 128, tc_m = 4096;
+
   // results
   bool ran = false;
   uint64_t total = 0;
@@ -316,29 +327,42 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
                          const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
                          DevBuf &out, uint64_t *eval, hipStream_t s) {
   const uint64_t nc = ix.ncell;
-  DevBuf cnt, ev, scan;
-  cnt.alloc((nc + 1) * 4);
-  ev.alloc((nc + 1) * 8);
-  scan.alloc(scan_tmp_bytes(nc + 1) + 64);
-  SJ_HIP(hipMemsetAsync(cnt.p, 0, (nc + 1) * 4, s));
-  SJ_HIP(hipMemsetAsync(ev.p, 0, (nc + 1) * 8, s));
-  launch_workunits(0, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
-                   run_off.as<uint32_t>(), runs.as<uint2>(), cnt.as<uint32_t>(),
-                   ev.as<uint64_t>(), nullptr, nullptr, s);
-  DevBuf tot;
+  DevBuf qb_off, run_total, scan, tot;
+  qb_off.alloc((nc + 1) * 4);
+  run_total.alloc(nc * 8);
   tot.alloc(64);
-  exclusive_scan_u32(cnt.as<uint32_t>(), cnt.as<uint32_t>(), nc + 1, tot.as<uint32_t>(), scan.p, s);
-  exclusive_scan_u64(ev.as<uint64_t>(), ev.as<uint64_t>(), nc + 1, tot.as<uint64_t>() + 1, scan.p,
-                     s);
+  SJ_HIP(hipMemsetAsync(qb_off.p, 0, (nc + 1) * 4, s));
+  launch_wu_cells(nc, tq, ix.cell_start.as<uint32_t>(), qlist, nq, run_off.as<uint32_t>(),
+                  runs.as<uint2>(), qb_off.as<uint32_t>(), run_total.as<uint64_t>(), s);
+  scan.alloc(scan_tmp_bytes(std::max<uint64_t>(nc + 1, 1)) + 64);
+  exclusive_scan_u32(qb_off.as<uint32_t>(), qb_off.as<uint32_t>(), nc + 1, tot.as<uint32_t>(),
+                     scan.p, s);
+  uint32_t h_nqb = 0;
+  SJ_HIP(hipMemcpyAsync(&h_nqb, tot.p, 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  const uint64_t nqb = h_nqb;
+  DevBuf units, ev;
+  units.alloc((nqb + 1) * 4);
+  ev.alloc((nqb + 1) * 8);
+  SJ_HIP(hipMemsetAsync(units.p, 0, (nqb + 1) * 4, s));
+  SJ_HIP(hipMemsetAsync(ev.p, 0, (nqb + 1) * 8, s));
+  launch_wu_count(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+                  qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
+                  run_total.as<uint64_t>(), units.as<uint32_t>(), ev.as<uint64_t>(), s);
+  scan.alloc(scan_tmp_bytes(nqb + 1) + 64);
+  exclusive_scan_u32(units.as<uint32_t>(), units.as<uint32_t>(), nqb + 1, tot.as<uint32_t>(),
+                     scan.p, s);
+  exclusive_scan_u64(ev.as<uint64_t>(), ev.as<uint64_t>(), nqb + 1, tot.as<uint64_t>() + 1,
+                     scan.p, s);
   uint64_t h[2] = {0, 0};
   SJ_HIP(hipMemcpyAsync(h, tot.p, 16, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
   const uint64_t n_wu = (uint32_t)h[0];
   *eval = h[1];
   out.alloc(n_wu * sizeof(WorkUnit));
-  launch_workunits(1, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
-                   run_off.as<uint32_t>(), runs.as<uint2>(), nullptr, nullptr,
-                   cnt.as<uint32_t>(), out.as<WorkUnit>(), s);
+  launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+                 qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
+                 run_total.as<uint64_t>(), units.as<uint32_t>(), out.as<WorkUnit>(), s);
   SJ_HIP(hipStreamSynchronize(s));
   return n_wu;
 }
@@ -375,8 +399,61 @@ void compute_thresholds(sj_index &ix) {
   ix.lo32 = l;
 }
 
+// Operands and thresholds of the matrix-core filter (see sj_mfma.hip).
+void mfma_prepare(sj_index &ix, hipStream_t s) {
+  const uint32_t d = ix.d;
+  // centre: per-dimension midrange (reordered order, like the rows of X)
+  std::vector<float> centre(d);
+  double max_abs = 0.0, n_bound = 0.0;
+  for (uint32_t r = 0; r < d; ++r) {
+    const uint32_t t = ix.perm[r];
+    centre[r] = (float)((ix.dmin[t] + ix.dmax[t]) * 0.5);
+    const double h = std::max(std::fabs(ix.dmax[t] - (double)centre[r]),
+                              std::fabs(ix.dmin[t] - (double)centre[r]));
+    max_abs = std::max(max_abs, h);
+    n_bound += h * h;
+  }
+  int fmt = ix.opt.precision == SJ_PREC_FP16 ? kFmtF16 : kFmtBF16;
+  if (fmt == kFmtF16 && (max_abs > 8192.0 || n_bound > 30000.0)) fmt = kFmtBF16;
+  if (fmt == kFmtBF16 && (max_abs > 1e15 || n_bound > 1e30))
+    fail(SJ_ERR_INVALID_ARG, "coordinates too large for the 16-bit matrix path; use SJ_PREC_FP32");
+  ix.fmt = fmt;
+  ix.prec = fmt == kFmtF16 ? SJ_PREC_FP16 : SJ_PREC_BF16;
+  ix.kp = mfma_kp(d, fmt);
+  ix.n_pad = (ix.n + 31) / 32 * 32 + 32;
+  const uint64_t np = ix.n_pad;
+  ix.XA.alloc(np * ix.kp * 2);
+  ix.XB.alloc(np * ix.kp * 2);
+  ix.thi.alloc(np * 4);
+  ix.tlo.alloc(np * 4);
+  DevBuf cdev, norm2, distc, fold, maxima;
+  cdev.alloc(d * 4);
+  norm2.alloc(np * 8);
+  distc.alloc(np * 8);
+  fold.alloc(np * 8);
+  maxima.alloc(64);
+  SJ_HIP(hipMemcpyAsync(cdev.p, centre.data(), d * 4, hipMemcpyHostToDevice, s));
+  launch_mfma_prep(fmt, ix.X.as<float>(), ix.n, np, d, ix.dp, ix.kp, cdev.as<float>(), ix.XA.p,
+                   ix.XB.p, norm2.as<double>(), distc.as<double>(), fold.as<double>(),
+                   maxima.as<unsigned long long>(), s);
+  MfmaBand band;
+  const double u16 = fmt == kFmtF16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
+  band.u = (1.0 + std::ldexp(1.0, -24)) * (1.0 + u16) - 1.0;
+  band.u *= 1.0 + std::ldexp(1.0, -40);
+  const double tiny = fmt == kFmtF16 ? std::ldexp(1.0, -14) : std::ldexp(1.0, -126);
+  band.eta_term = 2.0 * tiny * 1.0001 * std::sqrt((double)d);
+  band.gamma_acc = gamma_n((double)ix.kp + 1.0, std::ldexp(1.0, -23));
+  const double g64 = gamma_n((double)d + 2.0, std::ldexp(1.0, -53));
+  band.s_hi = ix.eps2 / (1.0 - g64);
+  band.s_lo = ix.eps2 / (1.0 + g64);
+  launch_mfma_thresholds(ix.n, np, band, norm2.as<double>(), distc.as<double>(),
+                         maxima.as<unsigned long long>(), ix.thi.as<float>(), ix.tlo.as<float>(), s);
+  SJ_HIP(hipStreamSynchronize(s));
+}
+
 void fill_defaults(sj_options *o) {
   std::memset(o, 0, sizeof(*o));
+  o->precision = SJ_PREC_FP32;
   o->struct_size = sizeof(sj_options);
   o->k = 0;
   o->k_min = 4;
@@ -510,6 +587,13 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   ix.tc = choose_tc(ev, ix.tq);
   ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc, ix.wu,
                             &ix.evaluated_sym, s);
+  if (ix.opt.precision != SJ_PREC_FP32) {
+    mfma_prepare(ix, s);
+    ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);
+    ix.tc_m = choose_tc(ev, ix.tq_m);
+    ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_m, ix.tc_m,
+                                ix.wu_m, &ix.evaluated_sym_m, s);
+  }
 
   SJ_HIP(hipEventRecord(ev1.e, s));
   SJ_HIP(hipEventSynchronize(ev1.e));
@@ -543,7 +627,33 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
   a.rq = fp32_rq_for(ix.dp);
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
-  launch_join_fp32(a, s);
+  if (ix.prec != SJ_PREC_FP32 && !count_only) {
+    MfmaLaunch m{};
+    m.fmt = ix.fmt;
+    m.kp = ix.kp;
+    m.XA = ix.XA.p;
+    m.XB = ix.XB.p;
+    m.thi = ix.thi.as<float>();
+    m.tlo = ix.tlo.as<float>();
+    m.X = a.X;
+    m.orig_id = a.orig_id;
+    m.inv_perm = a.inv_perm;
+    m.wu = a.wu;
+    m.n_wu = a.n_wu;
+    m.runs = a.runs;
+    m.qlist = a.qlist;
+    m.d = a.d;
+    m.dp = a.dp;
+    m.eps2 = a.eps2;
+    m.symmetric = sym;
+    m.out = out;
+    m.capacity = cap;
+    m.cursor = a.cursor;
+    m.rechecks = a.rechecks;
+    launch_join_mfma(m, s);
+  } else {
+    launch_join_fp32(a, s);
+  }
   SJ_HIP(hipEventRecord(e1.e, s));
   SJ_HIP(hipEventSynchronize(e1.e));
   *ms += elapsed_ms(e0, e1);
@@ -561,7 +671,7 @@ uint64_t read_counter(sj_index &ix, int which, hipStream_t s) {
 // filter cannot reject, so it is an upper-bound estimate.
 uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   const uint64_t n = ix.n;
-  const uint64_t target = 32768;
+  const uint64_t target = 8192;
   const uint64_t stride = n <= target ? 1 : n / target;
   const uint64_t nq = (n + stride - 1) / stride;
   DevBuf ql, wu;
@@ -604,8 +714,9 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
   for (int attempt = 0; attempt < 3; ++attempt) {
     ix.pairs.alloc(cap * 8);
     SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
-    join_launch(ix, ix.wu, ix.n_wu, ix.runs_sym, nullptr, 1, 0, ix.pairs.as<uint64_t>(), cap, s,
-                &ms_join);
+    const bool m = ix.prec != SJ_PREC_FP32;
+    join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, ix.runs_sym, nullptr, 1, 0,
+                ix.pairs.as<uint64_t>(), cap, s, &ms_join);
     ix.info.join_launches++;
     const uint64_t got = read_counter(ix, 0, s);
     if (got <= cap) {
@@ -625,7 +736,7 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
   SJ_HIP(hipEventSynchronize(e1.e));
   ix.info.ms_sort += elapsed_ms(e0, e1);
   ix.info.batches = 1;
-  ix.info.evaluated = ix.evaluated_sym;
+  ix.info.evaluated = ix.prec != SJ_PREC_FP32 ? ix.evaluated_sym_m : ix.evaluated_sym;
   ix.on_host = false;
 }
 
@@ -675,8 +786,10 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
       launch_narrow(kb[0], p32.as<uint32_t>(), nq, s);
       DevBuf wu;
       uint64_t ev = 0;
+      const bool mf = ix.prec != SJ_PREC_FP32;
       const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
-                                           ix.runs_full, ix.tq, ix.tc, wu, &ev, s);
+                                           ix.runs_full, mf ? ix.tq_m : ix.tq,
+                                           mf ? ix.tc_m : ix.tc, wu, &ev, s);
       evaluated += ev;
       Slot &sl = slots[slot & 1];
       if (sl.busy) {
@@ -865,7 +978,7 @@ int selfjoin_build_index(const float *points, uint64_t n, uint32_t d, double eps
       std::memcpy(&o, opts, opts->struct_size);
       o.struct_size = sizeof(o);
     }
-    if (o.precision != SJ_PREC_FP32) fail(SJ_ERR_INVALID_ARG, "unknown precision");
+    if (o.precision > SJ_PREC_BF16) fail(SJ_ERR_INVALID_ARG, "unknown precision");
     if (o.k < 0) fail(SJ_ERR_INVALID_ARG, "k must be >= 0");
     std::unique_ptr<sj_index> ix(new sj_index());
     SJ_HIP(hipGetDevice(&ix->device));
@@ -908,7 +1021,7 @@ int selfjoin_get_info(const sj_index *idx, sj_info *info) {
     x.n = idx->n;
     x.epsilon = idx->eps;
     x.k = idx->k;
-    x.precision = idx->opt.precision;
+    x.precision = idx->prec;
     x.n_cells = idx->ncell;
     x.candidates = idx->candidates;
     if (!idx->ran) x.evaluated = idx->evaluated_sym;

@@ -312,61 +312,106 @@ __device__ __forceinline__ void cell_query_slots(uint64_t A, const uint32_t *__r
   *qb = (uint32_t)lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_workunits(
-    int pass, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
-    const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qlist, uint64_t nq,
-    const uint32_t *__restrict__ run_off, const uint2 *__restrict__ runs,
-    uint32_t *__restrict__ wu_count, uint64_t *__restrict__ eval, const uint32_t *__restrict__ wu_off,
-    WorkUnit *__restrict__ wu) {
+// Per cell: its number of query blocks and the total length of its runs.
+__global__ __launch_bounds__(kBlock) void k_wu_cells(
+    uint64_t ncell, uint32_t tq, const uint32_t *__restrict__ cell_start,
+    const uint32_t *__restrict__ qlist, uint64_t nq, const uint32_t *__restrict__ run_off,
+    const uint2 *__restrict__ runs, uint32_t *__restrict__ nqb, uint64_t *__restrict__ run_total) {
   const uint64_t A = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (A >= ncell) return;
   uint32_t qa, qb;
   cell_query_slots(A, cell_start, qlist, nq, &qa, &qb);
-  const uint32_t r0 = run_off[A], r1 = run_off[A + 1];
+  nqb[A] = (qb - qa + tq - 1) / tq;
   uint64_t total = 0;
-  for (uint32_t r = r0; r < r1; ++r) total += runs[r].y - runs[r].x;
-  uint32_t units = 0;
-  uint64_t ev = 0;
-  uint32_t w = pass ? wu_off[A] : 0u;
-  for (uint32_t q0 = qa; q0 < qb; q0 += tq) {
-    const uint32_t q1 = min(q0 + tq, qb);
-    // symmetric: the first run starts at A; skip candidates before q0
-    const uint32_t skip = (sym && r1 > r0) ? (q0 - runs[r0].x) : 0u;
-    const uint64_t L = total - skip;
-    if (L == 0) continue;
-    const uint32_t nu = (uint32_t)((L + tc - 1) / tc);
-    units += nu;
-    ev += (uint64_t)(q1 - q0) * L;
-    if (pass) {
-      uint32_t r = r0;
-      uint32_t c = runs[r0].x + skip;
-      for (uint32_t u = 0; u < nu; ++u) {
-        WorkUnit x;
-        x.q0 = q0;
-        x.q1 = q1;
-        x.cell = (uint32_t)A;
-        x.pad = 0;
-        x.run_first = r;
-        x.c_begin = c;
-        uint32_t need = tc;
-        for (;;) {
-          const uint32_t avail = runs[r].y - c;
-          if (avail > need) { c += need; break; }
-          need -= avail;
-          if (r + 1 == r1 || need == 0) { c = runs[r].y; break; }
-          ++r;
-          c = runs[r].x;
-        }
-        x.run_last = r;
-        x.c_end = c;
-        wu[w++] = x;
-        if (c == runs[r].y && r + 1 < r1) { ++r; c = runs[r].x; }
-      }
-    }
+  for (uint32_t r = run_off[A]; r < run_off[A + 1]; ++r) total += runs[r].y - runs[r].x;
+  run_total[A] = total;
+}
+
+// Query block t: its cell (binary search over the scanned block counts),
+// slot range and candidate count.
+struct QBlock {
+  uint32_t A, q0, q1;
+  uint64_t L;   // candidates of the block
+  uint32_t skip;
+};
+
+__device__ __forceinline__ QBlock query_block(uint64_t t, int sym, uint64_t ncell, uint32_t tq,
+                                              const uint32_t *__restrict__ cell_start,
+                                              const uint32_t *__restrict__ qlist, uint64_t nq,
+                                              const uint32_t *__restrict__ qb_off,
+                                              const uint32_t *__restrict__ run_off,
+                                              const uint2 *__restrict__ runs,
+                                              const uint64_t *__restrict__ run_total) {
+  uint64_t lo = 0, hi = ncell;  // last cell with qb_off[A] <= t
+  while (hi - lo > 1) {
+    const uint64_t m = (lo + hi) >> 1;
+    if (qb_off[m] <= t) lo = m; else hi = m;
   }
-  if (!pass) {
-    wu_count[A] = units;
-    eval[A] = ev;
+  // cells without query blocks share their offset with the next cell, so
+  // the last cell whose offset is <= t is the one that owns block t
+  QBlock b;
+  b.A = (uint32_t)lo;
+  uint32_t qa, qe;
+  cell_query_slots(lo, cell_start, qlist, nq, &qa, &qe);
+  b.q0 = qa + (uint32_t)(t - qb_off[lo]) * tq;
+  b.q1 = min(b.q0 + tq, qe);
+  const uint32_t r0 = run_off[lo];
+  b.skip = sym ? (b.q0 - runs[r0].x) : 0u;
+  b.L = run_total[lo] - b.skip;
+  return b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wu_count(
+    uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+    const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qlist, uint64_t nq,
+    const uint32_t *__restrict__ qb_off, const uint32_t *__restrict__ run_off,
+    const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_total,
+    uint32_t *__restrict__ units, uint64_t *__restrict__ eval) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nqb_total) return;
+  const QBlock b = query_block(t, sym, ncell, tq, cell_start, qlist, nq, qb_off, run_off, runs,
+                               run_total);
+  units[t] = (uint32_t)((b.L + tc - 1) / tc);
+  eval[t] = (uint64_t)(b.q1 - b.q0) * b.L;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wu_fill(
+    uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+    const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qlist, uint64_t nq,
+    const uint32_t *__restrict__ qb_off, const uint32_t *__restrict__ run_off,
+    const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_total,
+    const uint32_t *__restrict__ unit_off, WorkUnit *__restrict__ wu) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nqb_total) return;
+  const QBlock b = query_block(t, sym, ncell, tq, cell_start, qlist, nq, qb_off, run_off, runs,
+                               run_total);
+  if (b.L == 0) return;
+  const uint32_t nu = (uint32_t)((b.L + tc - 1) / tc);
+  const uint32_t r1 = run_off[b.A + 1];
+  uint32_t r = run_off[b.A];
+  uint32_t c = runs[r].x + b.skip;
+  uint32_t w = unit_off[t];
+  for (uint32_t u = 0; u < nu; ++u) {
+    WorkUnit x;
+    x.q0 = b.q0;
+    x.q1 = b.q1;
+    x.cell = b.A;
+    x.pad = 0;
+    x.run_first = r;
+    x.c_begin = c;
+    uint32_t need = tc;
+    for (;;) {
+      const uint32_t avail = runs[r].y - c;
+      if (avail > need) { c += need; break; }
+      need -= avail;
+      if (r + 1 == r1 || need == 0) { c = runs[r].y; break; }
+      ++r;
+      c = runs[r].x;
+    }
+    x.run_last = r;
+    x.c_end = c;
+    wu[w++] = x;
+    if (c == runs[r].y && r + 1 < r1) { ++r; c = runs[r].x; }
   }
 }
 
@@ -448,13 +493,35 @@ void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
   SJ_HIP(hipGetLastError());
 }
 
-void launch_workunits(int pass, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
-                      const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
-                      const uint32_t *run_off, const uint2 *runs, uint32_t *wu_count,
-                      uint64_t *eval, const uint32_t *wu_off, WorkUnit *wu, hipStream_t s) {
+void launch_wu_cells(uint64_t ncell, uint32_t tq, const uint32_t *cell_start,
+                     const uint32_t *qlist, uint64_t nq, const uint32_t *run_off,
+                     const uint2 *runs, uint32_t *nqb, uint64_t *run_total, hipStream_t s) {
   if (!ncell) return;
-  hipLaunchKernelGGL(k_workunits, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, pass, sym, ncell,
-                     tq, tc, cell_start, qlist, nq, run_off, runs, wu_count, eval, wu_off, wu);
+  hipLaunchKernelGGL(k_wu_cells, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, ncell, tq,
+                     cell_start, qlist, nq, run_off, runs, nqb, run_total);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_wu_count(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+                     const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
+                     const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
+                     const uint64_t *run_total, uint32_t *units, uint64_t *eval, hipStream_t s) {
+  if (!nqb_total) return;
+  hipLaunchKernelGGL(k_wu_count, dim3(blocks_for(nqb_total)), dim3(kBlock), 0, s, nqb_total, sym,
+                     ncell, tq, tc, cell_start, qlist, nq, qb_off, run_off, runs, run_total, units,
+                     eval);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_wu_fill(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+                    const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
+                    const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
+                    const uint64_t *run_total, const uint32_t *unit_off, WorkUnit *wu,
+                    hipStream_t s) {
+  if (!nqb_total) return;
+  hipLaunchKernelGGL(k_wu_fill, dim3(blocks_for(nqb_total)), dim3(kBlock), 0, s, nqb_total, sym,
+                     ncell, tq, tc, cell_start, qlist, nq, qb_off, run_off, runs, run_total,
+                     unit_off, wu);
   SJ_HIP(hipGetLastError());
 }
 

@@ -45,10 +45,20 @@ void launch_neighbors(int pass, const uint64_t *cell_key, const uint32_t *cell_s
 void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
                  const uint32_t *nbr_off, const uint32_t *nbr_cell, uint32_t *run_count,
                  const uint32_t *run_off, uint2 *runs, hipStream_t s);
-void launch_workunits(int pass, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
-                      const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
-                      const uint32_t *run_off, const uint2 *runs, uint32_t *wu_count,
-                      uint64_t *eval, const uint32_t *wu_off, WorkUnit *wu, hipStream_t s);
+// Work units in three steps: per cell (query blocks, run total), per query
+// block (units, evaluated pairs), per query block (fill).
+void launch_wu_cells(uint64_t ncell, uint32_t tq, const uint32_t *cell_start,
+                     const uint32_t *qlist, uint64_t nq, const uint32_t *run_off,
+                     const uint2 *runs, uint32_t *nqb, uint64_t *run_total, hipStream_t s);
+void launch_wu_count(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+                     const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
+                     const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
+                     const uint64_t *run_total, uint32_t *units, uint64_t *eval, hipStream_t s);
+void launch_wu_fill(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
+                    const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
+                    const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
+                    const uint64_t *run_total, const uint32_t *unit_off, WorkUnit *wu,
+                    hipStream_t s);
 void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
                           uint64_t *out, hipStream_t s);
 

@@ -79,11 +79,11 @@ struct Lanes {
   float init[RQ];    // 0 for a live slot, +inf for an empty one
 };
 
-template <int DP, int RQ, bool kFilter>
+template <int DP, int RQ, bool kFilter, bool kCount>
 __device__ __forceinline__ void eval_candidate(
     const Lanes<DP, RQ> &L, uint32_t c, const float *__restrict__ X,
     const uint32_t *__restrict__ orig_id, const uint16_t *__restrict__ inv_perm, uint32_t d,
-    float lo, float hi, double eps2, bool symmetric, bool count_only, bool shortc,
+    float lo, float hi, double eps2, bool symmetric, bool shortc,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
   constexpr int kFirst = DP < 8 ? DP : 8;
@@ -142,7 +142,7 @@ __device__ __forceinline__ void eval_candidate(
     if (!((alive >> r) & 1u)) continue;
     const uint64_t m = ballot(s[r] <= hi);
     if (m == 0) continue;
-    if (count_only) {
+    if (kCount) {
       n_count += (uint64_t)__builtin_popcountll(m);
       continue;
     }
@@ -172,15 +172,16 @@ __device__ __forceinline__ void eval_candidate(
   }
 }
 
-template <int DP, int RQ>
-__global__ __launch_bounds__(kBlock) void k_join_fp32(
+// One wave = one work unit.  kCount: count the pairs the filter cannot
+// reject (s <= hi) instead of emitting them.
+template <int DP, int RQ, bool kCount>
+__device__ __forceinline__ void join_body(
     const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
     const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,
     const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, float lo,
-    float hi, double eps2, int symmetric, int count_only, int shortc,
-    uint64_t *__restrict__ out, uint64_t capacity, unsigned long long *__restrict__ cursor,
-    unsigned long long *__restrict__ rechecks) {
-  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+    float hi, double eps2, int symmetric, int shortc, uint64_t *__restrict__ out,
+    uint64_t capacity, unsigned long long *__restrict__ cursor,
+    unsigned long long *__restrict__ rechecks, uint64_t (*stage_mem)[kStage]) {
   const uint32_t w = uniform_u32(threadIdx.x / kWave);
   const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
   if (u >= n_wu) return;  // whole wave leaves; no workgroup barrier follows
@@ -210,9 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_join_fp32(
   // "query position <= candidate position" filter; beyond it all pass
   const uint32_t filt_end = (symmetric && !qlist) ? wu.q1 : 0u;
 
-  WaveStage st{&stage_mem[w][0], 0u};
+  WaveStage st{kCount ? nullptr : &stage_mem[w][0], 0u};
   uint64_t n_recheck = 0, n_count = 0;
-  const bool sym = symmetric != 0, cnt_only = count_only != 0, sc = shortc != 0;
+  const bool sym = symmetric != 0, sc = shortc != 0;
 
   for (uint32_t r = wu.run_first; r <= wu.run_last; ++r) {
     const uint2 run = runs[r];
@@ -220,17 +221,40 @@ __global__ __launch_bounds__(kBlock) void k_join_fp32(
     const uint32_t ce = (r == wu.run_last) ? wu.c_end : run.y;
     const uint32_t mid = cb < filt_end ? (ce < filt_end ? ce : filt_end) : cb;
     for (uint32_t c = cb; c < mid; ++c)
-      eval_candidate<DP, RQ, true>(L, c, X, orig_id, inv_perm, d, lo, hi, eps2, sym, cnt_only,
-                                   sc, st, out, capacity, cursor, n_recheck, n_count);
+      eval_candidate<DP, RQ, true, kCount>(L, c, X, orig_id, inv_perm, d, lo, hi, eps2, sym, sc,
+                                           st, out, capacity, cursor, n_recheck, n_count);
     for (uint32_t c = mid; c < ce; ++c)
-      eval_candidate<DP, RQ, false>(L, c, X, orig_id, inv_perm, d, lo, hi, eps2, sym, cnt_only,
-                                    sc, st, out, capacity, cursor, n_recheck, n_count);
+      eval_candidate<DP, RQ, false, kCount>(L, c, X, orig_id, inv_perm, d, lo, hi, eps2, sym, sc,
+                                            st, out, capacity, cursor, n_recheck, n_count);
   }
   stage_flush(st, out, capacity, cursor);
   if (l == 0) {
     if (n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
     if (n_count) atomicAdd(cursor, (unsigned long long)n_count);
   }
+}
+
+#define SJ_JOIN_PARAMS                                                                          \
+  const float *__restrict__ X, const uint32_t *__restrict__ orig_id,                            \
+      const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,   \
+      const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, float lo, \
+      float hi, double eps2, int symmetric, int shortc, uint64_t *__restrict__ out,             \
+      uint64_t capacity, unsigned long long *__restrict__ cursor,                               \
+      unsigned long long *__restrict__ rechecks
+
+// The self-join distance kernel: emits result pairs.
+template <int DP, int RQ>
+__global__ __launch_bounds__(kBlock) void k_join_fp32(SJ_JOIN_PARAMS) {
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  join_body<DP, RQ, false>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi, eps2,
+                           symmetric, shortc, out, capacity, cursor, rechecks, stage_mem);
+}
+
+// The estimation kernel (count only) used to size result buffers.
+template <int DP, int RQ>
+__global__ __launch_bounds__(kBlock) void k_count_fp32(SJ_JOIN_PARAMS) {
+  join_body<DP, RQ, true>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi, eps2,
+                          symmetric, shortc, out, capacity, cursor, rechecks, nullptr);
 }
 
 __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ keys,
@@ -264,16 +288,15 @@ template <int DP>
 void launch_dp(const JoinLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
   if (grid == 0) return;
-  const uint64_t *dummy = nullptr;
-  (void)dummy;
-#define SJ_LAUNCH_RQ(RQV)                                                                       \
-  hipLaunchKernelGGL((k_join_fp32<DP, RQV>), dim3(grid), dim3(kBlock), 0, s, a.X, a.orig_id,    \
-                     a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi, a.eps2,        \
-                     a.symmetric, a.count_only, a.shortc, a.out, a.capacity, a.cursor,          \
-                     a.rechecks)
   constexpr int kRq = DP <= 24 ? 4 : (DP <= 64 ? 2 : 1);
-  SJ_LAUNCH_RQ(kRq);
-#undef SJ_LAUNCH_RQ
+  if (a.count_only)
+    hipLaunchKernelGGL((k_count_fp32<DP, kRq>), dim3(grid), dim3(kBlock), 0, s, a.X, a.orig_id,
+                       a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi, a.eps2,
+                       a.symmetric, a.shortc, a.out, a.capacity, a.cursor, a.rechecks);
+  else
+    hipLaunchKernelGGL((k_join_fp32<DP, kRq>), dim3(grid), dim3(kBlock), 0, s, a.X, a.orig_id,
+                       a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi, a.eps2,
+                       a.symmetric, a.shortc, a.out, a.capacity, a.cursor, a.rechecks);
   SJ_HIP(hipGetLastError());
 }
 

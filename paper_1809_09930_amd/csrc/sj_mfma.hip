@@ -1,0 +1,454 @@
+// Matrix-core distance filter of the self-join on gfx950: 16-bit operands,
+// FP32 accumulation, rigorous error band, FP64 recheck of the band.
+//
+// Form.  With a fixed centre c, every point is stored as x~ = Q(x - c) in
+// FP16 or BF16 (Q = round to nearest; magnitudes below the format's
+// smallest normal are flushed to 0).  For a candidate row a and a query
+// column b one 32x32 MFMA tile accumulates
+//     D = n_a - 2 a~ . b~        (n_a = |a~|^2, folded in as 2 or 3 exact
+//                                 16-bit pieces in spare K columns)
+// so that D + n_b is the squared distance of the quantised points.
+// The operands are laid out K-contiguous: A rows [a~ | pieces of n_a | 0],
+// B columns [-2 b~ | 1 .. 1 | 0]; scaling by -2 is exact.
+//
+// Band.  Per query b the FP64 preparation below gives thresholds
+// Thi(b) >= D for every candidate the canonical predicate accepts, and
+// Tlo(b) such that D <= Tlo(b) proves acceptance (derivation in
+// k_mfma_thresholds).  D > Thi rejects, D <= Tlo accepts, the rest is
+// rechecked with the canonical FP64 predicate, so the pair set is exact.
+//
+// Tiles.  Rows = 32 consecutive candidate positions, columns = 32 queries;
+// a wave holds QB query blocks (B operands and thresholds in registers) and
+// streams candidate blocks (A operands) from memory.  Each lane's 16
+// accumulators share one query column, so "any pair of this lane below its
+// threshold" is one min over 16 values (v_min3) and one compare; only tiles
+// with a hit enter the per-element path.
+#include "sj_internal.hpp"
+#include "sj_mfma.hpp"
+
+#include <algorithm>
+#include <cfloat>
+
+namespace sj {
+
+namespace {
+
+constexpr int kStage = 512;
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float float16v __attribute__((ext_vector_type(16)));
+
+template <int FMT>
+struct Fmt;
+template <>
+struct Fmt<kFmtF16> {
+  typedef _Float16 T;
+  typedef half8 V8;
+  static constexpr int kPieces = 2;
+  __device__ static T inf() { return (T)__builtin_inff(); }
+  __device__ static float16v mfma(V8 a, V8 b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Fmt<kFmtBF16> {
+  typedef __bf16 T;
+  typedef bf16x8 V8;
+  static constexpr int kPieces = 3;
+  __device__ static T inf() { return (T)__builtin_inff(); }
+  __device__ static float16v mfma(V8 a, V8 b, float16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Round to the 16-bit format, flushing magnitudes below its smallest
+// normal to zero (the error bound budgets for that flush).
+template <int FMT>
+__device__ __forceinline__ typename Fmt<FMT>::T quantise(double v) {
+  const double tiny = FMT == kFmtF16 ? 6.103515625e-05 /* 2^-14 */ : 1.1754943508222875e-38;
+  if (__builtin_fabs(v) < tiny) return (typename Fmt<FMT>::T)0.0f;
+  // double -> float is exact for the values used here (v is a float
+  // difference or a residual of a float-sized sum); float -> 16 bit rounds
+  return (typename Fmt<FMT>::T)(float)v;
+}
+
+// ---------------------------------------------------------------------------
+// Preparation, pass 1: quantised rows, norms and the global maxima.
+// ---------------------------------------------------------------------------
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_mfma_prep(
+    const float *__restrict__ X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
+    uint32_t kp, const float *__restrict__ centre, typename Fmt<FMT>::T *__restrict__ XA,
+    typename Fmt<FMT>::T *__restrict__ XB, double *__restrict__ norm2,
+    double *__restrict__ dist_c, double *__restrict__ fold_err,
+    unsigned long long *__restrict__ maxima) {
+  typedef typename Fmt<FMT>::T T;
+  const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n_pad) return;
+  T *a = XA + p * kp;
+  T *b = XB + p * kp;
+  if (p >= n) {  // padding rows: D = +inf for every query
+    for (uint32_t k = 0; k < kp; ++k) {
+      a[k] = (T)0.0f;
+      b[k] = (T)0.0f;
+    }
+    a[d] = Fmt<FMT>::inf();
+    return;
+  }
+  const float *x = X + p * dp;
+  double nn = 0.0, dc = 0.0;
+  for (uint32_t t = 0; t < d; ++t) {
+    const float diff = x[t] - centre[t];  // rounded to FP32: budgeted
+    const T q = quantise<FMT>((double)diff);
+    a[t] = q;
+    b[t] = (T)(-2.0f * (float)q);  // exact
+    const double qd = (double)(float)q;
+    nn += qd * qd;
+    const double e = (double)x[t] - (double)centre[t];
+    dc += e * e;
+  }
+  // exact pieces of the norm: n = h1 + h2 (+ h3) + residual
+  double r = nn;
+  for (int i = 0; i < Fmt<FMT>::kPieces; ++i) {
+    const T h = quantise<FMT>(r);
+    a[d + i] = h;
+    b[d + i] = (T)1.0f;
+    r -= (double)(float)h;
+  }
+  for (uint32_t k = d + Fmt<FMT>::kPieces; k < kp; ++k) {
+    a[k] = (T)0.0f;
+    b[k] = (T)0.0f;
+  }
+  norm2[p] = nn;
+  dist_c[p] = __builtin_sqrt(dc);
+  fold_err[p] = __builtin_fabs(r);
+}
+
+// Maxima of |x - c|, |x~|, n and the fold residual over all points.
+// Non-negative doubles compare like their bit patterns.
+__global__ __launch_bounds__(kBlock) void k_mfma_maxima(uint64_t n, const double *__restrict__ norm2,
+                                                        const double *__restrict__ dist_c,
+                                                        const double *__restrict__ fold_err,
+                                                        unsigned long long *__restrict__ maxima) {
+  unsigned long long m[4] = {0, 0, 0, 0};
+  for (uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p < n;
+       p += (uint64_t)gridDim.x * kBlock) {
+    const double v[4] = {dist_c[p], __builtin_sqrt(norm2[p]), norm2[p], fold_err[p]};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, v[i]);
+      m[i] = b > m[i] ? b : m[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(m[i], off);
+      m[i] = o > m[i] ? o : m[i];
+    }
+    if (lane_id() == 0) atomicMax(&maxima[i], m[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Preparation, pass 2: per-query thresholds.
+//
+// Notation for a query b and any candidate a:
+//   S    exact squared distance of the FP32 points, S64 its canonical FP64
+//        value; canonical acceptance is S64 <= eps2, and
+//        S64 <= eps2 implies S <= s_hi = eps2/(1-g64), while
+//        S <= s_lo = eps2/(1+g64) implies S64 <= eps2 (g64 = gamma_{d+2}(2^-53)).
+//   S_q  squared distance of the quantised points a~, b~.
+//   Each coordinate error |x~ - (x-c)| <= u|x-c| + eta, u = (1+2^-24)(1+u16)-1
+//   (u16 = 2^-11 FP16, 2^-8 BF16; eta = the flush threshold), hence by the
+//   triangle inequality |sqrt(S_q) - sqrt(S)| <= Delta_b =
+//   u (|b-c| + R) + 2 eta sqrt(d), R = max over points of |x-c|.
+//   D = n_a - 2 a~.b~ up to E' = gamma_K(2^-23)(N + F + 2 |b~| Rq) + F + 2^-120
+//   (FP32 accumulation of K exact products in any order, even with
+//   truncating adds; N, Rq, F = maxima of n_a, |a~|, fold residual), and
+//   S_q = D_exact + n_b.
+// Then
+//   Thi(b) = (sqrt(s_hi) + Delta_b)^2 - n_b + E'   (canonical accept => D <= Thi)
+//   Tlo(b) = (max(0, sqrt(s_lo) - Delta_b))^2 - n_b - E'   (D <= Tlo => accept)
+// evaluated in FP64 with a relative margin and rounded outward to FP32.
+// ---------------------------------------------------------------------------
+// next float above a finite f (one ulp step on the bit pattern)
+__device__ __forceinline__ float next_up(float f) {
+  if (f == 0.0f) return __builtin_bit_cast(float, 1u);
+  const uint32_t b = __builtin_bit_cast(uint32_t, f);
+  return __builtin_bit_cast(float, f > 0.0f ? b + 1u : b - 1u);
+}
+__device__ __forceinline__ float round_up_f32(double v) {
+  if (v != v || v == __builtin_inf()) return __builtin_inff();
+  if (v == -__builtin_inf()) return -__builtin_inff();
+  float f = (float)v;
+  if ((double)f < v) f = next_up(f);
+  return f;
+}
+__device__ __forceinline__ float round_down_f32(double v) {
+  return -round_up_f32(-v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mfma_thresholds(
+    uint64_t n, uint64_t n_pad, MfmaBand band, const double *__restrict__ norm2,
+    const double *__restrict__ dist_c, const unsigned long long *__restrict__ maxima,
+    float *__restrict__ thi, float *__restrict__ tlo) {
+  const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p >= n_pad) return;
+  if (p >= n) {
+    thi[p] = -__builtin_inff();
+    tlo[p] = -__builtin_inff();
+    return;
+  }
+  const double R = __builtin_bit_cast(double, (uint64_t)maxima[0]);
+  const double Rq = __builtin_bit_cast(double, (uint64_t)maxima[1]);
+  const double N = __builtin_bit_cast(double, (uint64_t)maxima[2]);
+  const double F = __builtin_bit_cast(double, (uint64_t)maxima[3]);
+  const double nb = norm2[p];
+  const double bq = __builtin_sqrt(nb);
+  const double delta = band.u * (dist_c[p] + R) + band.eta_term;
+  const double E = band.gamma_acc * (N + F + 2.0 * bq * Rq) + F + 0x1p-120;
+  const double m = 0x1p-45;
+  const double hi_root = __builtin_sqrt(band.s_hi) * (1.0 + m) + delta;
+  const double thi_v = (hi_root * hi_root - nb + E) + m * (hi_root * hi_root + nb + E);
+  double lo_root = __builtin_sqrt(band.s_lo) * (1.0 - m) - delta;
+  double tlo_v;
+  if (lo_root <= 0.0) {
+    tlo_v = -__builtin_inf();
+  } else {
+    tlo_v = (lo_root * lo_root - nb - E) - m * (lo_root * lo_root + nb + E);
+  }
+  thi[p] = round_up_f32(thi_v);
+  tlo[p] = round_down_f32(tlo_v);
+}
+
+// ---------------------------------------------------------------------------
+// Canonical predicate on positions (caller's dimension order, FP64, no
+// contraction).
+// ---------------------------------------------------------------------------
+__device__ __noinline__ bool canonical_within_m(const float *__restrict__ X, uint32_t a, uint32_t b,
+                                                const uint16_t *__restrict__ inv_perm, uint32_t d,
+                                                uint32_t dp, double eps2) {
+#pragma clang fp contract(off)
+  const float *pa = X + (uint64_t)a * dp;
+  const float *pb = X + (uint64_t)b * dp;
+  double acc = 0.0;
+  for (uint32_t t = 0; t < d; ++t) {
+    const uint32_t r = inv_perm[t];
+    const double diff = (double)pa[r] - (double)pb[r];
+    const double sq = diff * diff;
+    acc = acc + sq;
+  }
+  return acc <= eps2;
+}
+
+struct Stage {
+  uint64_t *buf;
+  uint32_t cnt;
+};
+
+__device__ __forceinline__ void flush(Stage &st, uint64_t *__restrict__ out, uint64_t capacity,
+                                      unsigned long long *__restrict__ cursor) {
+  if (st.cnt == 0) return;
+  __builtin_amdgcn_wave_barrier();
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(cursor, (unsigned long long)st.cnt);
+  base = uniform_u64(__shfl(base, 0));
+  for (uint32_t i = lane_id(); i < st.cnt; i += kWave) {
+    const uint64_t pos = base + i;
+    if (pos < capacity) out[pos] = st.buf[i];
+  }
+  __builtin_amdgcn_wave_barrier();
+  st.cnt = 0;
+}
+
+__device__ __forceinline__ float min16(const float16v &v) {
+  float a = __builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]);
+  float b = __builtin_fminf(__builtin_fminf(v[3], v[4]), v[5]);
+  float c = __builtin_fminf(__builtin_fminf(v[6], v[7]), v[8]);
+  float e = __builtin_fminf(__builtin_fminf(v[9], v[10]), v[11]);
+  float f = __builtin_fminf(__builtin_fminf(v[12], v[13]), v[14]);
+  a = __builtin_fminf(__builtin_fminf(a, b), c);
+  e = __builtin_fminf(__builtin_fminf(e, f), v[15]);
+  return __builtin_fminf(a, e);
+}
+
+template <int KP, int FMT, int QB>
+__global__ __launch_bounds__(kBlock) void k_join_mfma(
+    const typename Fmt<FMT>::V8 *__restrict__ XA, const typename Fmt<FMT>::V8 *__restrict__ XB,
+    const float *__restrict__ thi, const float *__restrict__ tlo, const float *__restrict__ X,
+    const uint32_t *__restrict__ orig_id, const uint16_t *__restrict__ inv_perm,
+    const WorkUnit *__restrict__ wus, uint64_t n_wu, const uint2 *__restrict__ runs,
+    const uint32_t *__restrict__ qlist, uint32_t d, uint32_t dp, double eps2, int symmetric,
+    uint64_t *__restrict__ out, uint64_t capacity, unsigned long long *__restrict__ cursor,
+    unsigned long long *__restrict__ rechecks) {
+  typedef typename Fmt<FMT>::V8 V8;
+  constexpr int KS = KP / 16;   // MFMA K steps
+  constexpr int RV = KP / 8;    // 8-element vectors per row
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
+  if (u >= n_wu) return;
+  const WorkUnit wu = wus[u];
+  const uint32_t l = lane_id();
+  const uint32_t half = l >> 5, col = l & 31;
+
+  // query columns: B operands, thresholds, positions
+  V8 B[QB][KS];
+  float th[QB];
+  uint32_t qpos[QB];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    const uint32_t slot = wu.q0 + (uint32_t)j * 32 + col;
+    const bool live = slot < wu.q1;
+    const uint32_t p = live ? (qlist ? qlist[slot] : slot) : 0u;
+    qpos[j] = live ? p : 0xffffffffu;
+    th[j] = live ? thi[p] : -__builtin_inff();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
+  }
+
+  Stage st{&stage_mem[w][0], 0u};
+  uint64_t n_recheck = 0;
+  const bool sym = symmetric != 0;
+
+  for (uint32_t r = wu.run_first; r <= wu.run_last; ++r) {
+    const uint2 run = runs[r];
+    const uint32_t cb = (r == wu.run_first) ? wu.c_begin : run.x;
+    const uint32_t ce = (r == wu.run_last) ? wu.c_end : run.y;
+    for (uint32_t c = cb; c < ce; c += 32) {
+      // candidate row of this lane's A operand; rows past the run's end (at
+      // most 31, inside the padded arrays) are dropped in the hit path
+      const uint32_t row_pos = c + col;
+      V8 A[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) A[ks] = XA[(uint64_t)row_pos * RV + ks * 2 + half];
+      float16v acc[QB];
+#pragma unroll
+      for (int j = 0; j < QB; ++j) {
+        float16v z = {};
+        acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
+#pragma unroll
+        for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < QB; ++j) {
+        if (ballot(min16(acc[j]) <= th[j]) == 0) continue;
+        // some pair of this tile may be a result: check element by element
+        float tl = 0.0f;
+        if (qpos[j] != 0xffffffffu) tl = tlo[qpos[j]];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const bool h = acc[j][e] <= th[j];
+          if (ballot(h) == 0) continue;
+          const uint32_t row = 8 * (e / 4) + 4 * half + (e % 4);
+          const uint32_t cp = c + row;
+          const bool ok = h && cp < ce && (!sym || qpos[j] <= cp);
+          bool acc_ok = ok && acc[j][e] <= tl;
+          const bool band = ok && !acc_ok;
+          const uint64_t bm = ballot(band);
+          if (bm) {
+            if (band) acc_ok = canonical_within_m(X, qpos[j], cp, inv_perm, d, dp, eps2);
+            n_recheck += (uint64_t)__builtin_popcountll(bm);
+          }
+          const uint64_t am = ballot(acc_ok);
+          if (am == 0) continue;
+          const bool two = acc_ok && sym && qpos[j] != cp;
+          const uint64_t m2 = ballot(two);
+          const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+          if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
+          const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+          if (acc_ok) {
+            const uint32_t qi = orig_id[qpos[j]], ci = orig_id[cp];
+            st.buf[off] = ((uint64_t)qi << 32) | ci;
+            if (two) st.buf[off + 1] = ((uint64_t)ci << 32) | qi;
+          }
+          st.cnt += total;
+        }
+      }
+    }
+  }
+  flush(st, out, capacity, cursor);
+  if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+template <int KP, int FMT>
+void launch_kp(const MfmaLaunch &a, hipStream_t s) {
+  const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (!grid) return;
+  typedef typename Fmt<FMT>::V8 V8;
+  constexpr int QB = KP <= 64 ? 4 : 2;
+  hipLaunchKernelGGL((k_join_mfma<KP, FMT, QB>), dim3(grid), dim3(kBlock), 0, s,
+                     (const V8 *)a.XA, (const V8 *)a.XB, a.thi, a.tlo, a.X, a.orig_id, a.inv_perm,
+                     a.wu, a.n_wu, a.runs, a.qlist, a.d, a.dp, a.eps2, a.symmetric, a.out,
+                     a.capacity, a.cursor, a.rechecks);
+  SJ_HIP(hipGetLastError());
+}
+
+template <int FMT>
+void launch_fmt(const MfmaLaunch &a, hipStream_t s) {
+  switch (a.kp) {
+    case 16: launch_kp<16, FMT>(a, s); break;
+    case 32: launch_kp<32, FMT>(a, s); break;
+    case 48: launch_kp<48, FMT>(a, s); break;
+    case 64: launch_kp<64, FMT>(a, s); break;
+    case 80: launch_kp<80, FMT>(a, s); break;
+    case 96: launch_kp<96, FMT>(a, s); break;
+    case 112: launch_kp<112, FMT>(a, s); break;
+    case 128: launch_kp<128, FMT>(a, s); break;
+    case 144: launch_kp<144, FMT>(a, s); break;
+    default: fail(SJ_ERR_INVALID_ARG, "unsupported MFMA K padding");
+  }
+}
+
+}  // namespace
+
+int mfma_pieces(int fmt) { return fmt == kFmtF16 ? 2 : 3; }
+
+uint32_t mfma_kp(uint32_t d, int fmt) {
+  const uint32_t k = d + (uint32_t)mfma_pieces(fmt);
+  return (k + 15) / 16 * 16;
+}
+
+int mfma_qb(uint32_t kp) { return kp <= 64 ? 4 : 2; }
+
+void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
+                      uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,
+                      double *dist_c, double *fold_err, unsigned long long *maxima,
+                      hipStream_t s) {
+  const uint32_t grid = (uint32_t)((n_pad + kBlock - 1) / kBlock);
+  if (!grid) return;
+  if (fmt == kFmtF16)
+    hipLaunchKernelGGL(k_mfma_prep<kFmtF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
+                       kp, centre, (_Float16 *)XA, (_Float16 *)XB, norm2, dist_c, fold_err,
+                       maxima);
+  else
+    hipLaunchKernelGGL(k_mfma_prep<kFmtBF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
+                       kp, centre, (__bf16 *)XA, (__bf16 *)XB, norm2, dist_c, fold_err, maxima);
+  SJ_HIP(hipGetLastError());
+  SJ_HIP(hipMemsetAsync(maxima, 0, 4 * sizeof(unsigned long long), s));
+  const uint32_t g2 = (uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
+  if (g2) {
+    hipLaunchKernelGGL(k_mfma_maxima, dim3(g2), dim3(kBlock), 0, s, n, norm2, dist_c, fold_err,
+                       maxima);
+    SJ_HIP(hipGetLastError());
+  }
+}
+
+void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, const double *norm2,
+                            const double *dist_c, const unsigned long long *maxima, float *thi,
+                            float *tlo, hipStream_t s) {
+  const uint32_t grid = (uint32_t)((n_pad + kBlock - 1) / kBlock);
+  if (!grid) return;
+  hipLaunchKernelGGL(k_mfma_thresholds, dim3(grid), dim3(kBlock), 0, s, n, n_pad, band, norm2,
+                     dist_c, maxima, thi, tlo);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_join_mfma(const MfmaLaunch &a, hipStream_t s) {
+  if (a.fmt == kFmtF16) launch_fmt<kFmtF16>(a, s);
+  else launch_fmt<kFmtBF16>(a, s);
+}
+
+}  // namespace sj

@@ -1,0 +1,50 @@
+// Matrix-core distance filter (sj_mfma.hip).
+#pragma once
+
+#include "sj_internal.hpp"
+
+namespace sj {
+
+constexpr int kFmtF16 = 0;
+constexpr int kFmtBF16 = 1;
+
+// Constants of the error band (see k_mfma_thresholds).
+struct MfmaBand {
+  double u;          // relative error of centring + quantisation per coordinate
+  double eta_term;   // 2 * flush threshold * sqrt(d)
+  double gamma_acc;  // gamma_K(2^-23) of the FP32 accumulation
+  double s_hi, s_lo; // eps2/(1-g64), eps2/(1+g64)
+};
+
+struct MfmaLaunch {
+  int fmt;
+  uint32_t kp;
+  const void *XA, *XB;      // [n_pad][kp] 16-bit operands (candidate rows / query columns)
+  const float *thi, *tlo;   // per-point thresholds
+  const float *X;           // FP32 rows (recheck)
+  const uint32_t *orig_id;
+  const uint16_t *inv_perm;
+  const WorkUnit *wu;
+  uint64_t n_wu;
+  const uint2 *runs;
+  const uint32_t *qlist;
+  uint32_t d, dp;
+  double eps2;
+  int symmetric;
+  uint64_t *out;
+  uint64_t capacity;
+  unsigned long long *cursor, *rechecks;
+};
+
+int mfma_pieces(int fmt);
+uint32_t mfma_kp(uint32_t d, int fmt);
+int mfma_qb(uint32_t kp);
+void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
+                      uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,
+                      double *dist_c, double *fold_err, unsigned long long *maxima, hipStream_t s);
+void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, const double *norm2,
+                            const double *dist_c, const unsigned long long *maxima, float *thi,
+                            float *tlo, hipStream_t s);
+void launch_join_mfma(const MfmaLaunch &a, hipStream_t s);
+
+}  // namespace sj

@@ -22,6 +22,9 @@ SJ_ERR_RANGE = -6
 SJ_MAX_DIM = 128
 
 SJ_PREC_FP32 = 0
+SJ_PREC_FP16 = 1
+SJ_PREC_BF16 = 2
+PRECISIONS = {"fp32": SJ_PREC_FP32, "fp16": SJ_PREC_FP16, "bf16": SJ_PREC_BF16}
 
 EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_run",
             "selfjoin_fetch_pairs", "selfjoin_get_info", "selfjoin_get_perm",
@@ -127,7 +130,7 @@ def _stream_handle(stream):
 def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = True,
                          shortc: bool = True, batch_pairs: int = 0, min_batches: int = 0,
                          mem_budget: int = 0, k_min: int = 4, k_max: int = 8,
-                         stream=None):
+                         precision="fp32", stream=None):
     """Build the grid index over a float32 [n, d] tensor (CUDA or CPU).
     Returns an opaque handle (int)."""
     import torch
@@ -143,6 +146,7 @@ def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = Tru
     o.batch_pairs = int(batch_pairs)
     o.min_batches = int(min_batches)
     o.mem_budget = int(mem_budget)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     h = ctypes.c_void_p()
     n, d = points.shape
     ptr = points.data_ptr() if points.numel() else None

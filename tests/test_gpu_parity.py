@@ -90,9 +90,61 @@ def test_clustered_many_cells_matches_oracle(n, d, seed):
     assert info["candidates"] < n * n
 
 
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("n,d,seed,target", [
+    (3000, 16, 1, 32), (2500, 8, 2, 20), (1999, 18, 3, 40), (1500, 64, 4, 16),
+    (777, 90, 5, 12), (640, 128, 6, 10), (1000, 1, 7, 5), (4097, 16, 9, 3)])
+def test_matrix_core_uniform_matches_oracle(prec, n, d, seed, target):
+    P = datagen.uniform_grid(n, d, seed)
+    info = assert_same_as_oracle(P, calibrated(P, target), precision=prec)
+    assert info["precision"] == {"fp16": 1, "bf16": 2}[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("n,d,seed", [(5000, 18, 11), (3000, 12, 12), (2000, 90, 13)])
+def test_matrix_core_clustered_matches_oracle(prec, n, d, seed):
+    std = datagen.decaying_std(d, 0.2, 0.002, seed)
+    P = datagen.gaussian_mixture(n, d, 20, std, seed)
+    assert_same_as_oracle(P, calibrated(P, 30), precision=prec)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_matrix_core_band_is_rechecked(prec):
+    """Many pairs sit right at eps: the 16-bit form cannot decide them, the
+    FP64 recheck must, and the result must still equal the oracle's."""
+    u = 2.0 ** -24
+    rng = np.random.default_rng(77)
+    base = datagen.uniform_grid(400, 4, 78)
+    eps = 0.1
+    # partners at distance eps * (1 + k * 2^-20), k in -3..3, along random axes
+    extra = []
+    for p in base[:150]:
+        axis = rng.integers(0, 4)
+        k = rng.integers(-3, 4)
+        q = p.astype(np.float64).copy()
+        q[axis] += eps * (1 + k * 2.0 ** -20)
+        extra.append(np.round(q / u) * u)
+    P = np.concatenate([base, np.array(extra, dtype=np.float32)])
+    info = assert_same_as_oracle(P, eps, precision=prec)
+    assert info["rechecks"] > 0
+
+
+def test_matrix_core_batched_and_filters():
+    P = datagen.uniform_grid(2500, 16, 51)
+    eps = calibrated(P, 30)
+    info = assert_same_as_oracle(P, eps, precision="fp16", batch_pairs=5000)
+    assert info["batches"] >= 3
+    assert_same_as_oracle(P, eps, precision="bf16", k=2, reorder=False)
+
+
 def test_empty_single_and_duplicates():
     gi, gj, gd, info = gpu_join(np.zeros((0, 5), np.float32), 0.5)
     assert len(gi) == 0 and info["pairs"] == 0
+    for prec in ("fp16", "bf16"):
+        assert_same_as_oracle(np.full((300, 4), 0.375, np.float32), 1e-6, precision=prec)
+        gi, gj, gd, _ = gpu_join(np.array([[0.5, 0.25, 0.125]], np.float32), 1e-3,
+                                 precision=prec)
+        assert gi.tolist() == [0] and gj.tolist() == [0]
     gi, gj, gd, _ = gpu_join(np.array([[0.5, 0.25, 0.125]], np.float32), 1e-3)
     assert gi.tolist() == [0] and gj.tolist() == [0] and gd.tolist() == [0.0]
     P = np.repeat(datagen.uniform_grid(40, 6, 21), 3, axis=0)
