@@ -55,6 +55,9 @@ def parse():
                     help="distance filter of the headline line")
     ap.add_argument("--compare", default="fp16",
                     help="comma list of other precisions timed on the same workload ('' = none)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only copy a buffer of this many MiB device-to-device 3 times (scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
 
 
@@ -122,6 +125,14 @@ def main():
               "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.copy_probe_mib:
+        src = torch.empty(a.copy_probe_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel() * 4, "copies": 3}))
+        return
     from paper_1809_09930_amd import selfjoin as sj
     sj.load_library()
     with open(EPS_TABLE) as f:

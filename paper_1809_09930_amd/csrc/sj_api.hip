@@ -137,7 +137,8 @@ struct Geometry {
   uint32_t k = 0;
   KeyParams kp{};
   NbrParams np{};
-  uint32_t key_bits = 0;
+  uint32_t key_bits = 0;   // bits of the sort key
+  uint32_t fine_bits = 0;  // low bits of the sort key below the cell key
 };
 
 double gamma_n(double m, double u) { return m * u / (1.0 - m * u); }
@@ -232,7 +233,23 @@ bool make_geometry(const sj_index &ix, uint32_t k, Geometry &g) {
     g.np.m[r] = m[r];
     mult *= m[r];
   }
-  g.key_bits = bits_for(mult - 1);
+  const uint32_t cell_bits = bits_for(mult - 1);
+  // fine key: Morton code of up to 6 reordered dimensions, 4 bits each,
+  // as far as the 64-bit sort key allows
+  const uint32_t fm = std::min<uint32_t>(ix.d, 6);
+  uint32_t fb = 4;
+  while (fb > 0 && cell_bits + fm * fb > 63) --fb;
+  g.kp.fm = fb ? fm : 0;
+  g.kp.fb = fb;
+  for (uint32_t r = 0; r < g.kp.fm; ++r) {
+    const uint32_t t = ix.perm[r];
+    g.kp.fdim[r] = t;
+    g.kp.forg[r] = ix.dmin[t];
+    const double span = ix.dmax[t] - ix.dmin[t];
+    g.kp.fscale[r] = span > 0.0 ? (double)(1u << fb) / span : 0.0;
+  }
+  g.fine_bits = g.kp.fm * g.kp.fb;
+  g.key_bits = cell_bits + g.fine_bits;
   uint64_t noff = 1;
   for (uint32_t r = 0; r < k; ++r) noff *= 3;
   g.np.n_off = noff;
@@ -261,8 +278,8 @@ uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t
                   ix.orig_id.as<uint32_t>(), ix.pos_of.as<uint32_t>(), s);
   }
   uint32_t *d_ncell = t.small.as<uint32_t>();
-  launch_compact(kb[0], n, t.flag.as<uint32_t>(), d_ncell, ix.cell_key.as<uint64_t>(),
-                 ix.cell_start.as<uint32_t>(), t.scan.p, s);
+  launch_compact(kb[0], n, g.fine_bits, t.flag.as<uint32_t>(), d_ncell,
+                 ix.cell_key.as<uint64_t>(), ix.cell_start.as<uint32_t>(), t.scan.p, s);
   uint32_t h_ncell = 0;
   SJ_HIP(hipMemcpyAsync(&h_ncell, d_ncell, 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
@@ -730,6 +747,7 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
   ix.info.ms_join += ms_join;
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
+  if (ix.prec != SJ_PREC_FP32) launch_pos_to_id(ix.pairs.as<uint64_t>(), ix.total, ix.orig_id.as<uint32_t>(), s);
   other.alloc(ix.total * 8);
   sort_pairs(ix, ix.pairs, other, ix.total, s);
   SJ_HIP(hipEventRecord(e1.e, s));
@@ -812,6 +830,7 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
       sl.tmp2.ensure(std::max<uint64_t>(got, 1) * 8);
       Event e0, e1;
       SJ_HIP(hipEventRecord(e0.e, s));
+      if (mf) launch_pos_to_id(sl.keys.as<uint64_t>(), got, ix.orig_id.as<uint32_t>(), s);
       sort_pairs(ix, sl.keys, sl.tmp2, got, s);
       SJ_HIP(hipEventRecord(e1.e, s));
       PinnedBuf hb;

@@ -128,7 +128,20 @@ __global__ __launch_bounds__(kBlock) void k_cellkey(const float *__restrict__ P,
     ci = ci > kp.cmax[r] ? kp.cmax[r] : ci;
     key += ci * kp.mult[r];
   }
-  keys[i] = key;
+  uint64_t fine = 0;
+  if (kp.fm) {
+    uint32_t f[kFineMaxDims];
+    const uint32_t fmax = (1u << kp.fb) - 1u;
+    for (uint32_t r = 0; r < kp.fm; ++r) {
+      double v = ((double)P[i * d + kp.fdim[r]] - kp.forg[r]) * kp.fscale[r];
+      v = v < 0.0 ? 0.0 : v;
+      uint32_t q = (uint32_t)v;
+      f[r] = q > fmax ? fmax : q;
+    }
+    for (int b = (int)kp.fb - 1; b >= 0; --b)
+      for (uint32_t r = 0; r < kp.fm; ++r) fine = (fine << 1) | ((f[r] >> b) & 1u);
+  }
+  keys[i] = (key << (kp.fm * kp.fb)) | fine;
   ids[i] = (uint32_t)i;
 }
 
@@ -158,22 +171,23 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ P, 
 // a5: compaction of the non-empty cells.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_cell_flags(const uint64_t *__restrict__ keys,
-                                                       uint64_t n, uint32_t *__restrict__ flag) {
+                                                       uint64_t n, uint32_t sh,
+                                                       uint32_t *__restrict__ flag) {
   const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
-  flag[p] = (p == 0 || keys[p] != keys[p - 1]) ? 1u : 0u;
+  flag[p] = (p == 0 || (keys[p] >> sh) != (keys[p - 1] >> sh)) ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_write(const uint64_t *__restrict__ keys,
-                                                       uint64_t n,
+                                                       uint64_t n, uint32_t sh,
                                                        const uint32_t *__restrict__ cidx,
                                                        uint64_t *__restrict__ cell_key,
                                                        uint32_t *__restrict__ cell_start) {
   const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n) return;
-  const bool first = (p == 0 || keys[p] != keys[p - 1]);
+  const bool first = (p == 0 || (keys[p] >> sh) != (keys[p - 1] >> sh));
   if (first) {
-    cell_key[cidx[p]] = keys[p];
+    cell_key[cidx[p]] = keys[p] >> sh;
     cell_start[cidx[p]] = (uint32_t)p;
   }
   // cell index of p is cidx[p] when p starts a cell, else cidx[p] - 1
@@ -462,14 +476,16 @@ void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const ui
   SJ_HIP(hipGetLastError());
 }
 
-void launch_compact(const uint64_t *keys, uint64_t n, uint32_t *flag_tmp, uint32_t *d_ncell,
-                    uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp, hipStream_t s) {
+void launch_compact(const uint64_t *keys, uint64_t n, uint32_t fine_shift, uint32_t *flag_tmp,
+                    uint32_t *d_ncell, uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp,
+                    hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_cell_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, keys, n, flag_tmp);
+  hipLaunchKernelGGL(k_cell_flags, dim3(blocks_for(n)), dim3(kBlock), 0, s, keys, n, fine_shift,
+                     flag_tmp);
   SJ_HIP(hipGetLastError());
   exclusive_scan_u32(flag_tmp, flag_tmp, n, d_ncell, scan_tmp, s);
-  hipLaunchKernelGGL(k_cell_write, dim3(blocks_for(n)), dim3(kBlock), 0, s, keys, n, flag_tmp,
-                     cell_key, cell_start);
+  hipLaunchKernelGGL(k_cell_write, dim3(blocks_for(n)), dim3(kBlock), 0, s, keys, n, fine_shift,
+                     flag_tmp, cell_key, cell_start);
   SJ_HIP(hipGetLastError());
 }
 

@@ -7,8 +7,15 @@ namespace sj {
 
 constexpr int kKeyMaxDims = 16;  // most dimensions one linearised cell key covers
 
-// Cell key of a point: sum over r < k of c_r * mult[r], with
+constexpr int kFineMaxDims = 8;
+
+// Sort key of a point: (cell key << fine_bits) | fine key.
+// Cell key: sum over r < k of c_r * mult[r], with
 // c_r = clamp(floor(((double)x[dim[r]] - org[r]) / w), 0, cmax[r]).
+// Fine key: Morton interleave of fb-bit coordinates of the first fm
+// reordered dimensions over their bounding box, so that points of a cell
+// are laid out along a space-filling curve (consecutive positions are near
+// each other).
 struct KeyParams {
   uint32_t k;
   uint32_t dim[kKeyMaxDims];
@@ -16,6 +23,9 @@ struct KeyParams {
   uint64_t mult[kKeyMaxDims];
   uint64_t cmax[kKeyMaxDims];
   double w;
+  uint32_t fm, fb;                 // fine dimensions and bits per dimension
+  uint32_t fdim[kFineMaxDims];
+  double forg[kFineMaxDims], fscale[kFineMaxDims];
 };
 
 // Decoding and neighbour search over the cell-key table.
@@ -37,8 +47,10 @@ void launch_cellkey(const float *P, uint64_t n, uint32_t d, const KeyParams &kp,
 void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const uint32_t *perm,
                    const uint32_t *sorted_ids, float *X, uint32_t *orig_id, uint32_t *pos_of,
                    hipStream_t s);
-void launch_compact(const uint64_t *keys, uint64_t n, uint32_t *flag_tmp, uint32_t *d_ncell,
-                    uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp, hipStream_t s);
+// Non-empty cells of sorted keys (cell part = key >> fine_shift).
+void launch_compact(const uint64_t *keys, uint64_t n, uint32_t fine_shift, uint32_t *flag_tmp,
+                    uint32_t *d_ncell, uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp,
+                    hipStream_t s);
 void launch_neighbors(int pass, const uint64_t *cell_key, const uint32_t *cell_start,
                       uint64_t ncell, const NbrParams &np, uint32_t *nbr_count, uint64_t *cand_sum,
                       const uint32_t *nbr_off, uint32_t *nbr_cell, hipStream_t s);

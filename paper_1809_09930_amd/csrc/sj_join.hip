@@ -12,8 +12,9 @@
 // added (round-to-nearest addition of a non-negative term never decreases
 // the sum), so once every lane of a query group has a partial sum above the
 // reject threshold `hi`, the rest of that candidate is skipped for the group.
-// The test is wave-uniform: it runs after the first 8 dimensions and then
-// every 4.
+// The test is wave-uniform: it runs after the first 4 dimensions and then
+// every 2.  Points inside a cell are ordered along a Morton curve, so the 64
+// queries of a group are neighbours and their partial sums rise together.
 //
 // Exactness.  `hi` and `lo` bound the FP32 rounding error of the sum against
 // the canonical FP64 predicate: s > hi proves rejection, s <= lo proves
@@ -86,8 +87,8 @@ __device__ __forceinline__ void eval_candidate(
     float lo, float hi, double eps2, bool symmetric, bool shortc,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
-  constexpr int kFirst = DP < 8 ? DP : 8;
-  constexpr int kStep = 4;
+  constexpr int kFirst = DP < 4 ? DP : 4;
+  constexpr int kStep = 2;
   const float *__restrict__ crow = X + (uint64_t)c * DP;
   float s[RQ];
 #pragma unroll

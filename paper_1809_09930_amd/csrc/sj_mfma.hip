@@ -274,15 +274,42 @@ __device__ __forceinline__ float min16(const float16v &v) {
   return __builtin_fminf(a, e);
 }
 
+// Walks the 32-row candidate blocks of a work unit, run by run.
+struct BlockIter {
+  const uint2 *runs;
+  uint32_t r, r_last, c, ce, c_end_last;
+  __device__ __forceinline__ void init(const WorkUnit &wu, const uint2 *rs) {
+    runs = rs;
+    r = wu.run_first;
+    r_last = wu.run_last;
+    c_end_last = wu.c_end;
+    c = wu.c_begin;
+    ce = (r == r_last) ? c_end_last : runs[r].y;
+    normalise();
+  }
+  __device__ __forceinline__ bool valid() const { return c < ce; }
+  // move past exhausted runs; leaves c >= ce only when all runs are done
+  __device__ __forceinline__ void normalise() {
+    while (c >= ce && r < r_last) {
+      ++r;
+      c = runs[r].x;
+      ce = (r == r_last) ? c_end_last : runs[r].y;
+    }
+  }
+  __device__ __forceinline__ void advance() {
+    c += 32;
+    normalise();
+  }
+};
+
 template <int KP, int FMT, int QB>
 __global__ __launch_bounds__(kBlock) void k_join_mfma(
     const typename Fmt<FMT>::V8 *__restrict__ XA, const typename Fmt<FMT>::V8 *__restrict__ XB,
     const float *__restrict__ thi, const float *__restrict__ tlo, const float *__restrict__ X,
-    const uint32_t *__restrict__ orig_id, const uint16_t *__restrict__ inv_perm,
-    const WorkUnit *__restrict__ wus, uint64_t n_wu, const uint2 *__restrict__ runs,
-    const uint32_t *__restrict__ qlist, uint32_t d, uint32_t dp, double eps2, int symmetric,
-    uint64_t *__restrict__ out, uint64_t capacity, unsigned long long *__restrict__ cursor,
-    unsigned long long *__restrict__ rechecks) {
+    const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,
+    const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, uint32_t dp,
+    double eps2, int symmetric, uint64_t *__restrict__ out, uint64_t capacity,
+    unsigned long long *__restrict__ cursor, unsigned long long *__restrict__ rechecks) {
   typedef typename Fmt<FMT>::V8 V8;
   constexpr int KS = KP / 16;   // MFMA K steps
   constexpr int RV = KP / 8;    // 8-element vectors per row
@@ -294,9 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
   const uint32_t l = lane_id();
   const uint32_t half = l >> 5, col = l & 31;
 
-  // query columns: B operands, thresholds, positions
+  // query columns: B operands, both thresholds, positions
   V8 B[QB][KS];
-  float th[QB];
+  float th[QB], tl[QB];
   uint32_t qpos[QB];
 #pragma unroll
   for (int j = 0; j < QB; ++j) {
@@ -305,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
     const uint32_t p = live ? (qlist ? qlist[slot] : slot) : 0u;
     qpos[j] = live ? p : 0xffffffffu;
     th[j] = live ? thi[p] : -__builtin_inff();
+    tl[j] = live ? tlo[p] : -__builtin_inff();
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
@@ -313,39 +341,49 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
   uint64_t n_recheck = 0;
   const bool sym = symmetric != 0;
 
-  for (uint32_t r = wu.run_first; r <= wu.run_last; ++r) {
-    const uint2 run = runs[r];
-    const uint32_t cb = (r == wu.run_first) ? wu.c_begin : run.x;
-    const uint32_t ce = (r == wu.run_last) ? wu.c_end : run.y;
-    for (uint32_t c = cb; c < ce; c += 32) {
-      // candidate row of this lane's A operand; rows past the run's end (at
-      // most 31, inside the padded arrays) are dropped in the hit path
-      const uint32_t row_pos = c + col;
-      V8 A[KS];
+  BlockIter it;
+  it.init(wu, runs);
+  if (!it.valid()) return;
+  // candidate operands of the current block; the next block's are fetched
+  // before the current block's MFMAs so their latency overlaps the math.
+  // Rows past the end of the run (at most 31, inside the padded arrays)
+  // are dropped in the hit path.
+  V8 A[KS];
+  uint32_t c = it.c, ce = it.ce;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) A[ks] = XA[(uint64_t)row_pos * RV + ks * 2 + half];
-      float16v acc[QB];
+  for (int ks = 0; ks < KS; ++ks) A[ks] = XA[(uint64_t)(c + col) * RV + ks * 2 + half];
+  it.advance();
+  for (;;) {
+    const bool more = it.valid();
+    V8 An[KS];
+    const uint32_t cn = it.c, cen = it.ce;
+    if (more) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) An[ks] = XA[(uint64_t)(cn + col) * RV + ks * 2 + half];
+      it.advance();
+    }
+    float16v acc[QB];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      float16v z = {};
+      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
+#pragma unroll
+      for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
+    }
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < QB; ++j) any = any || (min16(acc[j]) <= th[j]);
+    if (ballot(any)) {
+      // some pair of this block may be a result: element by element
 #pragma unroll
       for (int j = 0; j < QB; ++j) {
-        float16v z = {};
-        acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
-#pragma unroll
-        for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < QB; ++j) {
-        if (ballot(min16(acc[j]) <= th[j]) == 0) continue;
-        // some pair of this tile may be a result: check element by element
-        float tl = 0.0f;
-        if (qpos[j] != 0xffffffffu) tl = tlo[qpos[j]];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
           const bool h = acc[j][e] <= th[j];
           if (ballot(h) == 0) continue;
-          const uint32_t row = 8 * (e / 4) + 4 * half + (e % 4);
-          const uint32_t cp = c + row;
+          const uint32_t cp = c + 8 * (e / 4) + 4 * half + (e % 4);
           const bool ok = h && cp < ce && (!sym || qpos[j] <= cp);
-          bool acc_ok = ok && acc[j][e] <= tl;
+          bool acc_ok = ok && acc[j][e] <= tl[j];
           const bool band = ok && !acc_ok;
           const uint64_t bm = ballot(band);
           if (bm) {
@@ -354,23 +392,38 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
           }
           const uint64_t am = ballot(acc_ok);
           if (am == 0) continue;
+          // keys hold cell-order positions; they are mapped to caller
+          // indices before the result is sorted
           const bool two = acc_ok && sym && qpos[j] != cp;
           const uint64_t m2 = ballot(two);
           const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
           if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
           const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
           if (acc_ok) {
-            const uint32_t qi = orig_id[qpos[j]], ci = orig_id[cp];
-            st.buf[off] = ((uint64_t)qi << 32) | ci;
-            if (two) st.buf[off + 1] = ((uint64_t)ci << 32) | qi;
+            st.buf[off] = ((uint64_t)qpos[j] << 32) | cp;
+            if (two) st.buf[off + 1] = ((uint64_t)cp << 32) | qpos[j];
           }
           st.cnt += total;
         }
       }
     }
+    if (!more) break;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) A[ks] = An[ks];
+    c = cn;
+    ce = cen;
   }
   flush(st, out, capacity, cursor);
   if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+// Keys of cell-order positions (p << 32 | q) -> keys of caller indices.
+__global__ __launch_bounds__(kBlock) void k_pos_to_id(uint64_t *__restrict__ keys, uint64_t count,
+                                                      const uint32_t *__restrict__ orig_id) {
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= count) return;
+  const uint64_t k = keys[e];
+  keys[e] = ((uint64_t)orig_id[(uint32_t)(k >> 32)] << 32) | orig_id[(uint32_t)k];
 }
 
 template <int KP, int FMT>
@@ -380,9 +433,9 @@ void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   typedef typename Fmt<FMT>::V8 V8;
   constexpr int QB = KP <= 64 ? 4 : 2;
   hipLaunchKernelGGL((k_join_mfma<KP, FMT, QB>), dim3(grid), dim3(kBlock), 0, s,
-                     (const V8 *)a.XA, (const V8 *)a.XB, a.thi, a.tlo, a.X, a.orig_id, a.inv_perm,
-                     a.wu, a.n_wu, a.runs, a.qlist, a.d, a.dp, a.eps2, a.symmetric, a.out,
-                     a.capacity, a.cursor, a.rechecks);
+                     (const V8 *)a.XA, (const V8 *)a.XB, a.thi, a.tlo, a.X, a.inv_perm, a.wu,
+                     a.n_wu, a.runs, a.qlist, a.d, a.dp, a.eps2, a.symmetric, a.out, a.capacity,
+                     a.cursor, a.rechecks);
   SJ_HIP(hipGetLastError());
 }
 
@@ -443,6 +496,13 @@ void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, co
   if (!grid) return;
   hipLaunchKernelGGL(k_mfma_thresholds, dim3(grid), dim3(kBlock), 0, s, n, n_pad, band, norm2,
                      dist_c, maxima, thi, tlo);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_pos_to_id, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, keys, count, orig_id);
   SJ_HIP(hipGetLastError());
 }
 

@@ -45,6 +45,9 @@ void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint3
 void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, const double *norm2,
                             const double *dist_c, const unsigned long long *maxima, float *thi,
                             float *tlo, hipStream_t s);
+// Emits keys of cell-order positions (launch_pos_to_id maps them to
+// caller indices in place).
 void launch_join_mfma(const MfmaLaunch &a, hipStream_t s);
+void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, hipStream_t s);
 
 }  // namespace sj

@@ -173,13 +173,20 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n, int shift,
     const uint32_t *__restrict__ offs, uint32_t nblocks) {
   __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
+  __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];
+  __shared__ uint32_t dbase[kRadixBins];   // first slot of each digit in the tile
+  __shared__ uint32_t gbase[kRadixBins];   // first global slot of each digit
+  __shared__ uint64_t tkey[kRsTile];
+  __shared__ uint32_t tval[kVals ? kRsTile : 1];
   const int w = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock)
     (&cnt[0][0])[i] = 0;
   __syncthreads();
 
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile + (uint64_t)w * (kRsTile / kWavesPerBlock);
+  // 1. rank every key among equal digits of its wave, in input order
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kWavesPerBlock);
   uint64_t key[kRsRounds];
   uint32_t val[kRsRounds];
   uint32_t rank[kRsRounds];
@@ -208,26 +215,44 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // digit-major: workgroup-local offset of each wave's share of each digit
-  __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];
-  for (int dg = threadIdx.x; dg < kRadixBins; dg += kBlock) {
-    uint32_t s = 0;
+  // 2. per digit: offsets of the waves' shares, the tile-local start and the
+  //    global start (one digit per thread)
+  {
+    const uint32_t dg = threadIdx.x;
+    uint32_t sum = 0;
 #pragma unroll
     for (int i = 0; i < kWavesPerBlock; ++i) {
-      woff[i][dg] = s;
-      s += cnt[i][dg];
+      woff[i][dg] = sum;
+      sum += cnt[i][dg];
     }
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(sum, &total);
+    dbase[dg] = ex;
+    gbase[dg] = offs[(uint64_t)dg * nblocks + blockIdx.x];
   }
   __syncthreads();
+  // 3. place the keys digit-major in LDS
 #pragma unroll
   for (int r = 0; r < kRsRounds; ++r) {
     const uint64_t idx = base + (uint64_t)r * kWave + l;
     if (idx < n) {
       const uint32_t dg = (uint32_t)(key[r] >> shift) & (kRadixBins - 1);
-      const uint64_t pos = (uint64_t)offs[(uint64_t)dg * nblocks + blockIdx.x] + woff[w][dg] + rank[r];
-      kout[pos] = key[r];
-      if (kVals) vout[pos] = val[r];
+      const uint32_t lp = dbase[dg] + woff[w][dg] + rank[r];
+      tkey[lp] = key[r];
+      if (kVals) tval[lp] = val[r];
     }
+  }
+  __syncthreads();
+  // 4. write the tile out in digit order: consecutive threads write
+  //    consecutive slots of each digit's run
+  const uint32_t valid_keys =
+      (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
+  for (uint32_t i = threadIdx.x; i < valid_keys; i += kBlock) {
+    const uint64_t k = tkey[i];
+    const uint32_t dg = (uint32_t)(k >> shift) & (kRadixBins - 1);
+    const uint64_t pos = (uint64_t)gbase[dg] + (i - dbase[dg]);
+    kout[pos] = k;
+    if (kVals) vout[pos] = tval[i];
   }
 }
 
