@@ -13,9 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "sj_index.hpp"
-#include "sj_internal.hpp"
-#include "sj_mfma.hpp"
+#include "sj_runtime.hpp"
 
 namespace sj {
 
@@ -31,172 +29,12 @@ void check_hip(hipError_t e, const char *what) {
   fail(code, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-namespace {
-
-// Device allocation owned by a handle.
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  DevBuf() = default;
-  DevBuf(const DevBuf &) = delete;
-  DevBuf &operator=(const DevBuf &) = delete;
-  ~DevBuf() { reset(); }
-  void reset() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  void alloc(size_t b) {
-    reset();
-    if (b == 0) b = 256;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
-    }
-    bytes = b;
-  }
-  void ensure(size_t b) {
-    if (b > bytes || !p) alloc(b);
-  }
-  template <typename T>
-  T *as() const {
-    return static_cast<T *>(p);
-  }
-};
-
-struct PinnedBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  PinnedBuf() = default;
-  PinnedBuf(const PinnedBuf &) = delete;
-  PinnedBuf &operator=(const PinnedBuf &) = delete;
-  PinnedBuf(PinnedBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
-  ~PinnedBuf() {
-    if (p) (void)hipHostFree(p);
-  }
-  void alloc(size_t b) {
-    if (b == 0) b = 64;
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      fail(SJ_ERR_OUT_OF_MEMORY, "pinned host allocation of " + std::to_string(b) + " bytes failed");
-    }
-    bytes = b;
-  }
-};
-
-struct Event {
-  hipEvent_t e = nullptr;
-  Event() { SJ_HIP(hipEventCreate(&e)); }
-  ~Event() {
-    if (e) (void)hipEventDestroy(e);
-  }
-  Event(const Event &) = delete;
-  Event &operator=(const Event &) = delete;
-};
-
-float elapsed_ms(const Event &a, const Event &b) {
-  float ms = 0.0f;
-  SJ_HIP(hipEventElapsedTime(&ms, a.e, b.e));
-  return ms;
-}
-
-uint32_t bits_for(uint64_t v) {  // bits needed to represent v
-  uint32_t b = 0;
-  while (v) { ++b; v >>= 1; }
-  return b;
-}
-
-std::vector<int> digit_shifts(uint32_t lo_bits, uint32_t hi_bits) {
-  // 8-bit digits over bits [0, lo_bits) and [32, 32 + hi_bits)
-  std::vector<int> s;
-  for (uint32_t b = 0; b < lo_bits; b += 8) s.push_back((int)b);
-  for (uint32_t b = 0; b < hi_bits; b += 8) s.push_back(32 + (int)b);
-  return s;
-}
-
-bool is_device_pointer(const void *ptr) {
-  if (!ptr) return false;
-  hipPointerAttribute_t attr;
-  hipError_t e = hipPointerGetAttributes(&attr, ptr);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-#if HIP_VERSION_MAJOR >= 6
-  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-#else
-  return attr.memoryType == hipMemoryTypeDevice;
-#endif
-}
-
-// Grid geometry for one choice of k.
-struct Geometry {
-  uint32_t k = 0;
-  KeyParams kp{};
-  NbrParams np{};
-  uint32_t key_bits = 0;   // bits of the sort key
-  uint32_t fine_bits = 0;  // low bits of the sort key below the cell key
-};
-
-double gamma_n(double m, double u) { return m * u / (1.0 - m * u); }
-
-}  // namespace
 }  // namespace sj
 
 using namespace sj;
 
-struct sj_index {
-  int device = 0;
-  uint64_t n = 0;
-  uint32_t d = 0, dp = 0, k = 0;
-  double eps = 0.0, eps2 = 0.0;
-  sj_options opt{};
-  std::vector<uint32_t> perm;
-  std::vector<uint16_t> inv_perm;
-  std::vector<double> dmin, dmax;
-  float lo32 = 0.0f, hi32 = 0.0f;
-
-  // index
-  DevBuf X, orig_id, pos_of, perm_d, inv_perm_d;
-  DevBuf cell_key, cell_start;
-  uint64_t ncell = 0;
-  DevBuf nbr_off, nbr_cell;
-  uint64_t n_nbr = 0;
-  DevBuf run_off_sym, runs_sym, run_off_full, runs_full;
-  uint64_t n_runs_sym = 0, n_runs_full = 0;
-  DevBuf wu;
-  uint64_t n_wu = 0;
-  uint32_t tq = 256, tc = 16384;
-  uint64_t candidates = 0, evaluated_sym = 0;
-  DevBuf counters;  // [0] cursor, [1] rechecks
-
-  // matrix-core path
-  uint32_t prec = SJ_PREC_FP32;  // precision actually used
-  int fmt = 0;
-  uint32_t kp = 0;
-  uint64_t n_pad = 0;
-  DevBuf XA, XB, thi, tlo;
-  DevBuf wu_m;
-  uint64_t n_wu_m = 0, evaluated_sym_m = 0;
-  uint32_t tq_m = 128, tc_m = 4096;
-
-  // results
-  bool ran = false;
-  uint64_t total = 0;
-  DevBuf pairs;                     // sorted keys when device-resident
-  std::vector<PinnedBuf> host_res;  // sorted keys per batch when host-resident
-  std::vector<uint64_t> host_cnt;
-  bool on_host = false;
-  DevBuf fetch_stage;
-
-  sj_info info{};
-};
 
 namespace sj {
-namespace {
 
 constexpr double kWidthSlack = 1.0 + 1.0 / (1 << 20);  // cell side = eps * (1 + 2^-20)
 
@@ -617,6 +455,25 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   ix.info.ms_build = elapsed_ms(ev0, ev1);
 }
 
+MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist, int sym) {
+  MfmaView v{};
+  v.XA = ix.XA.p;
+  v.XB = ix.XB.p;
+  v.thi = ix.thi.as<float>();
+  v.tlo = ix.tlo.as<float>();
+  v.X = ix.X.as<float>();
+  v.inv_perm = ix.inv_perm_d.as<uint16_t>();
+  v.runs = runs;
+  v.qlist = qlist;
+  v.d = ix.d;
+  v.dp = ix.dp;
+  v.eps2 = ix.eps2;
+  v.symmetric = sym;
+  v.pshift = 32;
+  v.key_hi = 0;
+  return v;
+}
+
 // One launch of the distance kernel over a set of work units.
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
                  const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
@@ -648,21 +505,9 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     MfmaLaunch m{};
     m.fmt = ix.fmt;
     m.kp = ix.kp;
-    m.XA = ix.XA.p;
-    m.XB = ix.XB.p;
-    m.thi = ix.thi.as<float>();
-    m.tlo = ix.tlo.as<float>();
-    m.X = a.X;
-    m.orig_id = a.orig_id;
-    m.inv_perm = a.inv_perm;
+    m.view = mfma_view(ix, a.runs, a.qlist, sym);
     m.wu = a.wu;
     m.n_wu = a.n_wu;
-    m.runs = a.runs;
-    m.qlist = a.qlist;
-    m.d = a.d;
-    m.dp = a.dp;
-    m.eps2 = a.eps2;
-    m.symmetric = sym;
     m.out = out;
     m.capacity = cap;
     m.cursor = a.cursor;
@@ -950,25 +795,28 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   *n_written = cnt;
 }
 
-template <typename F>
-int guarded(F &&f) {
-  try {
-    g_last_error.clear();
-    f();
-    return SJ_OK;
-  } catch (const Error &e) {
-    g_last_error = e.msg;
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    g_last_error = "host allocation failed";
-    return SJ_ERR_OUT_OF_MEMORY;
-  } catch (...) {
-    g_last_error = "unexpected internal error";
-    return SJ_ERR_DEVICE;
+sj_options checked_options(const float *points, uint64_t n, uint32_t d, double epsilon,
+                           const sj_options *opts) {
+  if (d == 0 || d > SJ_MAX_DIM)
+    fail(SJ_ERR_INVALID_ARG, "d must be in [1, " + std::to_string(SJ_MAX_DIM) + "]");
+  if (n > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "n must be below 2^32");
+  if (n > 0 && !points) fail(SJ_ERR_INVALID_ARG, "points is NULL");
+  if (!std::isfinite(epsilon) || !(epsilon > 0.0))
+    fail(SJ_ERR_INVALID_ARG, "epsilon must be finite and > 0");
+  if (!std::isfinite(epsilon * epsilon)) fail(SJ_ERR_INVALID_ARG, "epsilon^2 overflows");
+  sj_options o;
+  fill_defaults(&o);
+  if (opts) {
+    if (opts->struct_size < offsetof(sj_options, reserved0) || opts->struct_size > sizeof(o))
+      fail(SJ_ERR_INVALID_ARG, "sj_options.struct_size is not a known size");
+    std::memcpy(&o, opts, opts->struct_size);
+    o.struct_size = sizeof(o);
   }
+  if (o.precision > SJ_PREC_BF16) fail(SJ_ERR_INVALID_ARG, "unknown precision");
+  if (o.k < 0) fail(SJ_ERR_INVALID_ARG, "k must be >= 0");
+  return o;
 }
 
-}  // namespace
 }  // namespace sj
 
 extern "C" {
@@ -981,24 +829,8 @@ int selfjoin_build_index(const float *points, uint64_t n, uint32_t d, double eps
                          const sj_options *opts, void *stream, sj_index **out) {
   return sj::guarded([&] {
     if (!out) fail(SJ_ERR_INVALID_ARG, "out is NULL");
-    if (d == 0 || d > SJ_MAX_DIM)
-      fail(SJ_ERR_INVALID_ARG, "d must be in [1, " + std::to_string(SJ_MAX_DIM) + "]");
-    if (n > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "n must be below 2^32");
-    if (n > 0 && !points) fail(SJ_ERR_INVALID_ARG, "points is NULL");
-    if (!std::isfinite(epsilon) || !(epsilon > 0.0))
-      fail(SJ_ERR_INVALID_ARG, "epsilon must be finite and > 0");
+    const sj_options o = sj::checked_options(points, n, d, epsilon, opts);
     const double eps2 = epsilon * epsilon;
-    if (!std::isfinite(eps2)) fail(SJ_ERR_INVALID_ARG, "epsilon^2 overflows");
-    sj_options o;
-    sj::fill_defaults(&o);
-    if (opts) {
-      if (opts->struct_size < offsetof(sj_options, reserved0) || opts->struct_size > sizeof(o))
-        fail(SJ_ERR_INVALID_ARG, "sj_options.struct_size is not a known size");
-      std::memcpy(&o, opts, opts->struct_size);
-      o.struct_size = sizeof(o);
-    }
-    if (o.precision > SJ_PREC_BF16) fail(SJ_ERR_INVALID_ARG, "unknown precision");
-    if (o.k < 0) fail(SJ_ERR_INVALID_ARG, "k must be >= 0");
     std::unique_ptr<sj_index> ix(new sj_index());
     SJ_HIP(hipGetDevice(&ix->device));
     ix->n = n;

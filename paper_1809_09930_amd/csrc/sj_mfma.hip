@@ -302,22 +302,19 @@ struct BlockIter {
   }
 };
 
+// One work unit of the matrix-core filter: QB query column blocks against
+// the candidate blocks of the unit's runs.  Accepted pairs are staged as
+// keys key_hi | pos_q << pshift | pos_c.
 template <int KP, int FMT, int QB>
-__global__ __launch_bounds__(kBlock) void k_join_mfma(
-    const typename Fmt<FMT>::V8 *__restrict__ XA, const typename Fmt<FMT>::V8 *__restrict__ XB,
-    const float *__restrict__ thi, const float *__restrict__ tlo, const float *__restrict__ X,
-    const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,
-    const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, uint32_t dp,
-    double eps2, int symmetric, uint64_t *__restrict__ out, uint64_t capacity,
-    unsigned long long *__restrict__ cursor, unsigned long long *__restrict__ rechecks) {
+__device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu, Stage &st,
+                                          uint64_t *__restrict__ out, uint64_t capacity,
+                                          unsigned long long *__restrict__ cursor,
+                                          uint64_t &n_recheck) {
   typedef typename Fmt<FMT>::V8 V8;
   constexpr int KS = KP / 16;   // MFMA K steps
   constexpr int RV = KP / 8;    // 8-element vectors per row
-  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  const uint32_t w = uniform_u32(threadIdx.x / kWave);
-  const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
-  if (u >= n_wu) return;
-  const WorkUnit wu = wus[u];
+  const V8 *__restrict__ XA = static_cast<const V8 *>(v.XA);
+  const V8 *__restrict__ XB = static_cast<const V8 *>(v.XB);
   const uint32_t l = lane_id();
   const uint32_t half = l >> 5, col = l & 31;
 
@@ -329,20 +326,17 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
   for (int j = 0; j < QB; ++j) {
     const uint32_t slot = wu.q0 + (uint32_t)j * 32 + col;
     const bool live = slot < wu.q1;
-    const uint32_t p = live ? (qlist ? qlist[slot] : slot) : 0u;
+    const uint32_t p = live ? (v.qlist ? v.qlist[slot] : slot) : 0u;
     qpos[j] = live ? p : 0xffffffffu;
-    th[j] = live ? thi[p] : -__builtin_inff();
-    tl[j] = live ? tlo[p] : -__builtin_inff();
+    th[j] = live ? v.thi[p] : -__builtin_inff();
+    tl[j] = live ? v.tlo[p] : -__builtin_inff();
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
-
-  Stage st{&stage_mem[w][0], 0u};
-  uint64_t n_recheck = 0;
-  const bool sym = symmetric != 0;
+  const bool sym = v.symmetric != 0;
 
   BlockIter it;
-  it.init(wu, runs);
+  it.init(wu, v.runs);
   if (!it.valid()) return;
   // candidate operands of the current block; the next block's are fetched
   // before the current block's MFMAs so their latency overlaps the math.
@@ -387,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
           const bool band = ok && !acc_ok;
           const uint64_t bm = ballot(band);
           if (bm) {
-            if (band) acc_ok = canonical_within_m(X, qpos[j], cp, inv_perm, d, dp, eps2);
+            if (band) acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
             n_recheck += (uint64_t)__builtin_popcountll(bm);
           }
           const uint64_t am = ballot(acc_ok);
@@ -400,8 +394,8 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
           if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
           const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
           if (acc_ok) {
-            st.buf[off] = ((uint64_t)qpos[j] << 32) | cp;
-            if (two) st.buf[off + 1] = ((uint64_t)cp << 32) | qpos[j];
+            st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+            if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
           }
           st.cnt += total;
         }
@@ -413,8 +407,108 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(
     c = cn;
     ce = cen;
   }
+}
+
+template <int KP, int FMT, int QB>
+__global__ __launch_bounds__(kBlock) void k_join_mfma(MfmaView v, const WorkUnit *__restrict__ wus,
+                                                      uint64_t n_wu, uint64_t *__restrict__ out,
+                                                      uint64_t capacity,
+                                                      unsigned long long *__restrict__ cursor,
+                                                      unsigned long long *__restrict__ rechecks) {
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
+  if (u >= n_wu) return;  // whole wave leaves; no workgroup barrier follows
+  const WorkUnit wu = wus[u];
+  Stage st{&stage_mem[w][0], 0u};
+  uint64_t n_recheck = 0;
+  mfma_unit<KP, FMT, QB>(v, wu, st, out, capacity, cursor, n_recheck);
   flush(st, out, capacity, cursor);
-  if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+  if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+// Many independent joins in one persistent launch.  Every wave takes
+// `grab` work units at a time from a global queue shared by all jobs and
+// runs each with the instantiation of its job's K padding and format.  A
+// wave leaves once the queue is exhausted, so the grid drains by itself.
+template <int KP, int FMT>
+__device__ __forceinline__ void batched_dispatch(const MfmaView &v, const WorkUnit &wu, Stage &st,
+                                                 uint64_t *__restrict__ out, uint64_t capacity,
+                                                 unsigned long long *__restrict__ cursor,
+                                                 uint64_t &n_recheck) {
+  mfma_unit<KP, FMT, (KP <= 64 ? 4 : 2)>(v, wu, st, out, capacity, cursor, n_recheck);
+}
+
+__global__ __launch_bounds__(kBlock) void k_join_batched(
+    const BatchJob *__restrict__ jobs, const WorkUnit *__restrict__ wus, uint64_t n_wu,
+    uint32_t grab, unsigned int *__restrict__ queue, uint64_t *__restrict__ out,
+    const unsigned long long *__restrict__ capacity_p, unsigned long long *__restrict__ cursor,
+    unsigned long long *__restrict__ rechecks) {
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  Stage st{&stage_mem[w][0], 0u};
+  uint64_t n_recheck = 0;
+  const uint64_t capacity = *capacity_p;
+  for (;;) {
+    unsigned int u0 = 0;
+    if (lane_id() == 0) u0 = atomicAdd(queue, grab);
+    u0 = uniform_u32(__shfl(u0, 0));
+    if ((uint64_t)u0 >= n_wu) break;
+    const uint64_t u1 = (uint64_t)u0 + grab < n_wu ? (uint64_t)u0 + grab : n_wu;
+    for (uint64_t u = u0; u < u1; ++u) {
+      const WorkUnit wu = wus[u];
+      const uint32_t job = wu.pad;
+      MfmaView v = jobs[job].view;
+      v.key_hi = (uint64_t)job << 40;
+      switch (jobs[job].variant) {
+        case 0: batched_dispatch<16, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 1: batched_dispatch<32, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 2: batched_dispatch<48, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 3: batched_dispatch<64, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 4: batched_dispatch<80, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 5: batched_dispatch<16, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 6: batched_dispatch<32, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 7: batched_dispatch<48, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 8: batched_dispatch<64, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 9: batched_dispatch<80, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        default: break;
+      }
+    }
+  }
+  flush(st, out, capacity, cursor);
+  if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+// Batched keys job << 40 | pos_q << 20 | pos_c -> job << 40 | id_q << 20 | id_c,
+// for the first min(*count, capacity) keys.
+__global__ __launch_bounds__(kBlock) void k_pos_to_id_batched(
+    uint64_t *__restrict__ keys, const unsigned long long *__restrict__ count,
+    const unsigned long long *__restrict__ capacity_p, const BatchJob *__restrict__ jobs) {
+  const unsigned long long cap = *capacity_p;
+  const uint64_t total = *count < cap ? *count : cap;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t k = keys[e];
+    const uint32_t job = (uint32_t)(k >> 40);
+    const uint32_t *oid = jobs[job].orig_id;
+    const uint32_t q = (uint32_t)(k >> 20) & 0xfffffu, c = (uint32_t)k & 0xfffffu;
+    keys[e] = ((uint64_t)job << 40) | ((uint64_t)oid[q] << 20) | oid[c];
+  }
+}
+
+// First and last+1 slot of every job in the sorted batched keys.
+__global__ __launch_bounds__(kBlock) void k_job_bounds(
+    const uint64_t *__restrict__ keys, const unsigned long long *__restrict__ count,
+    const unsigned long long *__restrict__ capacity_p, unsigned long long *__restrict__ first,
+    unsigned long long *__restrict__ last) {
+  const unsigned long long cap = *capacity_p;
+  const uint64_t total = *count < cap ? *count : cap;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t job = (uint32_t)(keys[e] >> 40);
+    if (e == 0 || (uint32_t)(keys[e - 1] >> 40) != job) first[job] = e;
+    if (e + 1 == total || (uint32_t)(keys[e + 1] >> 40) != job) last[job] = e + 1;
+  }
 }
 
 // Keys of cell-order positions (p << 32 | q) -> keys of caller indices.
@@ -430,12 +524,10 @@ template <int KP, int FMT>
 void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
   if (!grid) return;
-  typedef typename Fmt<FMT>::V8 V8;
   constexpr int QB = KP <= 64 ? 4 : 2;
-  hipLaunchKernelGGL((k_join_mfma<KP, FMT, QB>), dim3(grid), dim3(kBlock), 0, s,
-                     (const V8 *)a.XA, (const V8 *)a.XB, a.thi, a.tlo, a.X, a.inv_perm, a.wu,
-                     a.n_wu, a.runs, a.qlist, a.d, a.dp, a.eps2, a.symmetric, a.out, a.capacity,
-                     a.cursor, a.rechecks);
+  MfmaView v = a.view;
+  hipLaunchKernelGGL((k_join_mfma<KP, FMT, QB>), dim3(grid), dim3(kBlock), 0, s, v, a.wu, a.n_wu,
+                     a.out, a.capacity, a.cursor, a.rechecks);
   SJ_HIP(hipGetLastError());
 }
 
@@ -503,6 +595,53 @@ void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, h
   if (!count) return;
   hipLaunchKernelGGL(k_pos_to_id, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                      s, keys, count, orig_id);
+  SJ_HIP(hipGetLastError());
+}
+
+int batched_variant(uint32_t kp, int fmt) {
+  int base = fmt == kFmtF16 ? 0 : 5;
+  switch (kp) {
+    case 16: return base + 0;
+    case 32: return base + 1;
+    case 48: return base + 2;
+    case 64: return base + 3;
+    case 80: return base + 4;
+    default: return -1;
+  }
+}
+
+int batched_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_join_batched, kBlock, 0) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    blocks = 2;
+  }
+  return blocks > 0 ? blocks : 1;
+}
+
+void launch_join_batched(const BatchJob *jobs, const WorkUnit *wus, uint64_t n_wu, uint32_t grab,
+                         unsigned int *queue, uint64_t *out, const unsigned long long *capacity,
+                         unsigned long long *cursor, unsigned long long *rechecks, uint32_t grid,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_join_batched, dim3(grid), dim3(kBlock), 0, s, jobs, wus, n_wu, grab, queue,
+                     out, capacity, cursor, rechecks);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_pos_to_id_batched(uint64_t *keys, const unsigned long long *count,
+                              const unsigned long long *capacity, const BatchJob *jobs,
+                              uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_pos_to_id_batched, dim3(grid), dim3(kBlock), 0, s, keys, count, capacity,
+                     jobs);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_job_bounds(const uint64_t *keys, const unsigned long long *count,
+                       const unsigned long long *capacity, unsigned long long *first,
+                       unsigned long long *last, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_job_bounds, dim3(grid), dim3(kBlock), 0, s, keys, count, capacity, first,
+                     last);
   SJ_HIP(hipGetLastError());
 }
 

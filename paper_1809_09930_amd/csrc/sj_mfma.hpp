@@ -16,24 +16,38 @@ struct MfmaBand {
   double s_hi, s_lo; // eps2/(1-g64), eps2/(1+g64)
 };
 
-struct MfmaLaunch {
-  int fmt;
-  uint32_t kp;
+// Everything a work unit of the matrix-core filter reads.
+struct MfmaView {
   const void *XA, *XB;      // [n_pad][kp] 16-bit operands (candidate rows / query columns)
   const float *thi, *tlo;   // per-point thresholds
   const float *X;           // FP32 rows (recheck)
-  const uint32_t *orig_id;
   const uint16_t *inv_perm;
-  const WorkUnit *wu;
-  uint64_t n_wu;
   const uint2 *runs;
-  const uint32_t *qlist;
+  const uint32_t *qlist;    // query positions, or null for contiguous slots
   uint32_t d, dp;
   double eps2;
   int symmetric;
+  uint32_t pshift;          // key = key_hi | pos_q << pshift | pos_c
+  uint64_t key_hi;
+};
+
+struct MfmaLaunch {
+  int fmt;
+  uint32_t kp;
+  MfmaView view;
+  const WorkUnit *wu;
+  uint64_t n_wu;
   uint64_t *out;
   uint64_t capacity;
   unsigned long long *cursor, *rechecks;
+};
+
+// One job of a batched launch.
+struct BatchJob {
+  MfmaView view;
+  const uint32_t *orig_id;
+  int32_t variant;  // instantiation (K padding, format) of the batched kernel
+  uint32_t pad;
 };
 
 int mfma_pieces(int fmt);
@@ -49,5 +63,20 @@ void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, co
 // caller indices in place).
 void launch_join_mfma(const MfmaLaunch &a, hipStream_t s);
 void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, hipStream_t s);
+
+// Batched path: variant index of (kp, fmt), or -1 when kp is not supported
+// (kp <= 80); workgroups per CU the persistent kernel fits.
+int batched_variant(uint32_t kp, int fmt);
+int batched_blocks_per_cu();
+void launch_join_batched(const BatchJob *jobs, const WorkUnit *wus, uint64_t n_wu, uint32_t grab,
+                         unsigned int *queue, uint64_t *out, const unsigned long long *capacity,
+                         unsigned long long *cursor, unsigned long long *rechecks, uint32_t grid,
+                         hipStream_t s);
+void launch_pos_to_id_batched(uint64_t *keys, const unsigned long long *count,
+                              const unsigned long long *capacity, const BatchJob *jobs,
+                              uint32_t grid, hipStream_t s);
+void launch_job_bounds(const uint64_t *keys, const unsigned long long *count,
+                       const unsigned long long *capacity, unsigned long long *first,
+                       unsigned long long *last, uint32_t grid, hipStream_t s);
 
 }  // namespace sj

@@ -1,0 +1,214 @@
+// Host runtime shared by the translation units of libselfjoin: device and
+// pinned buffers, events, the index handle and the build/run helpers.
+#pragma once
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sj_index.hpp"
+#include "sj_internal.hpp"
+#include "sj_mfma.hpp"
+
+namespace sj {
+
+extern thread_local std::string g_last_error;
+
+// Device allocation owned by a handle.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    reset();
+    if (b == 0) b = 256;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+  void ensure(size_t b) {
+    if (b > bytes || !p) alloc(b);
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+struct PinnedBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf &) = delete;
+  PinnedBuf &operator=(const PinnedBuf &) = delete;
+  PinnedBuf(PinnedBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t b) {
+    if (b == 0) b = 64;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(SJ_ERR_OUT_OF_MEMORY, "pinned host allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+  }
+};
+
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() { SJ_HIP(hipEventCreate(&e)); }
+  ~Event() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  Event(const Event &) = delete;
+  Event &operator=(const Event &) = delete;
+};
+
+inline float elapsed_ms(const Event &a, const Event &b) {
+  float ms = 0.0f;
+  SJ_HIP(hipEventElapsedTime(&ms, a.e, b.e));
+  return ms;
+}
+
+inline uint32_t bits_for(uint64_t v) {  // bits needed to represent v
+  uint32_t b = 0;
+  while (v) { ++b; v >>= 1; }
+  return b;
+}
+
+inline std::vector<int> digit_shifts(uint32_t lo_bits, uint32_t hi_bits) {
+  // 8-bit digits over bits [0, lo_bits) and [32, 32 + hi_bits)
+  std::vector<int> s;
+  for (uint32_t b = 0; b < lo_bits; b += 8) s.push_back((int)b);
+  for (uint32_t b = 0; b < hi_bits; b += 8) s.push_back(32 + (int)b);
+  return s;
+}
+
+inline bool is_device_pointer(const void *ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+#if HIP_VERSION_MAJOR >= 6
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+#else
+  return attr.memoryType == hipMemoryTypeDevice;
+#endif
+}
+
+// Grid geometry for one choice of k.
+struct Geometry {
+  uint32_t k = 0;
+  KeyParams kp{};
+  NbrParams np{};
+  uint32_t key_bits = 0;   // bits of the sort key
+  uint32_t fine_bits = 0;  // low bits of the sort key below the cell key
+};
+
+inline double gamma_n(double m, double u) { return m * u / (1.0 - m * u); }
+
+
+}  // namespace sj
+
+// The opaque handle of the C ABI.
+struct sj_index {
+  typedef sj::DevBuf DevBuf;
+  typedef sj::PinnedBuf PinnedBuf;
+  int device = 0;
+  uint64_t n = 0;
+  uint32_t d = 0, dp = 0, k = 0;
+  double eps = 0.0, eps2 = 0.0;
+  sj_options opt{};
+  std::vector<uint32_t> perm;
+  std::vector<uint16_t> inv_perm;
+  std::vector<double> dmin, dmax;
+  float lo32 = 0.0f, hi32 = 0.0f;
+
+  // index
+  DevBuf X, orig_id, pos_of, perm_d, inv_perm_d;
+  DevBuf cell_key, cell_start;
+  uint64_t ncell = 0;
+  DevBuf nbr_off, nbr_cell;
+  uint64_t n_nbr = 0;
+  DevBuf run_off_sym, runs_sym, run_off_full, runs_full;
+  uint64_t n_runs_sym = 0, n_runs_full = 0;
+  DevBuf wu;
+  uint64_t n_wu = 0;
+  uint32_t tq = 256, tc = 16384;
+  uint64_t candidates = 0, evaluated_sym = 0;
+  DevBuf counters;  // [0] cursor, [1] rechecks
+
+  // matrix-core path
+  uint32_t prec = SJ_PREC_FP32;  // precision actually used
+  int fmt = 0;
+  uint32_t kp = 0;
+  uint64_t n_pad = 0;
+  DevBuf XA, XB, thi, tlo;
+  DevBuf wu_m;
+  uint64_t n_wu_m = 0, evaluated_sym_m = 0;
+  uint32_t tq_m = 128, tc_m = 4096;
+
+  // results
+  bool ran = false;
+  uint64_t total = 0;
+  DevBuf pairs;                     // sorted keys when device-resident
+  std::vector<PinnedBuf> host_res;  // sorted keys per batch when host-resident
+  std::vector<uint64_t> host_cnt;
+  bool on_host = false;
+  DevBuf fetch_stage;
+
+  sj_info info{};
+};
+
+
+namespace sj {
+
+void fill_defaults(sj_options *o);
+// Validates arguments and options of an index build (throws Error).
+sj_options checked_options(const float *points, uint64_t n, uint32_t d, double epsilon,
+                           const sj_options *opts);
+void build(sj_index &ix, const float *points, hipStream_t s);
+uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms);
+uint64_t default_budget();
+MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist, int sym);
+
+template <typename F>
+int guarded(F &&f) {
+  try {
+    g_last_error.clear();
+    f();
+    return SJ_OK;
+  } catch (const Error &e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_last_error = "host allocation failed";
+    return SJ_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return SJ_ERR_DEVICE;
+  }
+}
+
+}  // namespace sj
