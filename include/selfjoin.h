@@ -83,7 +83,7 @@ typedef struct sj_options {
     uint32_t precision;     /* enum sj_precision */
     uint64_t batch_pairs;   /* b_s of Section 3.2.2: maximum result pairs held on the device per batch; 0 = automatic (as many as fit) */
     uint32_t min_batches;   /* minimum number of batches n_b (Section 3.2.2 uses >= 3); 0 or 1 = as few as possible */
-    uint32_t reserved0;
+    uint32_t autotune;      /* selfjoin_run_batched only: 1 = time candidate tile lengths and queue granularities on the batch and keep the fastest */
     uint64_t mem_budget;    /* device bytes the result buffers may use; 0 = a default share of free device memory */
 } sj_options;
 
@@ -164,6 +164,74 @@ int selfjoin_get_perm(const sj_index *idx, uint32_t *perm, uint32_t cap);
 
 /* Releases the handle and all its memory.  NULL is ignored. */
 void selfjoin_free(sj_index *idx);
+
+/* ------------------------------------------------------------------------
+ * Many independent self-joins at once.
+ *
+ * Each job is the problem of Section 3.1 on its own point set.  Every job
+ * gets its own grid index (as selfjoin_build_index, automatic k per job);
+ * the distance filtering of ALL jobs then runs as one persistent
+ * matrix-core kernel over a shared work queue, captured together with the
+ * result sort into a hipGraph and replayed.  Results are exact (canonical
+ * predicate) and sorted by (i, j) per job.
+ * ---------------------------------------------------------------------- */
+typedef struct sj_job {
+    const float *points;  /* host or device, row-major float32 [n][d], caller-owned, read during the call */
+    uint64_t n;           /* 0 .. 2^20 - 1 points */
+    uint32_t d;           /* 1 .. 77 dimensions (matrix-core K padding <= 80) */
+    uint32_t reserved;
+    double epsilon;       /* finite, > 0 */
+} sj_job;
+
+typedef struct sj_batch sj_batch; /* opaque; owns every job's index and the shared result */
+
+typedef struct sj_batch_info {
+    uint32_t struct_size;     /* sizeof(sj_batch_info) */
+    uint32_t njobs;
+    uint64_t pairs;           /* total |R| over all jobs */
+    uint64_t candidates;      /* total ordered candidate pairs */
+    uint64_t evaluated;       /* pair evaluations of the persistent kernel */
+    uint64_t rechecks;        /* FP64 band rechecks */
+    uint64_t capacity;        /* key slots of the shared result buffer */
+    uint64_t n_wu;            /* work units in the shared queue */
+    uint32_t tile_candidates; /* candidate stretch per work unit (tile shape) */
+    uint32_t queue_grab;      /* work units a wave takes from the queue at once */
+    uint32_t grid;            /* workgroups of the persistent launch */
+    uint32_t tuned;           /* 0 defaults, 1 tuned now, 2 taken from the tuning cache */
+    float    ms_build;        /* sum of the jobs' index builds (device events) */
+    float    ms_estimate;     /* sum of the jobs' sampled counts */
+    float    ms_graph;        /* last replay of the captured graph: join + ids + sort + bounds */
+    float    ms_host_build;   /* wall time of all index builds */
+    float    ms_host_prepare; /* wall time of counting, queue and buffer set-up */
+    float    ms_tune;         /* wall time of the autotuner (0 when cached or off) */
+} sj_batch_info;
+
+/* Builds every job's index, pre-sizes the shared result from sampled
+ * counts, captures the persistent join + sort into a hipGraph and replays
+ * it once.  opts (NULL = defaults) apply to every job; the precision is
+ * SJ_PREC_FP16 unless SJ_PREC_BF16 is asked for (SJ_PREC_FP32 selects FP16
+ * here).  Errors as selfjoin_build_index, plus SJ_ERR_INVALID_ARG for njobs
+ * outside [1, 65536], n >= 2^20 or d > 77. */
+int selfjoin_run_batched(const sj_job *jobs, uint32_t njobs, const sj_options *opts,
+                         void *stream, sj_batch **out);
+
+/* Replays the captured graph (same result); *ms receives its device time. */
+int selfjoin_batch_replay(sj_batch *batch, float *ms);
+
+/* Slot range of job `job` in the batch result: *count pairs. */
+int selfjoin_batch_range(const sj_batch *batch, uint32_t job, uint64_t *first, uint64_t *count);
+
+/* As selfjoin_fetch_pairs, for the pairs [first, first + max_pairs) of one
+ * job (indices are the job's own row indices). */
+int selfjoin_batch_fetch(sj_batch *batch, uint32_t job, uint64_t first, uint64_t max_pairs,
+                         uint32_t *out_i, uint32_t *out_j, float *out_dist,
+                         uint64_t *n_written, void *stream);
+
+/* info->struct_size must be set by the caller. */
+int selfjoin_batch_get_info(const sj_batch *batch, sj_batch_info *info);
+
+/* Releases the batch and all its memory.  NULL is ignored. */
+void selfjoin_batch_free(sj_batch *batch);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *selfjoin_last_error(void);

@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -571,6 +572,7 @@ void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s)
 // Single batch: symmetric join of all work units into device memory.
 void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
   uint64_t cap = est + est / 8 + (1u << 20);
+  if (debug_undersize()) cap = std::max<uint64_t>(1, est / 16);
   float ms_join = 0.0f;
   DevBuf other;
   for (int attempt = 0; attempt < 3; ++attempt) {
@@ -660,6 +662,7 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
         sl.busy = false;
       }
       uint64_t cap = per_batch + per_batch / 8 + (1u << 16);
+      if (debug_undersize()) cap = std::max<uint64_t>(1, per_batch / 16);
       uint64_t got = 0;
       for (int attempt = 0; attempt < 3; ++attempt) {
         sl.keys.ensure(cap * 8);
@@ -795,6 +798,11 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   *n_written = cnt;
 }
 
+bool debug_undersize() {
+  const char *v = std::getenv("SJ_DEBUG_UNDERSIZE");
+  return v && v[0] == '1';
+}
+
 sj_options checked_options(const float *points, uint64_t n, uint32_t d, double epsilon,
                            const sj_options *opts) {
   if (d == 0 || d > SJ_MAX_DIM)
@@ -807,7 +815,7 @@ sj_options checked_options(const float *points, uint64_t n, uint32_t d, double e
   sj_options o;
   fill_defaults(&o);
   if (opts) {
-    if (opts->struct_size < offsetof(sj_options, reserved0) || opts->struct_size > sizeof(o))
+    if (opts->struct_size < offsetof(sj_options, autotune) || opts->struct_size > sizeof(o))
       fail(SJ_ERR_INVALID_ARG, "sj_options.struct_size is not a known size");
     std::memcpy(&o, opts, opts->struct_size);
     o.struct_size = sizeof(o);

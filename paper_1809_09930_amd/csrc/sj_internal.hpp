@@ -91,9 +91,14 @@ void exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t n,
 // Stable LSD radix sort of 64-bit keys (optionally with 32-bit values) over
 // the bit ranges listed in `shifts` (8-bit digits at each shift).  Sorted
 // output ends in keys[0]/vals[0]; keys[1]/vals[1] are the ping-pong buffers.
+// With d_count non-null, n is the capacity that sizes the launches and only
+// the first min(*d_count, n) keys are sorted (for captured graphs, where
+// the count is known on the device only).
 size_t radix_tmp_bytes(uint64_t n);
 void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n,
-                    const int *shifts, int n_passes, void *tmp, hipStream_t s);
+                    const int *shifts, int n_passes, void *tmp, hipStream_t s,
+                    const unsigned long long *d_count = nullptr);
+void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v, hipStream_t s);
 
 // out[i] = i * stride; widen u32 -> u64; narrow u64 -> u32 (low half).
 void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, hipStream_t s);
@@ -137,9 +142,10 @@ void launch_join_fp32(const JoinLaunch &a, hipStream_t s);
 
 // Unpack sorted keys [first, first+count) to (i, j) columns and optionally
 // recompute FP32 distances.
+// Keys are (i << ishift) | j with both fields `ishift` bits wide.
 void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i,
                    uint32_t *out_j, float *out_dist, const float *X,
                    const uint32_t *pos_of, const uint16_t *inv_perm,
-                   uint32_t d, uint32_t dp, hipStream_t s);
+                   uint32_t d, uint32_t dp, hipStream_t s, uint32_t ishift = 32);
 
 }  // namespace sj

@@ -265,11 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ 
                                                    const float *__restrict__ X,
                                                    const uint32_t *__restrict__ pos_of,
                                                    const uint16_t *__restrict__ inv_perm,
-                                                   uint32_t d, uint32_t dp) {
+                                                   uint32_t d, uint32_t dp, uint32_t ishift) {
   const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= count) return;
   const uint64_t key = keys[e];
-  const uint32_t i = (uint32_t)(key >> 32), j = (uint32_t)key;
+  const uint64_t mask = (1ull << ishift) - 1ull;
+  const uint32_t i = (uint32_t)((key >> ishift) & mask), j = (uint32_t)(key & mask);
   if (out_i) out_i[e] = i;
   if (out_j) out_j[e] = j;
   if (out_dist) {
@@ -329,11 +330,12 @@ void launch_join_fp32(const JoinLaunch &a, hipStream_t s) {
 
 void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i, uint32_t *out_j,
                    float *out_dist, const float *X, const uint32_t *pos_of,
-                   const uint16_t *inv_perm, uint32_t d, uint32_t dp, hipStream_t s) {
+                   const uint16_t *inv_perm, uint32_t d, uint32_t dp, hipStream_t s,
+                   uint32_t ishift) {
   if (!count) return;
   const uint32_t grid = (uint32_t)((count + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_unpack, dim3(grid), dim3(kBlock), 0, s, keys, count, out_i, out_j,
-                     out_dist, X, pos_of, inv_perm, d, dp);
+                     out_dist, X, pos_of, inv_perm, d, dp, ishift);
   SJ_HIP(hipGetLastError());
 }
 

@@ -2,6 +2,7 @@
 // Both are plain gfx950 kernels (wave64, 256-thread workgroups, LDS staging).
 #include "sj_internal.hpp"
 
+#include <algorithm>
 #include <vector>
 
 namespace sj {
@@ -140,11 +141,18 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRsRounds = 16;
 constexpr int kRsTile = kBlock * kRsRounds;  // 4096
 
+// When d_count is non-null only the first min(*d_count, n) keys take part.
+__device__ __forceinline__ uint64_t live_count(uint64_t n, const unsigned long long *d_count) {
+  return d_count ? (*d_count < n ? (uint64_t)*d_count : n) : n;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys,
-                                                    uint64_t n, int shift,
+                                                    uint64_t n_cap, int shift,
                                                     uint32_t *__restrict__ hist,
-                                                    uint32_t nblocks) {
+                                                    uint32_t nblocks,
+                                                    const unsigned long long *__restrict__ d_count) {
   __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
+  const uint64_t n = live_count(n_cap, d_count);
   const int w = threadIdx.x / kWave;
   for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock)
     (&cnt[0][0])[i] = 0;
@@ -170,8 +178,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
 template <bool kVals>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n, int shift,
-    const uint32_t *__restrict__ offs, uint32_t nblocks) {
+    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n_cap, int shift,
+    const uint32_t *__restrict__ offs, uint32_t nblocks,
+    const unsigned long long *__restrict__ d_count) {
   __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
   __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];
   __shared__ uint32_t dbase[kRadixBins];   // first slot of each digit in the tile
@@ -185,6 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   __syncthreads();
 
   // 1. rank every key among equal digits of its wave, in input order
+  const uint64_t n = live_count(n_cap, d_count);
   const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
   const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kWavesPerBlock);
   uint64_t key[kRsRounds];
@@ -246,7 +256,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   // 4. write the tile out in digit order: consecutive threads write
   //    consecutive slots of each digit's run
   const uint32_t valid_keys =
-      (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
+      tile0 >= n ? 0u
+                 : (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
   for (uint32_t i = threadIdx.x; i < valid_keys; i += kBlock) {
     const uint64_t k = tkey[i];
     const uint32_t dg = (uint32_t)(k >> shift) & (kRadixBins - 1);
@@ -254,6 +265,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     kout[pos] = k;
     if (kVals) vout[pos] = tval[i];
   }
+}
+
+__global__ void k_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+__global__ void k_copy_u64(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t n,
+                           const unsigned long long *__restrict__ d_count) {
+  const uint64_t m = live_count(n, d_count);
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+       i += (uint64_t)gridDim.x * kBlock)
+    out[i] = in[i];
 }
 
 __global__ void k_iota_strided(uint32_t *out, uint64_t count, uint64_t stride) {
@@ -308,9 +331,16 @@ size_t radix_tmp_bytes(uint64_t n) {
   return ((hist * 4 + 255) / 256) * 256 + scan_levels_bytes<uint32_t>(hist);
 }
 
+void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v, hipStream_t s) {
+  if (!count) return;
+  hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     p, count, v);
+  SJ_HIP(hipGetLastError());
+}
+
 void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int *shifts,
-                    int n_passes, void *tmp, hipStream_t s) {
-  if (n <= 1 || n_passes == 0) return;
+                    int n_passes, void *tmp, hipStream_t s, const unsigned long long *d_count) {
+  if (n == 0 || (n == 1 && !d_count) || n_passes == 0) return;
   if (n > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "radix sort of more than 2^32-1 keys");
   const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
   const uint64_t nhist = (uint64_t)kRadixBins * nb;
@@ -319,25 +349,33 @@ void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int 
   int cur = 0;
   for (int p = 0; p < n_passes; ++p) {
     const int sh = shifts[p];
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kBlock), 0, s, keys[cur], n, sh, hist, nb);
+    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kBlock), 0, s, keys[cur], n, sh, hist, nb,
+                       d_count);
     SJ_HIP(hipGetLastError());
     exclusive_scan_u32(hist, hist, nhist, nullptr, scan_tmp, s);
     if (vals) {
       hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
-                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, sh, hist, nb);
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, sh, hist, nb, d_count);
     } else {
       hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
                          (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n,
-                         sh, hist, nb);
+                         sh, hist, nb, d_count);
     }
     SJ_HIP(hipGetLastError());
     cur ^= 1;
   }
   if (cur == 1) {
     // odd number of passes: move the result into buffer 0
-    SJ_HIP(hipMemcpyAsync(keys[0], keys[1], n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    if (vals)
-      SJ_HIP(hipMemcpyAsync(vals[0], vals[1], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (d_count) {
+      if (vals) fail(SJ_ERR_INVALID_ARG, "odd pass count with values and a device count");
+      const uint32_t g = (uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 65536);
+      hipLaunchKernelGGL(k_copy_u64, dim3(g), dim3(kBlock), 0, s, keys[1], keys[0], n, d_count);
+      SJ_HIP(hipGetLastError());
+    } else {
+      SJ_HIP(hipMemcpyAsync(keys[0], keys[1], n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+      if (vals)
+        SJ_HIP(hipMemcpyAsync(vals[0], vals[1], n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
   }
 }
 

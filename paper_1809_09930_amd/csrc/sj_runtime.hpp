@@ -192,6 +192,10 @@ void build(sj_index &ix, const float *points, hipStream_t s);
 uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms);
 uint64_t default_budget();
 MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist, int sym);
+// Fault injection from the host: SJ_DEBUG_UNDERSIZE=1 makes the first
+// result buffer of every run far too small, so the device-side overflow
+// detection and the resize-and-rerun path are exercised.
+bool debug_undersize();
 
 template <typename F>
 int guarded(F &&f) {

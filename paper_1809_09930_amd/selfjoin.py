@@ -28,7 +28,9 @@ PRECISIONS = {"fp32": SJ_PREC_FP32, "fp16": SJ_PREC_FP16, "bf16": SJ_PREC_BF16}
 
 EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_run",
             "selfjoin_fetch_pairs", "selfjoin_get_info", "selfjoin_get_perm",
-            "selfjoin_free", "selfjoin_last_error")
+            "selfjoin_free", "selfjoin_last_error", "selfjoin_run_batched",
+            "selfjoin_batch_replay", "selfjoin_batch_range", "selfjoin_batch_fetch",
+            "selfjoin_batch_get_info", "selfjoin_batch_free")
 
 
 class SjOptions(ctypes.Structure):
@@ -41,7 +43,7 @@ class SjOptions(ctypes.Structure):
                 ("precision", ctypes.c_uint32),
                 ("batch_pairs", ctypes.c_uint64),
                 ("min_batches", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32),
+                ("autotune", ctypes.c_uint32),
                 ("mem_budget", ctypes.c_uint64)]
 
 
@@ -65,6 +67,35 @@ class SjInfo(ctypes.Structure):
                 ("ms_run", ctypes.c_float),
                 ("join_launches", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32)]
+
+
+class SjJob(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p),
+                ("n", ctypes.c_uint64),
+                ("d", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32),
+                ("epsilon", ctypes.c_double)]
+
+
+class SjBatchInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32),
+                ("njobs", ctypes.c_uint32),
+                ("pairs", ctypes.c_uint64),
+                ("candidates", ctypes.c_uint64),
+                ("evaluated", ctypes.c_uint64),
+                ("rechecks", ctypes.c_uint64),
+                ("capacity", ctypes.c_uint64),
+                ("n_wu", ctypes.c_uint64),
+                ("tile_candidates", ctypes.c_uint32),
+                ("queue_grab", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32),
+                ("tuned", ctypes.c_uint32),
+                ("ms_build", ctypes.c_float),
+                ("ms_estimate", ctypes.c_float),
+                ("ms_graph", ctypes.c_float),
+                ("ms_host_build", ctypes.c_float),
+                ("ms_host_prepare", ctypes.c_float),
+                ("ms_tune", ctypes.c_float)]
 
 
 class SelfJoinError(RuntimeError):
@@ -104,6 +135,19 @@ def load_library(path: str = LIB_PATH):
     lib.selfjoin_free.restype = None
     lib.selfjoin_last_error.argtypes = []
     lib.selfjoin_last_error.restype = ctypes.c_char_p
+    lib.selfjoin_run_batched.argtypes = [ctypes.POINTER(SjJob), u32, ctypes.POINTER(SjOptions), vp,
+                                         ctypes.POINTER(vp)]
+    lib.selfjoin_run_batched.restype = ctypes.c_int
+    lib.selfjoin_batch_replay.argtypes = [vp, ctypes.POINTER(ctypes.c_float)]
+    lib.selfjoin_batch_replay.restype = ctypes.c_int
+    lib.selfjoin_batch_range.argtypes = [vp, u32, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.selfjoin_batch_range.restype = ctypes.c_int
+    lib.selfjoin_batch_fetch.argtypes = [vp, u32, u64, u64, vp, vp, vp, ctypes.POINTER(u64), vp]
+    lib.selfjoin_batch_fetch.restype = ctypes.c_int
+    lib.selfjoin_batch_get_info.argtypes = [vp, ctypes.POINTER(SjBatchInfo)]
+    lib.selfjoin_batch_get_info.restype = ctypes.c_int
+    lib.selfjoin_batch_free.argtypes = [vp]
+    lib.selfjoin_batch_free.restype = None
     _lib = lib
     return lib
 
@@ -191,6 +235,71 @@ def selfjoin_get_perm(handle, d: int):
     arr = (ctypes.c_uint32 * d)()
     _check(load_library().selfjoin_get_perm(handle, arr, d))
     return list(arr)
+
+
+def selfjoin_run_batched(points_list, eps_list, precision="fp16", autotune: bool = False,
+                         k: int = 0, reorder: bool = True, stream=None):
+    """Run len(points_list) independent self-joins in one persistent launch
+    (float32 [n, d] tensors, CUDA or CPU).  Returns an opaque batch handle."""
+    import torch
+    lib = load_library()
+    pts = [p.contiguous() for p in points_list]
+    for p in pts:
+        if p.dtype != torch.float32 or p.dim() != 2:
+            raise ValueError("points must be float32 [n, d] tensors")
+    jobs = (SjJob * len(pts))()
+    for i, (p, e) in enumerate(zip(pts, eps_list)):
+        jobs[i].points = p.data_ptr() if p.numel() else None
+        jobs[i].n, jobs[i].d = p.shape
+        jobs[i].epsilon = float(e)
+    o = default_options()
+    o.k = int(k)
+    o.reorder = 1 if reorder else 0
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.autotune = 1 if autotune else 0
+    h = ctypes.c_void_p()
+    _check(lib.selfjoin_run_batched(jobs, len(pts), ctypes.byref(o), _stream_handle(stream),
+                                    ctypes.byref(h)))
+    return h.value
+
+
+def selfjoin_batch_replay(batch) -> float:
+    ms = ctypes.c_float()
+    _check(load_library().selfjoin_batch_replay(batch, ctypes.byref(ms)))
+    return ms.value
+
+
+def selfjoin_batch_range(batch, job: int):
+    first, count = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().selfjoin_batch_range(batch, job, ctypes.byref(first),
+                                               ctypes.byref(count)))
+    return first.value, count.value
+
+
+def selfjoin_batch_fetch(batch, job: int, first: int, out_i=None, out_j=None, out_dist=None,
+                         max_pairs: int | None = None, stream=None) -> int:
+    sizes = [t.numel() for t in (out_i, out_j, out_dist) if t is not None]
+    if max_pairs is None:
+        max_pairs = min(sizes) if sizes else 0
+    nw = ctypes.c_uint64()
+    ptr = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+    _check(load_library().selfjoin_batch_fetch(batch, job, int(first), int(max_pairs),
+                                               ptr(out_i), ptr(out_j), ptr(out_dist),
+                                               ctypes.byref(nw), _stream_handle(stream)))
+    return nw.value
+
+
+def selfjoin_batch_get_info(batch) -> dict:
+    info = SjBatchInfo()
+    info.struct_size = ctypes.sizeof(SjBatchInfo)
+    _check(load_library().selfjoin_batch_get_info(batch, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in SjBatchInfo._fields_
+            if name != "struct_size"}
+
+
+def selfjoin_batch_free(batch) -> None:
+    if batch:
+        load_library().selfjoin_batch_free(batch)
 
 
 def selfjoin_free(handle) -> None:
