@@ -39,6 +39,14 @@ namespace sj {
 
 constexpr double kWidthSlack = 1.0 + 1.0 / (1 << 20);  // cell side = eps * (1 + 2^-20)
 
+// Fine (Morton) ordering inside cells: dimensions and bits per dimension.
+#ifndef SJ_FINE_DIMS
+#define SJ_FINE_DIMS 8
+#endif
+#ifndef SJ_FINE_BITS
+#define SJ_FINE_BITS 3
+#endif
+
 // Cost model for the automatic choice of k (Section 5.5 compares the memory
 // operations of index searches with those of distance calculations): one
 // unit per 3^k-offset lookup of each non-empty cell, one per evaluated pair.
@@ -73,10 +81,10 @@ bool make_geometry(const sj_index &ix, uint32_t k, Geometry &g) {
     mult *= m[r];
   }
   const uint32_t cell_bits = bits_for(mult - 1);
-  // fine key: Morton code of up to 6 reordered dimensions, 4 bits each,
-  // as far as the 64-bit sort key allows
-  const uint32_t fm = std::min<uint32_t>(ix.d, 6);
-  uint32_t fb = 4;
+  // fine key: Morton code of up to SJ_FINE_DIMS reordered dimensions,
+  // SJ_FINE_BITS bits each, as far as the 64-bit sort key allows
+  const uint32_t fm = std::min<uint32_t>(ix.d, SJ_FINE_DIMS);
+  uint32_t fb = SJ_FINE_BITS;
   while (fb > 0 && cell_bits + fm * fb > 63) --fb;
   g.kp.fm = fb ? fm : 0;
   g.kp.fb = fb;
@@ -276,7 +284,7 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
   ix.fmt = fmt;
   ix.prec = fmt == kFmtF16 ? SJ_PREC_FP16 : SJ_PREC_BF16;
   ix.kp = mfma_kp(d, fmt);
-  ix.n_pad = (ix.n + 31) / 32 * 32 + 32;
+  ix.n_pad = (ix.n + 31) / 32 * 32 + 64;  // chunks of 64 rows read past a run's end
   const uint64_t np = ix.n_pad;
   ix.XA.alloc(np * ix.kp * 2);
   ix.XB.alloc(np * ix.kp * 2);
@@ -445,9 +453,11 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
                             &ix.evaluated_sym, s);
   if (ix.opt.precision != SJ_PREC_FP32) {
     mfma_prepare(ix, s);
-    ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);
+    ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);         // per wave (batched kernel)
+    const uint32_t tq_wg = mfma_wg_queries(ix.kp);    // per workgroup (single join)
     ix.tc_m = choose_tc(ev, ix.tq_m);
-    ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_m, ix.tc_m,
+    const uint32_t tc_wg = std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
+    ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, tq_wg, tc_wg,
                                 ix.wu_m, &ix.evaluated_sym_m, s);
   }
 
@@ -653,8 +663,8 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
       uint64_t ev = 0;
       const bool mf = ix.prec != SJ_PREC_FP32;
       const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
-                                           ix.runs_full, mf ? ix.tq_m : ix.tq,
-                                           mf ? ix.tc_m : ix.tc, wu, &ev, s);
+                                           ix.runs_full, mf ? mfma_wg_queries(ix.kp) : ix.tq,
+                                           mf ? ix.tc_m * 4 : ix.tc, wu, &ev, s);
       evaluated += ev;
       Slot &sl = slots[slot & 1];
       if (sl.busy) {

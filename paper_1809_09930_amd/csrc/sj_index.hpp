@@ -7,7 +7,7 @@ namespace sj {
 
 constexpr int kKeyMaxDims = 16;  // most dimensions one linearised cell key covers
 
-constexpr int kFineMaxDims = 8;
+constexpr int kFineMaxDims = 16;
 
 // Sort key of a point: (cell key << fine_bits) | fine key.
 // Cell key: sum over r < k of c_r * mult[r], with

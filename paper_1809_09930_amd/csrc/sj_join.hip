@@ -12,9 +12,9 @@
 // added (round-to-nearest addition of a non-negative term never decreases
 // the sum), so once every lane of a query group has a partial sum above the
 // reject threshold `hi`, the rest of that candidate is skipped for the group.
-// The test is wave-uniform: it runs after the first 4 dimensions and then
-// every 2.  Points inside a cell are ordered along a Morton curve, so the 64
-// queries of a group are neighbours and their partial sums rise together.
+// The test is wave-uniform; its schedule is SJ_SHORTC_FIRST / SJ_SHORTC_STEP.
+// Points inside a cell are ordered along a Morton curve, so the 64 queries of
+// a group are neighbours and their partial sums rise together.
 //
 // Exactness.  `hi` and `lo` bound the FP32 rounding error of the sum against
 // the canonical FP64 predicate: s > hi proves rejection, s <= lo proves
@@ -33,6 +33,22 @@ namespace sj {
 namespace {
 
 constexpr int kStage = 512;  // u64 keys staged per wave
+
+// Short-circuit schedule: first test after SJ_SHORTC_FIRST dimensions, then
+// every SJ_SHORTC_STEP.
+#ifndef SJ_SHORTC_FIRST
+#define SJ_SHORTC_FIRST 8
+#endif
+#ifndef SJ_SHORTC_STEP
+#define SJ_SHORTC_STEP 4
+#endif
+// Query points per lane by padded dimension (register blocking).
+#ifndef SJ_FP32_RQ_SMALL
+#define SJ_FP32_RQ_SMALL 4  // dp <= 24
+#endif
+#ifndef SJ_FP32_RQ_MID
+#define SJ_FP32_RQ_MID 2    // dp <= 64
+#endif
 
 // Canonical predicate on positions a, b of the cell-ordered rows.
 __device__ __noinline__ bool canonical_within(const float *__restrict__ X, uint32_t a, uint32_t b,
@@ -87,8 +103,8 @@ __device__ __forceinline__ void eval_candidate(
     float lo, float hi, double eps2, bool symmetric, bool shortc,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
-  constexpr int kFirst = DP < 4 ? DP : 4;
-  constexpr int kStep = 2;
+  constexpr int kFirst = DP < SJ_SHORTC_FIRST ? DP : SJ_SHORTC_FIRST;
+  constexpr int kStep = SJ_SHORTC_STEP;
   const float *__restrict__ crow = X + (uint64_t)c * DP;
   float s[RQ];
 #pragma unroll
@@ -122,16 +138,21 @@ __device__ __forceinline__ void eval_candidate(
           if (ballot(s[r] <= hi) == 0) alive &= ~(1u << r);
       if (alive == 0) return;
     }
+    // the last step is shorter when kStep does not divide DP (the bounds
+    // are compile-time constants once the loops are unrolled)
     float cv[kStep];
 #pragma unroll
-    for (int t = 0; t < kStep; ++t) cv[t] = crow[t0 + t];
+    for (int t = 0; t < kStep; ++t)
+      if (t0 + t < DP) cv[t] = crow[t0 + t];
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
       if ((alive >> r) & 1u) {
 #pragma unroll
         for (int t = 0; t < kStep; ++t) {
-          const float diff = L.q[r][t0 + t] - cv[t];
-          s[r] = __builtin_fmaf(diff, diff, s[r]);
+          if (t0 + t < DP) {
+            const float diff = L.q[r][t0 + t] - cv[t];
+            s[r] = __builtin_fmaf(diff, diff, s[r]);
+          }
         }
       }
     }
@@ -290,7 +311,7 @@ template <int DP>
 void launch_dp(const JoinLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
   if (grid == 0) return;
-  constexpr int kRq = DP <= 24 ? 4 : (DP <= 64 ? 2 : 1);
+  constexpr int kRq = DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1);
   if (a.count_only)
     hipLaunchKernelGGL((k_count_fp32<DP, kRq>), dim3(grid), dim3(kBlock), 0, s, a.X, a.orig_id,
                        a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi, a.eps2,
@@ -310,7 +331,7 @@ uint32_t padded_dim(uint32_t d) {
   return (d + 15) / 16 * 16;
 }
 
-int fp32_rq_for(uint32_t dp) { return dp <= 24 ? 4 : (dp <= 64 ? 2 : 1); }
+int fp32_rq_for(uint32_t dp) { return dp <= 24 ? SJ_FP32_RQ_SMALL : (dp <= 64 ? SJ_FP32_RQ_MID : 1); }
 
 void launch_join_fp32(const JoinLaunch &a, hipStream_t s) {
   switch (a.dp) {

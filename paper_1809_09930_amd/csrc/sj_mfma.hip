@@ -366,7 +366,7 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
     }
     bool any = false;
 #pragma unroll
-    for (int j = 0; j < QB; ++j) any = any || (min16(acc[j]) <= th[j]);
+    for (int j = 0; j < QB; ++j) any |= (min16(acc[j]) <= th[j]);
     if (ballot(any)) {
       // some pair of this block may be a result: element by element
 #pragma unroll
@@ -425,6 +425,151 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(MfmaView v, const WorkUnit
   mfma_unit<KP, FMT, QB>(v, wu, st, out, capacity, cursor, n_recheck);
   flush(st, out, capacity, cursor);
   if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+// Workgroup-cooperative form of the same filter for a single join: the 4
+// waves of a workgroup own 4 x 32*QB query columns of one work unit and
+// share every candidate chunk of kChunk rows, which is fetched from memory
+// once into a double-buffered LDS stage (global -> registers during the
+// MFMAs of the previous chunk -> LDS) instead of once per wave.
+constexpr int kChunk = 64;  // candidate rows per LDS stage (2 MFMA row blocks)
+
+template <int KP, int FMT, int QB>
+__global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
+                                                         const WorkUnit *__restrict__ wus,
+                                                         uint64_t n_wu, uint64_t *__restrict__ out,
+                                                         uint64_t capacity,
+                                                         unsigned long long *__restrict__ cursor,
+                                                         unsigned long long *__restrict__ rechecks) {
+  typedef typename Fmt<FMT>::V8 V8;
+  constexpr int KS = KP / 16;                     // MFMA K steps
+  constexpr int RV = KP / 8;                      // 8-element vectors per row
+  constexpr int CHUNK_VECS = kChunk * RV;         // vectors per LDS stage
+  constexpr int PER_THREAD = (CHUNK_VECS + kBlock - 1) / kBlock;
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  __shared__ V8 tile[2][CHUNK_VECS];
+  const uint64_t u = blockIdx.x;
+  if (u >= n_wu) return;  // whole workgroup leaves together
+  const WorkUnit wu = wus[u];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  const uint32_t l = lane_id();
+  const uint32_t half = l >> 5, col = l & 31;
+  const V8 *__restrict__ XA = static_cast<const V8 *>(v.XA);
+  const V8 *__restrict__ XB = static_cast<const V8 *>(v.XB);
+
+  // this wave's query columns
+  V8 B[QB][KS];
+  float th[QB], tl[QB];
+  uint32_t qpos[QB];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    const uint32_t slot = wu.q0 + (w * QB + (uint32_t)j) * 32 + col;
+    const bool live = slot < wu.q1;
+    const uint32_t p = live ? (v.qlist ? v.qlist[slot] : slot) : 0u;
+    qpos[j] = live ? p : 0xffffffffu;
+    th[j] = live ? v.thi[p] : -__builtin_inff();
+    tl[j] = live ? v.tlo[p] : -__builtin_inff();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
+  }
+  const bool sym = v.symmetric != 0;
+  Stage st{&stage_mem[w][0], 0u};
+  uint64_t n_recheck = 0;
+
+  // chunk walk (uniform over the workgroup)
+  uint32_t r = wu.run_first, c = wu.c_begin;
+  uint32_t ce = (r == wu.run_last) ? wu.c_end : v.runs[r].y;
+  auto normalise = [&]() {
+    while (c >= ce && r < wu.run_last) {
+      ++r;
+      c = v.runs[r].x;
+      ce = (r == wu.run_last) ? wu.c_end : v.runs[r].y;
+    }
+  };
+  normalise();
+  V8 pre[PER_THREAD];
+  auto fetch = [&](uint32_t base) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
+      if (e < (uint32_t)CHUNK_VECS) pre[i] = XA[(uint64_t)base * RV + e];
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
+      if (e < (uint32_t)CHUNK_VECS) tile[buf][e] = pre[i];
+    }
+  };
+  if (c >= ce) return;  // empty unit (uniform)
+  fetch(c);
+  store(0);
+  __syncthreads();
+  int cur = 0;
+  for (;;) {
+    const uint32_t cc = c, cce = ce;
+    c += kChunk;
+    normalise();
+    const bool more = c < ce;
+    if (more) fetch(c);
+    for (int blk = 0; blk < kChunk / 32; ++blk) {
+      V8 A[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) A[ks] = tile[cur][(blk * 32 + col) * RV + ks * 2 + half];
+      float16v acc[QB];
+#pragma unroll
+      for (int j = 0; j < QB; ++j) {
+        float16v z = {};
+        acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
+#pragma unroll
+        for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
+      }
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < QB; ++j) any |= (min16(acc[j]) <= th[j]);
+      if (ballot(any)) {
+        const uint32_t c0 = cc + (uint32_t)blk * 32;
+#pragma unroll
+        for (int j = 0; j < QB; ++j) {
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            const bool h = acc[j][e] <= th[j];
+            if (ballot(h) == 0) continue;
+            const uint32_t cp = c0 + 8 * (e / 4) + 4 * half + (e % 4);
+            const bool ok = h && cp < cce && (!sym || qpos[j] <= cp);
+            bool acc_ok = ok && acc[j][e] <= tl[j];
+            const bool band = ok && !acc_ok;
+            const uint64_t bm = ballot(band);
+            if (bm) {
+              if (band)
+                acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+              n_recheck += (uint64_t)__builtin_popcountll(bm);
+            }
+            const uint64_t am = ballot(acc_ok);
+            if (am == 0) continue;
+            const bool two = acc_ok && sym && qpos[j] != cp;
+            const uint64_t m2 = ballot(two);
+            const uint32_t total =
+                (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+            if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
+            const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+            if (acc_ok) {
+              st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+              if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
+            }
+            st.cnt += total;
+          }
+        }
+      }
+    }
+    if (!more) break;
+    store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  flush(st, out, capacity, cursor);
+  if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
 }
 
 // Many independent joins in one persistent launch.  Every wave takes
@@ -526,8 +671,10 @@ void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   if (!grid) return;
   constexpr int QB = KP <= 64 ? 4 : 2;
   MfmaView v = a.view;
-  hipLaunchKernelGGL((k_join_mfma<KP, FMT, QB>), dim3(grid), dim3(kBlock), 0, s, v, a.wu, a.n_wu,
-                     a.out, a.capacity, a.cursor, a.rechecks);
+  // one workgroup per work unit (4 waves x 32*QB queries)
+  hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB>), dim3((uint32_t)a.n_wu), dim3(kBlock), 0, s, v,
+                     a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
+  (void)grid;
   SJ_HIP(hipGetLastError());
 }
 
@@ -557,6 +704,8 @@ uint32_t mfma_kp(uint32_t d, int fmt) {
 }
 
 int mfma_qb(uint32_t kp) { return kp <= 64 ? 4 : 2; }
+
+uint32_t mfma_wg_queries(uint32_t kp) { return (uint32_t)(kWavesPerBlock * 32 * mfma_qb(kp)); }
 
 void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
                       uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,

@@ -53,6 +53,9 @@ struct BatchJob {
 int mfma_pieces(int fmt);
 uint32_t mfma_kp(uint32_t d, int fmt);
 int mfma_qb(uint32_t kp);
+// Query slots of one work unit of the single-join matrix kernel (a whole
+// workgroup); the batched kernel uses 32*mfma_qb per wave.
+uint32_t mfma_wg_queries(uint32_t kp);
 void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
                       uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,
                       double *dist_c, double *fold_err, unsigned long long *maxima, hipStream_t s);

@@ -16,6 +16,29 @@ import oracle  # noqa: E402
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "eps.json")
 
 
+def batched(name="batched_256", n_jobs=256, seed=7):
+    """Per-job epsilons of the many-joins workload (datagen.batched_job_specs):
+    each job's own target mean-neighbour count on its own seeded sample."""
+    table = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            table = json.load(f)
+    t0 = time.time()
+    jobs = []
+    for spec in datagen.batched_job_specs(n_jobs, seed):
+        P = datagen.make_job(spec)
+        rows = datagen.calibration_rows(len(P), spec["seed"])
+        eps, sd = oracle.calibrate_eps(P, spec["target"], rows)
+        jobs.append({"hex": float(eps).hex(), "value": float(eps), "sample_sd": sd,
+                     "n": spec["n"], "d": spec["d"], "kind": spec["kind"],
+                     "target": spec["target"]})
+        if len(jobs) % 32 == 0:
+            print(name, len(jobs), "%.1fs" % (time.time() - t0), flush=True)
+    table[name] = {"n_jobs": n_jobs, "seed": seed, "jobs": jobs}
+    with open(OUT, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+
+
 def main(names):
     table = {}
     if os.path.exists(OUT):
@@ -40,4 +63,8 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or list(datagen.WORKLOADS))
+    args = sys.argv[1:]
+    if args == ["batched_256"]:
+        batched()
+    else:
+        main(args or list(datagen.WORKLOADS))
