@@ -35,19 +35,26 @@ namespace {
 constexpr int kStage = 512;  // u64 keys staged per wave
 
 // Short-circuit schedule: first test after SJ_SHORTC_FIRST dimensions, then
-// every SJ_SHORTC_STEP.
+// every SJ_SHORTC_STEP (padded dimension above 24); the _SMALL pair applies
+// up to 24.
+#ifndef SJ_SHORTC_FIRST_SMALL
+#define SJ_SHORTC_FIRST_SMALL 8
+#endif
+#ifndef SJ_SHORTC_STEP_SMALL
+#define SJ_SHORTC_STEP_SMALL 8
+#endif
 #ifndef SJ_SHORTC_FIRST
-#define SJ_SHORTC_FIRST 8
+#define SJ_SHORTC_FIRST 24
 #endif
 #ifndef SJ_SHORTC_STEP
-#define SJ_SHORTC_STEP 4
+#define SJ_SHORTC_STEP 8
 #endif
 // Query points per lane by padded dimension (register blocking).
 #ifndef SJ_FP32_RQ_SMALL
-#define SJ_FP32_RQ_SMALL 4  // dp <= 24
+#define SJ_FP32_RQ_SMALL 2  // dp <= 24
 #endif
 #ifndef SJ_FP32_RQ_MID
-#define SJ_FP32_RQ_MID 2    // dp <= 64
+#define SJ_FP32_RQ_MID 1    // dp <= 64
 #endif
 
 // Canonical predicate on positions a, b of the cell-ordered rows.
@@ -103,8 +110,9 @@ __device__ __forceinline__ void eval_candidate(
     float lo, float hi, double eps2, bool symmetric, bool shortc,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
-  constexpr int kFirst = DP < SJ_SHORTC_FIRST ? DP : SJ_SHORTC_FIRST;
-  constexpr int kStep = SJ_SHORTC_STEP;
+  constexpr int kFirst0 = DP <= 24 ? SJ_SHORTC_FIRST_SMALL : SJ_SHORTC_FIRST;
+  constexpr int kFirst = DP < kFirst0 ? DP : kFirst0;
+  constexpr int kStep = DP <= 24 ? SJ_SHORTC_STEP_SMALL : SJ_SHORTC_STEP;
   const float *__restrict__ crow = X + (uint64_t)c * DP;
   float s[RQ];
 #pragma unroll

@@ -301,3 +301,53 @@ def test_uniform_2m_d16_sampled_rows_and_symmetry():
     assert info["candidates"] == n * n
     sd = (total - n) / n
     assert 40 < sd < 90
+
+
+@pytest.mark.parametrize("workload,target,prec", [
+    ("uniform_2m_d64", "16", "bf16"),
+    ("uniform_2m_d64", "128", "fp16"),
+    ("mixture50_5m_d18", "50", "fp16"),
+    ("mixture50_5m_d18", "50", "fp32"),
+    ("mixture20_515k_d90", "50", "fp16"),
+])
+def test_full_size_workloads_sampled_rows(workload, target, prec):
+    """The other full-size workloads at their calibrated epsilons: sampled
+    full rows against the oracle, and the symmetry / self-pair invariants of
+    the whole result."""
+    import json
+    import os
+    from conftest import GOLDEN
+    with open(os.path.join(GOLDEN, "eps.json")) as f:
+        table = json.load(f)
+    eps = float.fromhex(table[workload]["eps"][target]["hex"])
+    P = datagen.make_workload(workload)
+    from paper_1809_09930_amd import selfjoin as sj
+    print("case", workload, target, prec, flush=True)
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps, precision=prec)
+    try:
+        total = sj.selfjoin_run(h)
+        oi = torch.empty(total, dtype=torch.int32, device="cuda")
+        oj = torch.empty(total, dtype=torch.int32, device="cuda")
+        sj.selfjoin_fetch_pairs(h, 0, oi, oj, None, max_pairs=total)
+        info = sj.selfjoin_get_info(h)
+    finally:
+        sj.selfjoin_free(h)
+    n = len(P)
+    key = (oi.to(torch.int64) << 32) | oj.to(torch.int64)
+    assert bool((key[1:] > key[:-1]).all())
+    rkey = (oj.to(torch.int64) << 32) | oi.to(torch.int64)
+    assert bool(torch.equal(torch.sort(rkey).values, key))
+    assert int((oi == oj).sum()) == n
+    del rkey
+    rng = np.random.default_rng(11)
+    rows = np.sort(rng.choice(n, size=24, replace=False))
+    cnt, js = oracle.rows(P, eps, rows)
+    starts = torch.searchsorted(oi, torch.from_numpy(rows.astype(np.int32)).cuda()).tolist()
+    off = 0
+    for r, c, st in zip(rows, cnt, starts):
+        got = oj[st:st + int(c)].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, js[off:off + c]), r
+        if st + int(c) < total:
+            assert int(oi[st + int(c)]) != r
+        off += int(c)
+    assert info["candidates"] >= total
