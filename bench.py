@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 import datagen  # noqa: E402
 
 EPS_TABLE = os.path.join(ROOT, "tests", "golden", "eps.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "pmc_k_join_fp32_uniform_2m_d16.md")
 JOIN_SRC = os.path.join(ROOT, "paper_1809_09930_amd", "csrc", "sj_join.hip")
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 FP32 lane
@@ -83,16 +83,21 @@ def shortc_prefix_mean(P, perm, eps2, n_pairs=400_000, seed=99):
 
 
 def traffic_for_join():
-    """HBM bytes per join launch from the committed rocprofv3 counter runs,
-    valid only while the kernel source is unchanged."""
+    """HBM bytes per join launch from the committed rocprofv3 counter
+    summary (its 'key: value' lines), valid only while the kernel source is
+    unchanged."""
     if not os.path.exists(TRAFFIC):
         return None
+    fields = {}
     with open(TRAFFIC) as f:
-        t = json.load(f)
+        for line in f:
+            key, sep, val = line.partition(":")
+            if sep and key.strip() in ("kernel", "source_sha256", "bytes_per_launch"):
+                fields[key.strip()] = val.strip()
     sha = hashlib.sha256(open(JOIN_SRC, "rb").read()).hexdigest()
-    if t.get("source_sha256") != sha:
+    if fields.get("source_sha256") != sha or "bytes_per_launch" not in fields:
         return None
-    return t.get("bytes_per_launch")
+    return int(fields["bytes_per_launch"])
 
 
 def cpu_baseline(P, eps, rows_req):
@@ -133,21 +138,24 @@ def bench_batched(a, table):
 
     def batched_once():
         h = sj.selfjoin_run_batched(pts, eps, precision=prec, autotune=True)
-        info = sj.selfjoin_batch_get_info(h)
-        replays = [sj.selfjoin_batch_replay(h) for _ in range(3)]
-        sj.selfjoin_batch_free(h)
-        return info, replays
+        return h, sj.selfjoin_batch_get_info(h)
 
     for _ in range(a.warmup):
-        batched_once()
+        sj.selfjoin_batch_free(batched_once()[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
     for _ in range(a.steps):
-        infos.append(batched_once())
+        h, info = batched_once()
+        infos.append(info)
+        if len(infos) < a.steps:
+            sj.selfjoin_batch_free(h)
     torch.cuda.synchronize()
     elapsed = (time.perf_counter() - t0) / a.steps
-    info, replays = infos[-1]
+    # replays of the captured graph, outside the timed steps
+    replays = [sj.selfjoin_batch_replay(h) for _ in range(3)]
+    sj.selfjoin_batch_free(h)
+    info = infos[-1]
     cand = info["candidates"]
 
     def sequential(precision):
@@ -297,7 +305,8 @@ def main():
         "per_epsilon": per_eps,
         "roofline": {"bound": "alu" if fp32 else "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic_for_join(),
+                     "traffic": (traffic_for_join()
+                                 if fp32 and a.workload == "uniform_2m_d16" else None),
                      "kernel": "k_join_fp32" if fp32 else "k_join_mfma",
                      "mean_launch_ms": float(np.mean(join_ms))},
     }

@@ -198,11 +198,11 @@ typedef struct sj_batch_info {
     uint32_t queue_grab;      /* work units a wave takes from the queue at once */
     uint32_t grid;            /* workgroups of the persistent launch */
     uint32_t tuned;           /* 0 defaults, 1 tuned now, 2 taken from the tuning cache */
-    float    ms_build;        /* sum of the jobs' index builds (device events) */
-    float    ms_estimate;     /* sum of the jobs' sampled counts */
+    float    ms_build;        /* sum of the jobs' index builds (device events; builds overlap) */
+    float    ms_estimate;     /* sum of the jobs' sampled counts (device events) */
     float    ms_graph;        /* last replay of the captured graph: join + ids + sort + bounds */
-    float    ms_host_build;   /* wall time of all index builds */
-    float    ms_host_prepare; /* wall time of counting, queue and buffer set-up */
+    float    ms_host_build;   /* wall time of all index builds and sampled counts */
+    float    ms_host_prepare; /* wall time of the job table, queue and buffer set-up */
     float    ms_tune;         /* wall time of the autotuner (0 when cached or off) */
 } sj_batch_info;
 

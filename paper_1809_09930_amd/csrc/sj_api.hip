@@ -20,6 +20,68 @@ namespace sj {
 
 thread_local std::string g_last_error;
 
+Scratch &thread_scratch() {
+  thread_local Scratch s;
+  return s;
+}
+
+void *Scratch::take(size_t bytes) {
+  if (depth <= 0) fail(SJ_ERR_DEVICE, "internal: scratch taken outside a scope");
+  const size_t b = std::max<size_t>(256, (bytes + 255) & ~(size_t)255);
+  while (cur_ < chunks_.size()) {
+    if (used_ + b <= chunks_[cur_].size) {
+      void *p = static_cast<char *>(chunks_[cur_].p) + used_;
+      used_ += b;
+      return p;
+    }
+    ++cur_;
+    used_ = 0;
+  }
+  const size_t size = std::max<size_t>(b, (size_t)8 << 20);
+  void *p = nullptr;
+  if (hipMalloc(&p, size) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(size) + " bytes failed");
+  }
+  chunks_.push_back({p, size});
+  cur_ = chunks_.size() - 1;
+  used_ = b;
+  return p;
+}
+
+void Scratch::release(bool error) {
+  cur_ = 0;
+  used_ = 0;
+  size_t total = 0;
+  for (const Chunk &c : chunks_) total += c.size;
+  // after an error, work that used the temporaries may still be queued:
+  // free everything (a free waits for the device)
+  const size_t keep = error ? 0 : keep_bytes;
+  while (!chunks_.empty() && total > keep) {
+    (void)hipFree(chunks_.back().p);
+    total -= chunks_.back().size;
+    chunks_.pop_back();
+  }
+}
+
+void Scratch::trim() {
+  if (depth > 0) return;
+  const size_t k = keep_bytes;
+  keep_bytes = 0;
+  release(false);
+  keep_bytes = k;
+}
+
+// Kept chunks are freed by trim(); those still held when the thread ends
+// belong to the process until it exits (the HIP runtime may already be gone
+// when thread-local destructors run).
+Scratch::~Scratch() = default;
+
+ScratchScope::~ScratchScope() {
+  Scratch &s = thread_scratch();
+  if (--s.depth == 0) s.release(std::uncaught_exceptions() > uncaught);
+}
+
 [[noreturn]] void fail(int code, const std::string &msg) { throw Error{code, msg}; }
 
 void check_hip(hipError_t e, const char *what) {
@@ -104,9 +166,9 @@ bool make_geometry(const sj_index &ix, uint32_t k, Geometry &g) {
 }
 
 // Temporary buffers of one build.
-struct BuildTmp {
-  DevBuf keys[2], ids[2], flag, radix, scan, small;
-  DevBuf nbr_count, cand_sum, prod;
+struct BuildTmp {  // temporaries of the grid builds (thread scratch)
+  TmpBuf keys[2], ids[2], flag, radix, scan, small;
+  TmpBuf nbr_count, cand_sum, prod;
 };
 
 // Keys, sort, gather, compaction and neighbour counts for geometry g.
@@ -168,7 +230,8 @@ uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t
 // Candidate runs (sym: only cells B >= A) into off/runs.
 uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &t, hipStream_t s) {
   const uint64_t nc = ix.ncell;
-  DevBuf cnt;
+  ScratchScope scope;
+  TmpBuf cnt;
   cnt.alloc((nc + 1) * 4);
   SJ_HIP(hipMemsetAsync(cnt.p, 0, (nc + 1) * 4, s));
   launch_runs(0, sym, nc, ix.cell_start.as<uint32_t>(), ix.nbr_off.as<uint32_t>(),
@@ -191,7 +254,8 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
                          const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
                          DevBuf &out, uint64_t *eval, hipStream_t s) {
   const uint64_t nc = ix.ncell;
-  DevBuf qb_off, run_total, scan, tot;
+  ScratchScope scope;  // every temporary below is dead at the final synchronisation
+  TmpBuf qb_off, run_total, scan, tot;
   qb_off.alloc((nc + 1) * 4);
   run_total.alloc(nc * 8);
   tot.alloc(64);
@@ -205,7 +269,7 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
   SJ_HIP(hipMemcpyAsync(&h_nqb, tot.p, 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
   const uint64_t nqb = h_nqb;
-  DevBuf units, ev;
+  TmpBuf units, ev;
   units.alloc((nqb + 1) * 4);
   ev.alloc((nqb + 1) * 8);
   SJ_HIP(hipMemsetAsync(units.p, 0, (nqb + 1) * 4, s));
@@ -290,7 +354,8 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
   ix.XB.alloc(np * ix.kp * 2);
   ix.thi.alloc(np * 4);
   ix.tlo.alloc(np * 4);
-  DevBuf cdev, norm2, distc, fold, maxima;
+  ScratchScope scope;  // ends after the final synchronisation below
+  TmpBuf cdev, norm2, distc, fold, maxima;
   cdev.alloc(d * 4);
   norm2.alloc(np * 8);
   distc.alloc(np * 8);
@@ -328,6 +393,7 @@ void fill_defaults(sj_options *o) {
 }
 
 void build(sj_index &ix, const float *points, hipStream_t s) {
+  ScratchScope scope;  // temporaries live until the final event synchronisation
   Event ev0, ev1;
   SJ_HIP(hipEventRecord(ev0.e, s));
   const uint64_t n = ix.n;
@@ -349,7 +415,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     return;
   }
   // input on the device (copy host input once)
-  DevBuf staged;
+  TmpBuf staged;
   const float *P = points;
   if (!is_device_pointer(points)) {
     staged.alloc(n * d * sizeof(float));
@@ -357,7 +423,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     P = staged.as<float>();
   }
   // a1/a2: min/max, finiteness, sample variance
-  DevBuf stats;
+  TmpBuf stats;
   stats.alloc(d * 16 + 256);
   uint32_t *gmin = stats.as<uint32_t>();
   uint32_t *gmax = gmin + d;
@@ -422,7 +488,17 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     const uint32_t k1 = std::max(k0, std::min(ix.opt.k_max ? ix.opt.k_max : 8u, kcap));
     double best = 0.0;
     bool have = false;
-    for (uint32_t k = k0; k <= k1; ++k) {
+    // With at most two cells along each of the first k1 reordered dimensions
+    // every pair of cells is adjacent, so C(k) = n^2 for every k, while the
+    // enumeration term grows with k: the model's choice is k0 without
+    // building the other grids.
+    bool all_adjacent = true;
+    for (uint32_t r = 0; r < k1 && all_adjacent; ++r) {
+      const uint32_t t = ix.perm[r];
+      all_adjacent = std::floor((ix.dmax[t] - ix.dmin[t]) / (ix.eps * kWidthSlack)) <= 1.0;
+    }
+    if (all_adjacent && make_geometry(ix, k0, g)) have = true;
+    for (uint32_t k = k0; k <= k1 && !all_adjacent; ++k) {
       Geometry gk;
       if (!make_geometry(ix, k, gk)) break;  // longer keys would overflow: stop
       const uint64_t C = build_grid(ix, P, gk, t, s, false);
@@ -512,15 +588,15 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
   a.rq = fp32_rq_for(ix.dp);
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
-  if (ix.prec != SJ_PREC_FP32 && !count_only) {
+  if (ix.prec != SJ_PREC_FP32) {
     MfmaLaunch m{};
     m.fmt = ix.fmt;
     m.kp = ix.kp;
     m.view = mfma_view(ix, a.runs, a.qlist, sym);
     m.wu = a.wu;
     m.n_wu = a.n_wu;
-    m.out = out;
-    m.capacity = cap;
+    m.out = count_only ? nullptr : out;
+    m.capacity = count_only ? 0 : cap;
     m.cursor = a.cursor;
     m.rechecks = a.rechecks;
     launch_join_mfma(m, s);
@@ -547,13 +623,18 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   const uint64_t target = 8192;
   const uint64_t stride = n <= target ? 1 : n / target;
   const uint64_t nq = (n + stride - 1) / stride;
-  DevBuf ql, wu;
+  ScratchScope scope;  // the read-back of the count below synchronises the stream
+  TmpBuf ql;
+  DevBuf wu;
   ql.alloc(nq * 4);
   launch_iota_strided(ql.as<uint32_t>(), nq, stride, s);
   uint64_t ev = 0;
-  const uint32_t tq = ix.tq;
+  // the matrix-core path counts with its own filter (no keys are stored at
+  // capacity 0); the FP32 path has a count-only kernel
+  const bool mf = ix.prec != SJ_PREC_FP32;
   const uint64_t nwu = build_workunits(ix, 0, ql.as<uint32_t>(), nq, ix.run_off_full,
-                                       ix.runs_full, tq, 4096, wu, &ev, s);
+                                       ix.runs_full, mf ? mfma_wg_queries(ix.kp) : ix.tq,
+                                       mf ? ix.tc_m * 4 : 4096, wu, &ev, s);
   SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
   join_launch(ix, wu, nwu, ix.runs_full, ql.as<uint32_t>(), 0, 1, nullptr, 0, s, ms);
   const uint64_t cnt = read_counter(ix, 0, s);

@@ -16,7 +16,10 @@
 // itself; k is chosen per job by the index build's cost model.  Choices are
 // cached per batch signature in the process and, when SJ_TUNE_CACHE names a
 // file, on disk.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <exception>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
@@ -26,6 +29,7 @@
 #include <numeric>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sj_runtime.hpp"
@@ -68,6 +72,8 @@ namespace sj {
 namespace {
 
 constexpr uint32_t kMaxBatchN = (1u << 20) - 1;  // positions fit 20 bits
+constexpr uint32_t kBuildThreads = 8;             // host threads building job indexes
+constexpr size_t kBuildScratchKeep = (size_t)256 << 20;  // scratch a build thread keeps
 
 __global__ void k_tag_wus(WorkUnit *__restrict__ wu, uint64_t count, uint32_t job) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -272,37 +278,86 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
   uint32_t autotune_on = opts && opts->struct_size >= offsetof(sj_options, mem_budget)
                              ? opts->autotune
                              : 0u;
+  // validate every job first (host only), then build the jobs' indexes and
+  // sampled counts on a few host threads, each with its own stream: the
+  // build of one small job is a chain of short launches and read-backs, so
+  // several chains in flight keep the GPU busy
+  std::vector<sj_options> jopt(njobs);
   for (uint32_t j = 0; j < njobs; ++j) {
     const sj_job &jb = jobs[j];
     if (jb.n > kMaxBatchN)
       fail(SJ_ERR_INVALID_ARG, "batched jobs hold at most 2^20 - 1 points (job " +
                                    std::to_string(j) + ")");
-    sj_options o = checked_options(jb.points, jb.n, jb.d, jb.epsilon, opts);
-    if (o.precision == SJ_PREC_FP32) o.precision = SJ_PREC_FP16;  // matrix-core path only
-    std::unique_ptr<sj_index> ix(new sj_index());
-    ix->device = dev;
-    ix->n = jb.n;
-    ix->d = jb.d;
-    ix->eps = jb.epsilon;
-    ix->eps2 = jb.epsilon * jb.epsilon;
-    ix->opt = o;
-    ix->info.struct_size = sizeof(sj_info);
-    build(*ix, jb.points, b.cs);
-    if (ix->n && batched_variant(ix->kp, ix->fmt) < 0)
-      fail(SJ_ERR_INVALID_ARG, "batched jobs support d up to 77 (job " + std::to_string(j) + ")");
-    b.info.ms_build += ix->info.ms_build;
-    b.jobs[j] = std::move(ix);
+    jopt[j] = checked_options(jb.points, jb.n, jb.d, jb.epsilon, opts);
+    if (jopt[j].precision == SJ_PREC_FP32) jopt[j].precision = SJ_PREC_FP16;  // matrix cores only
+  }
+  std::vector<std::exception_ptr> err(njobs);
+  std::vector<float> ms_est(njobs, 0.0f);
+  std::atomic<uint32_t> next{0};
+  std::atomic<bool> stop{false};
+  auto worker = [&]() {
+    // keep this thread's scratch chunks from one job to the next
+    Scratch &scr = thread_scratch();
+    const size_t keep0 = scr.keep_bytes;
+    scr.keep_bytes = kBuildScratchKeep;
+    hipStream_t ws = nullptr;
+    try {
+      SJ_HIP(hipSetDevice(dev));
+      SJ_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+    } catch (...) {
+      const uint32_t j = next.fetch_add(1);
+      if (j < njobs) err[j] = std::current_exception();
+      stop = true;
+      scr.keep_bytes = keep0;
+      return;
+    }
+    for (;;) {
+      const uint32_t j = next.fetch_add(1);
+      if (j >= njobs || stop) break;
+      try {
+        const sj_job &jb = jobs[j];
+        std::unique_ptr<sj_index> ix(new sj_index());
+        ix->device = dev;
+        ix->n = jb.n;
+        ix->d = jb.d;
+        ix->eps = jb.epsilon;
+        ix->eps2 = jb.epsilon * jb.epsilon;
+        ix->opt = jopt[j];
+        ix->info.struct_size = sizeof(sj_info);
+        build(*ix, jb.points, ws);
+        if (ix->n && batched_variant(ix->kp, ix->fmt) < 0)
+          fail(SJ_ERR_INVALID_ARG,
+               "batched jobs support d up to 77 (job " + std::to_string(j) + ")");
+        if (ix->n) b.est[j] = estimate_pairs(*ix, ws, &ms_est[j]);
+        b.jobs[j] = std::move(ix);
+      } catch (...) {
+        err[j] = std::current_exception();
+        stop = true;
+      }
+    }
+    (void)hipStreamSynchronize(ws);
+    (void)hipStreamDestroy(ws);
+    scr.keep_bytes = keep0;
+    scr.trim();
+  };
+  const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const uint32_t nthr = std::max(1u, std::min({njobs, hw, kBuildThreads}));
+  {
+    std::vector<std::thread> pool;
+    for (uint32_t w = 1; w < nthr; ++w) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+  }
+  for (uint32_t j = 0; j < njobs; ++j)
+    if (err[j]) std::rethrow_exception(err[j]);
+  for (uint32_t j = 0; j < njobs; ++j) {
+    b.info.ms_build += b.jobs[j]->info.ms_build;
+    b.info.ms_estimate += ms_est[j];
   }
   auto t1 = std::chrono::steady_clock::now();
   // pre-size the shared output from every job's sampled count
   uint64_t cap = 1u << 20;
-  for (uint32_t j = 0; j < njobs; ++j) {
-    if (!b.jobs[j]->n) continue;
-    float ms = 0.0f;
-    b.est[j] = estimate_pairs(*b.jobs[j], b.cs, &ms);
-    b.info.ms_estimate += ms;
-    cap += b.est[j] + b.est[j] / 8;
-  }
+  for (uint32_t j = 0; j < njobs; ++j) cap += b.est[j] + b.est[j] / 8;
   // job table
   std::vector<BatchJob> table(njobs);
   for (uint32_t j = 0; j < njobs; ++j) {

@@ -6,6 +6,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <string>
 #include <utility>
 #include <vector>
@@ -44,6 +45,58 @@ struct DevBuf {
   }
   void ensure(size_t b) {
     if (b > bytes || !p) alloc(b);
+  }
+  template <typename T>
+  T *as() const {
+    return static_cast<T *>(p);
+  }
+};
+
+// Per-thread scratch for the temporaries of one index build or sampled
+// count.  Temporaries are bump-allocated from a few large chunks and all die
+// together when the outermost ScratchScope of the thread ends; the code
+// inside a scope synchronises every stream that used them before the scope
+// ends.  This replaces dozens of allocate/free pairs per build (each free
+// waits for the whole device) with a handful of chunk allocations, and with
+// none at all on a thread that keeps its chunks between scopes.
+class Scratch {
+ public:
+  void *take(size_t bytes);
+  // end of the outermost scope: every temporary is dead; keep at most
+  // `keep_bytes` of chunks for the next scope (free the rest)
+  void release(bool error);
+  // free every chunk (no scope open on this thread)
+  void trim();
+  size_t keep_bytes = 0;
+  int depth = 0;
+  ~Scratch();
+
+ private:
+  struct Chunk {
+    void *p;
+    size_t size;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, used_ = 0;
+};
+
+Scratch &thread_scratch();
+
+struct ScratchScope {
+  ScratchScope() { ++thread_scratch().depth; }
+  ~ScratchScope();
+  ScratchScope(const ScratchScope &) = delete;
+  ScratchScope &operator=(const ScratchScope &) = delete;
+  int uncaught = std::uncaught_exceptions();
+};
+
+// A temporary device buffer taken from the thread's scratch (no free).
+struct TmpBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void alloc(size_t b) {
+    p = thread_scratch().take(b);
+    bytes = b;
   }
   template <typename T>
   T *as() const {

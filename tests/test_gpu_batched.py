@@ -116,3 +116,22 @@ def test_batched_argument_errors():
     with pytest.raises(sj.SelfJoinError) as e:
         sj.selfjoin_run_batched([big], [0.1])
     assert e.value.code == sj.SJ_ERR_INVALID_ARG
+
+
+def test_batched_error_in_one_job_of_many():
+    """A job that fails inside the (multi-threaded) index builds fails the
+    whole call with that job's error; the library stays usable."""
+    from paper_1809_09930_amd import selfjoin as sj
+    good = [torch.from_numpy(datagen.uniform_grid(500 + 50 * i, 8, 40 + i)).cuda()
+            for i in range(12)]
+    bad = good[7].clone()
+    bad[3, 2] = float("nan")
+    with pytest.raises(sj.SelfJoinError) as e:
+        sj.selfjoin_run_batched(good[:7] + [bad] + good[8:], [0.3] * 12)
+    assert e.value.code == sj.SJ_ERR_INVALID_ARG
+    assert "NaN" in str(e.value)
+    wide = torch.zeros((40, 90), dtype=torch.float32, device="cuda")
+    with pytest.raises(sj.SelfJoinError) as e:
+        sj.selfjoin_run_batched(good[:5] + [wide] + good[5:], [0.3] * 13)
+    assert e.value.code == sj.SJ_ERR_INVALID_ARG
+    check_batch([(g.cpu().numpy(), 0.3) for g in good[:4]])
