@@ -224,10 +224,13 @@ __global__ __launch_bounds__(kBlock) void k_mfma_thresholds(
 }
 
 // ---------------------------------------------------------------------------
+#ifndef SJ_RECHECK_INLINE
+#define SJ_RECHECK_INLINE __noinline__
+#endif
 // Canonical predicate on positions (caller's dimension order, FP64, no
 // contraction).
 // ---------------------------------------------------------------------------
-__device__ __noinline__ bool canonical_within_m(const float *__restrict__ X, uint32_t a, uint32_t b,
+__device__ SJ_RECHECK_INLINE bool canonical_within_m(const float *__restrict__ X, uint32_t a, uint32_t b,
                                                 const uint16_t *__restrict__ inv_perm, uint32_t d,
                                                 uint32_t dp, double eps2) {
 #pragma clang fp contract(off)
@@ -273,6 +276,137 @@ __device__ __forceinline__ float min16(const float16v &v) {
   e = __builtin_fminf(__builtin_fminf(e, f), v[15]);
   return __builtin_fminf(a, e);
 }
+
+// Unroll factor of the element loop of the hit path.
+#ifndef SJ_HIT_UNROLL
+#define SJ_HIT_UNROLL 4
+#endif
+#define SJ_PRAGMA_(x) _Pragma(#x)
+#define SJ_UNROLL_(n) SJ_PRAGMA_(unroll n)
+#define SJ_UNROLL(n) SJ_UNROLL_(n)
+
+// Does any element of the QB tiles pass its query's upper threshold?
+template <int QB>
+__device__ __forceinline__ bool tiles_any(const float16v (&acc)[QB], const float (&th)[QB]) {
+  bool any = false;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) any |= (min16(acc[j]) <= th[j]);
+  return any;
+}
+
+// Element-by-element filter of QB tiles with at least one candidate hit.
+// The accumulators are first reduced to two 16-bit masks per tile (at or
+// below the upper and the lower threshold), so the rest of the path holds
+// no accumulator; it runs only for the rare tiles with a hit.  Element e of
+// a lane's tile is candidate row c0 + 8*(e/4) + 4*half + e%4.
+template <int QB>
+__device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const float (&th)[QB],
+                                           const float (&tl)[QB], const uint32_t (&qpos)[QB],
+                                           uint32_t c0, uint32_t cend, uint32_t half,
+                                           const MfmaView &v, Stage &st,
+                                           uint64_t *__restrict__ out, uint64_t capacity,
+                                           unsigned long long *__restrict__ cursor,
+                                           uint64_t &n_recheck) {
+  uint32_t mh[QB], ml[QB];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    uint32_t a = 0, b = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      a |= (acc[j][e] <= th[j] ? 1u : 0u) << e;
+      b |= (acc[j][e] <= tl[j] ? 1u : 0u) << e;
+    }
+    mh[j] = a;
+    ml[j] = b;
+  }
+  const bool sym = v.symmetric != 0;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    SJ_UNROLL(SJ_HIT_UNROLL)
+    for (uint32_t e = 0; e < 16; ++e) {
+      const bool h = ((mh[j] >> e) & 1u) != 0u;
+      if (ballot(h) == 0) continue;
+      const uint32_t cp = c0 + 8u * (e / 4u) + 4u * half + (e % 4u);
+      const bool ok = h && cp < cend && (!sym || qpos[j] <= cp);
+      bool acc_ok = ok && ((ml[j] >> e) & 1u) != 0u;
+      const bool band = ok && !acc_ok;
+      const uint64_t bm = ballot(band);
+      if (bm) {
+        if (band) acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+        n_recheck += (uint64_t)__builtin_popcountll(bm);
+      }
+      const uint64_t am = ballot(acc_ok);
+      if (am == 0) continue;
+      // keys hold cell-order positions; they are mapped to caller indices
+      // before the result is sorted
+      const bool two = acc_ok && sym && qpos[j] != cp;
+      const uint64_t m2 = ballot(two);
+      const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+      if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
+      const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+      if (acc_ok) {
+        st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+        if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
+      }
+      st.cnt += total;
+    }
+  }
+}
+
+// The same filter reading the accumulators element by element (fully
+// unrolled, accumulators live throughout): fewer instructions per hit tile
+// than building the masks, at a higher register count, which matters less
+// when the operands of a long K already dominate the registers.
+template <int QB>
+__device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const float (&th)[QB],
+                                               const float (&tl)[QB],
+                                               const uint32_t (&qpos)[QB], uint32_t c0,
+                                               uint32_t cend, uint32_t half, const MfmaView &v,
+                                               Stage &st, uint64_t *__restrict__ out,
+                                               uint64_t capacity,
+                                               unsigned long long *__restrict__ cursor,
+                                               uint64_t &n_recheck) {
+  const bool sym = v.symmetric != 0;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const bool h = acc[j][e] <= th[j];
+      if (ballot(h) == 0) continue;
+      const uint32_t cp = c0 + 8 * (e / 4) + 4 * half + (e % 4);
+      const bool ok = h && cp < cend && (!sym || qpos[j] <= cp);
+      bool acc_ok = ok && acc[j][e] <= tl[j];
+      const bool band = ok && !acc_ok;
+      const uint64_t bm = ballot(band);
+      if (bm) {
+        if (band) acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+        n_recheck += (uint64_t)__builtin_popcountll(bm);
+      }
+      const uint64_t am = ballot(acc_ok);
+      if (am == 0) continue;
+      const bool two = acc_ok && sym && qpos[j] != cp;
+      const uint64_t m2 = ballot(two);
+      const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+      if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
+      const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+      if (acc_ok) {
+        st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+        if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
+      }
+      st.cnt += total;
+    }
+  }
+}
+
+// K padding above which the workgroup kernel takes the accumulator-based
+// hit path; the persistent batched kernel holds all its variants in one
+// register allocation and keeps the mask path throughout.
+#ifndef SJ_HIT_ACC_ABOVE_KP
+#define SJ_HIT_ACC_ABOVE_KP 64
+#endif
+#ifndef SJ_BATCH_HIT_ACC_ABOVE_KP
+#define SJ_BATCH_HIT_ACC_ABOVE_KP 1024
+#endif
 
 // Walks the 32-row candidate blocks of a work unit, run by run.
 struct BlockIter {
@@ -333,7 +467,6 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
-  const bool sym = v.symmetric != 0;
 
   BlockIter it;
   it.init(wu, v.runs);
@@ -364,42 +497,12 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
 #pragma unroll
       for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
     }
-    bool any = false;
-#pragma unroll
-    for (int j = 0; j < QB; ++j) any |= (min16(acc[j]) <= th[j]);
-    if (ballot(any)) {
-      // some pair of this block may be a result: element by element
-#pragma unroll
-      for (int j = 0; j < QB; ++j) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const bool h = acc[j][e] <= th[j];
-          if (ballot(h) == 0) continue;
-          const uint32_t cp = c + 8 * (e / 4) + 4 * half + (e % 4);
-          const bool ok = h && cp < ce && (!sym || qpos[j] <= cp);
-          bool acc_ok = ok && acc[j][e] <= tl[j];
-          const bool band = ok && !acc_ok;
-          const uint64_t bm = ballot(band);
-          if (bm) {
-            if (band) acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
-            n_recheck += (uint64_t)__builtin_popcountll(bm);
-          }
-          const uint64_t am = ballot(acc_ok);
-          if (am == 0) continue;
-          // keys hold cell-order positions; they are mapped to caller
-          // indices before the result is sorted
-          const bool two = acc_ok && sym && qpos[j] != cp;
-          const uint64_t m2 = ballot(two);
-          const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
-          if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
-          const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
-          if (acc_ok) {
-            st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
-            if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
-          }
-          st.cnt += total;
-        }
-      }
+    if (ballot(tiles_any<QB>(acc, th))) {
+      if constexpr (KP > SJ_BATCH_HIT_ACC_ABOVE_KP)
+        tiles_hits_acc<QB>(acc, th, tl, qpos, c, ce, half, v, st, out, capacity, cursor,
+                           n_recheck);
+      else
+        tiles_hits<QB>(acc, th, tl, qpos, c, ce, half, v, st, out, capacity, cursor, n_recheck);
     }
     if (!more) break;
 #pragma unroll
@@ -433,6 +536,19 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma(MfmaView v, const WorkUnit
 // once into a double-buffered LDS stage (global -> registers during the
 // MFMAs of the previous chunk -> LDS) instead of once per wave.
 constexpr int kChunk = 64;  // candidate rows per LDS stage (2 MFMA row blocks)
+// query column blocks per wave for K padding up to 64, and above
+#ifndef SJ_WG_QB_SMALL
+#define SJ_WG_QB_SMALL 2
+#endif
+#ifndef SJ_WG_QB_LARGE
+#define SJ_WG_QB_LARGE 2
+#endif
+// 1: the MFMAs of a block are issued before the filter of the block before
+// it (two accumulator sets); 0: one block at a time
+#ifndef SJ_WG_PIPE
+#define SJ_WG_PIPE 0
+#endif
+static_assert(kChunk == 64, "the workgroup kernel pipelines exactly two 32-row blocks per chunk");
 
 template <int KP, int FMT, int QB>
 __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
@@ -472,7 +588,6 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
-  const bool sym = v.symmetric != 0;
   Stage st{&stage_mem[w][0], 0u};
   uint64_t n_recheck = 0;
 
@@ -502,75 +617,86 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
       if (e < (uint32_t)CHUNK_VECS) tile[buf][e] = pre[i];
     }
   };
+  // filter of one 32-row block whose MFMA results are in acc; rows from
+  // c0, valid below cend
+  auto epilogue = [&](const float16v(&acc)[QB], uint32_t c0,
+                      uint32_t cend) __attribute__((always_inline)) {
+    if (ballot(tiles_any<QB>(acc, th))) {
+      if constexpr (KP > SJ_HIT_ACC_ABOVE_KP)
+        tiles_hits_acc<QB>(acc, th, tl, qpos, c0, cend, half, v, st, out, capacity, cursor,
+                           n_recheck);
+      else
+        tiles_hits<QB>(acc, th, tl, qpos, c0, cend, half, v, st, out, capacity, cursor,
+                       n_recheck);
+    }
+  };
+  auto block_mfma = [&](int buf, int blk, float16v(&acc)[QB]) __attribute__((always_inline)) {
+    V8 A[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RV + ks * 2 + half];
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      float16v z = {};
+      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
+#pragma unroll
+      for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
+    }
+  };
+
   if (c >= ce) return;  // empty unit (uniform)
   fetch(c);
   store(0);
   __syncthreads();
   int cur = 0;
+  // Software pipeline over the two 32-row blocks of each chunk: the MFMAs
+  // of a block are issued before the filter of the block before it, so the
+  // matrix unit works while the vector ALU runs the filter.  accA holds the
+  // first block of a chunk, accB the second (fixed registers, no copies).
+  float16v accA[QB], accB[QB];
+  uint32_t prev_c0 = 0, prev_end = 0;  // block held in accB
+  bool have_prev = false;
   for (;;) {
     const uint32_t cc = c, cce = ce;
     c += kChunk;
     normalise();
     const bool more = c < ce;
     if (more) fetch(c);
-    for (int blk = 0; blk < kChunk / 32; ++blk) {
-      V8 A[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) A[ks] = tile[cur][(blk * 32 + col) * RV + ks * 2 + half];
-      float16v acc[QB];
-#pragma unroll
-      for (int j = 0; j < QB; ++j) {
-        float16v z = {};
-        acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
-#pragma unroll
-        for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
-      }
-      bool any = false;
-#pragma unroll
-      for (int j = 0; j < QB; ++j) any |= (min16(acc[j]) <= th[j]);
-      if (ballot(any)) {
-        const uint32_t c0 = cc + (uint32_t)blk * 32;
-#pragma unroll
-        for (int j = 0; j < QB; ++j) {
-#pragma unroll
-          for (int e = 0; e < 16; ++e) {
-            const bool h = acc[j][e] <= th[j];
-            if (ballot(h) == 0) continue;
-            const uint32_t cp = c0 + 8 * (e / 4) + 4 * half + (e % 4);
-            const bool ok = h && cp < cce && (!sym || qpos[j] <= cp);
-            bool acc_ok = ok && acc[j][e] <= tl[j];
-            const bool band = ok && !acc_ok;
-            const uint64_t bm = ballot(band);
-            if (bm) {
-              if (band)
-                acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
-              n_recheck += (uint64_t)__builtin_popcountll(bm);
-            }
-            const uint64_t am = ballot(acc_ok);
-            if (am == 0) continue;
-            const bool two = acc_ok && sym && qpos[j] != cp;
-            const uint64_t m2 = ballot(two);
-            const uint32_t total =
-                (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
-            if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
-            const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
-            if (acc_ok) {
-              st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
-              if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
-            }
-            st.cnt += total;
-          }
-        }
-      }
+#if SJ_WG_PIPE
+    block_mfma(cur, 0, accA);
+    if (have_prev) epilogue(accB, prev_c0, prev_end);
+    block_mfma(cur, 1, accB);
+    epilogue(accA, cc, cce);
+    prev_c0 = cc + 32;
+    prev_end = cce;
+    have_prev = true;
+#else
+#pragma nounroll
+    for (int blk = 0; blk < 2; ++blk) {
+      block_mfma(cur, blk, accA);
+      epilogue(accA, cc + 32u * (uint32_t)blk, cce);
     }
+#endif
     if (!more) break;
     store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
   }
+#if SJ_WG_PIPE
+  epilogue(accB, prev_c0, prev_end);
+#else
+  (void)accB;
+  (void)prev_c0;
+  (void)prev_end;
+  (void)have_prev;
+#endif
   flush(st, out, capacity, cursor);
   if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
 }
+
+// query column blocks per wave of the persistent batched kernel
+#ifndef SJ_BATCH_QB
+#define SJ_BATCH_QB 2
+#endif
 
 // Many independent joins in one persistent launch.  Every wave takes
 // `grab` work units at a time from a global queue shared by all jobs and
@@ -581,7 +707,7 @@ __device__ __forceinline__ void batched_dispatch(const MfmaView &v, const WorkUn
                                                  uint64_t *__restrict__ out, uint64_t capacity,
                                                  unsigned long long *__restrict__ cursor,
                                                  uint64_t &n_recheck) {
-  mfma_unit<KP, FMT, (KP <= 64 ? 4 : 2)>(v, wu, st, out, capacity, cursor, n_recheck);
+  mfma_unit<KP, FMT, SJ_BATCH_QB>(v, wu, st, out, capacity, cursor, n_recheck);
 }
 
 __global__ __launch_bounds__(kBlock) void k_join_batched(
@@ -669,7 +795,7 @@ template <int KP, int FMT>
 void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
   if (!grid) return;
-  constexpr int QB = KP <= 64 ? 4 : 2;
+  constexpr int QB = KP <= 64 ? SJ_WG_QB_SMALL : SJ_WG_QB_LARGE;
   MfmaView v = a.view;
   // one workgroup per work unit (4 waves x 32*QB queries)
   hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB>), dim3((uint32_t)a.n_wu), dim3(kBlock), 0, s, v,
@@ -703,9 +829,11 @@ uint32_t mfma_kp(uint32_t d, int fmt) {
   return (k + 15) / 16 * 16;
 }
 
-int mfma_qb(uint32_t kp) { return kp <= 64 ? 4 : 2; }
+int mfma_qb(uint32_t) { return SJ_BATCH_QB; }
 
-uint32_t mfma_wg_queries(uint32_t kp) { return (uint32_t)(kWavesPerBlock * 32 * mfma_qb(kp)); }
+uint32_t mfma_wg_queries(uint32_t kp) {
+  return (uint32_t)(kWavesPerBlock * 32 * (kp <= 64 ? SJ_WG_QB_SMALL : SJ_WG_QB_LARGE));
+}
 
 void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
                       uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,
