@@ -100,6 +100,10 @@ using namespace sj;
 namespace sj {
 
 constexpr double kWidthSlack = 1.0 + 1.0 / (1 << 20);  // cell side = eps * (1 + 2^-20)
+#ifndef SJ_WU_BY_STRETCH
+#define SJ_WU_BY_STRETCH 1
+#endif
+constexpr bool kWuByStretch = SJ_WU_BY_STRETCH != 0;  // join work units in stretch order
 
 // Fine (Morton) ordering inside cells: dimensions and bits per dimension.
 #ifndef SJ_FINE_DIMS
@@ -250,9 +254,13 @@ uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &
 
 // Work units over the given runs; qlist == nullptr: contiguous queries.
 // Returns the number of units; *eval receives the evaluated pair count.
+// With by_stretch, the units are ordered by their stretch index within
+// their query block, then by block: units that run at the same time then
+// read overlapping candidate rows (shared in the caches) instead of every
+// stretch of one block.
 uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
                          const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
-                         DevBuf &out, uint64_t *eval, hipStream_t s) {
+                         DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch = false) {
   const uint64_t nc = ix.ncell;
   ScratchScope scope;  // every temporary below is dead at the final synchronisation
   TmpBuf qb_off, run_total, scan, tot;
@@ -288,9 +296,28 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
   const uint64_t n_wu = (uint32_t)h[0];
   *eval = h[1];
   out.alloc(n_wu * sizeof(WorkUnit));
-  launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
-                 qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
-                 run_total.as<uint64_t>(), units.as<uint32_t>(), out.as<WorkUnit>(), s);
+  if (by_stretch && n_wu > 1) {
+    TmpBuf unordered, keys[2], rtmp;
+    unordered.alloc(n_wu * sizeof(WorkUnit));
+    keys[0].alloc(n_wu * 8);
+    keys[1].alloc(n_wu * 8);
+    launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+                   qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
+                   run_total.as<uint64_t>(), units.as<uint32_t>(), unordered.as<WorkUnit>(),
+                   keys[0].as<uint64_t>(), s);
+    // stable LSD sort on the stretch index (high word) keeps block order
+    std::vector<int> sh;
+    for (uint32_t b = 0; b < bits_for(n_wu - 1); b += 8) sh.push_back(32 + (int)b);
+    rtmp.alloc(radix_tmp_bytes(n_wu));
+    uint64_t *kb[2] = {keys[0].as<uint64_t>(), keys[1].as<uint64_t>()};
+    radix_sort_u64(kb, nullptr, n_wu, sh.data(), (int)sh.size(), rtmp.p, s);
+    launch_gather_wu(unordered.as<WorkUnit>(), kb[0], n_wu, out.as<WorkUnit>(), s);
+  } else {
+    launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+                   qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
+                   run_total.as<uint64_t>(), units.as<uint32_t>(), out.as<WorkUnit>(), nullptr,
+                   s);
+  }
   SJ_HIP(hipStreamSynchronize(s));
   return n_wu;
 }
@@ -342,16 +369,17 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
     n_bound += h * h;
   }
   int fmt = ix.opt.precision == SJ_PREC_FP16 ? kFmtF16 : kFmtBF16;
-  if (fmt == kFmtF16 && (max_abs > 8192.0 || n_bound > 30000.0)) fmt = kFmtBF16;
+  if (fmt == kFmtF16 && max_abs > 8192.0) fmt = kFmtBF16;  // -2 x~ must fit FP16
   if (fmt == kFmtBF16 && (max_abs > 1e15 || n_bound > 1e30))
     fail(SJ_ERR_INVALID_ARG, "coordinates too large for the 16-bit matrix path; use SJ_PREC_FP32");
   ix.fmt = fmt;
   ix.prec = fmt == kFmtF16 ? SJ_PREC_FP16 : SJ_PREC_BF16;
-  ix.kp = mfma_kp(d, fmt);
+  ix.kp = mfma_kp(d);
   ix.n_pad = (ix.n + 31) / 32 * 32 + 64;  // chunks of 64 rows read past a run's end
   const uint64_t np = ix.n_pad;
   ix.XA.alloc(np * ix.kp * 2);
   ix.XB.alloc(np * ix.kp * 2);
+  ix.cn.alloc(np * 4);
   ix.thi.alloc(np * 4);
   ix.tlo.alloc(np * 4);
   ScratchScope scope;  // ends after the final synchronisation below
@@ -363,8 +391,8 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
   maxima.alloc(64);
   SJ_HIP(hipMemcpyAsync(cdev.p, centre.data(), d * 4, hipMemcpyHostToDevice, s));
   launch_mfma_prep(fmt, ix.X.as<float>(), ix.n, np, d, ix.dp, ix.kp, cdev.as<float>(), ix.XA.p,
-                   ix.XB.p, norm2.as<double>(), distc.as<double>(), fold.as<double>(),
-                   maxima.as<unsigned long long>(), s);
+                   ix.XB.p, ix.cn.as<float>(), norm2.as<double>(), distc.as<double>(),
+                   fold.as<double>(), maxima.as<unsigned long long>(), s);
   MfmaBand band;
   const double u16 = fmt == kFmtF16 ? std::ldexp(1.0, -11) : std::ldexp(1.0, -8);
   band.u = (1.0 + std::ldexp(1.0, -24)) * (1.0 + u16) - 1.0;
@@ -526,7 +554,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s);
   ix.tc = choose_tc(ev, ix.tq);
   ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc, ix.wu,
-                            &ix.evaluated_sym, s);
+                            &ix.evaluated_sym, s, kWuByStretch);
   if (ix.opt.precision != SJ_PREC_FP32) {
     mfma_prepare(ix, s);
     ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);         // per wave (batched kernel)
@@ -534,7 +562,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     ix.tc_m = choose_tc(ev, ix.tq_m);
     const uint32_t tc_wg = std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
     ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, tq_wg, tc_wg,
-                                ix.wu_m, &ix.evaluated_sym_m, s);
+                                ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch);
   }
 
   SJ_HIP(hipEventRecord(ev1.e, s));
@@ -546,6 +574,7 @@ MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist,
   MfmaView v{};
   v.XA = ix.XA.p;
   v.XB = ix.XB.p;
+  v.cn = ix.cn.as<float>();
   v.thi = ix.thi.as<float>();
   v.tlo = ix.tlo.as<float>();
   v.X = ix.X.as<float>();
@@ -745,7 +774,7 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
       const bool mf = ix.prec != SJ_PREC_FP32;
       const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
                                            ix.runs_full, mf ? mfma_wg_queries(ix.kp) : ix.tq,
-                                           mf ? ix.tc_m * 4 : ix.tc, wu, &ev, s);
+                                           mf ? ix.tc_m * 4 : ix.tc, wu, &ev, s, kWuByStretch);
       evaluated += ev;
       Slot &sl = slots[slot & 1];
       if (sl.busy) {

@@ -394,7 +394,8 @@ __global__ __launch_bounds__(kBlock) void k_wu_fill(
     const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qlist, uint64_t nq,
     const uint32_t *__restrict__ qb_off, const uint32_t *__restrict__ run_off,
     const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_total,
-    const uint32_t *__restrict__ unit_off, WorkUnit *__restrict__ wu) {
+    const uint32_t *__restrict__ unit_off, WorkUnit *__restrict__ wu,
+    uint64_t *__restrict__ order_key) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= nqb_total) return;
   const QBlock b = query_block(t, sym, ncell, tq, cell_start, qlist, nq, qb_off, run_off, runs,
@@ -424,9 +425,20 @@ __global__ __launch_bounds__(kBlock) void k_wu_fill(
     }
     x.run_last = r;
     x.c_end = c;
+    // optional order key: stretch index within the block, then unit index
+    if (order_key) order_key[w] = ((uint64_t)u << 32) | w;
     wu[w++] = x;
     if (c == runs[r].y && r + 1 < r1) { ++r; c = runs[r].x; }
   }
+}
+
+// dst[i] = src[low 32 bits of keys[i]]
+__global__ __launch_bounds__(kBlock) void k_gather_wu(const WorkUnit *__restrict__ src,
+                                                      const uint64_t *__restrict__ keys,
+                                                      uint64_t n, WorkUnit *__restrict__ dst) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = src[(uint32_t)keys[i]];
 }
 
 __global__ void k_cell_products(uint64_t ncell, const uint32_t *__restrict__ cell_start,
@@ -533,11 +545,18 @@ void launch_wu_fill(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, ui
                     const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
                     const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
                     const uint64_t *run_total, const uint32_t *unit_off, WorkUnit *wu,
-                    hipStream_t s) {
+                    uint64_t *order_key, hipStream_t s) {
   if (!nqb_total) return;
   hipLaunchKernelGGL(k_wu_fill, dim3(blocks_for(nqb_total)), dim3(kBlock), 0, s, nqb_total, sym,
                      ncell, tq, tc, cell_start, qlist, nq, qb_off, run_off, runs, run_total,
-                     unit_off, wu);
+                     unit_off, wu, order_key);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_gather_wu(const WorkUnit *src, const uint64_t *keys, uint64_t n, WorkUnit *dst,
+                      hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_gather_wu, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, keys, n, dst);
   SJ_HIP(hipGetLastError());
 }
 

@@ -70,7 +70,11 @@ void launch_wu_fill(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, ui
                     const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
                     const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
                     const uint64_t *run_total, const uint32_t *unit_off, WorkUnit *wu,
+                    uint64_t *order_key,
                     hipStream_t s);
+// dst[i] = src[(uint32_t)keys[i]] (work units in the order of sorted keys)
+void launch_gather_wu(const WorkUnit *src, const uint64_t *keys, uint64_t n, WorkUnit *dst,
+                      hipStream_t s);
 void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
                           uint64_t *out, hipStream_t s);
 

@@ -38,6 +38,7 @@ constexpr int kStage = 512;
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float float16v __attribute__((ext_vector_type(16)));
+typedef float float4v __attribute__((ext_vector_type(4)));
 
 template <int FMT>
 struct Fmt;
@@ -45,7 +46,6 @@ template <>
 struct Fmt<kFmtF16> {
   typedef _Float16 T;
   typedef half8 V8;
-  static constexpr int kPieces = 2;
   __device__ static T inf() { return (T)__builtin_inff(); }
   __device__ static float16v mfma(V8 a, V8 b, float16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -55,7 +55,6 @@ template <>
 struct Fmt<kFmtBF16> {
   typedef __bf16 T;
   typedef bf16x8 V8;
-  static constexpr int kPieces = 3;
   __device__ static T inf() { return (T)__builtin_inff(); }
   __device__ static float16v mfma(V8 a, V8 b, float16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -80,7 +79,7 @@ template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_mfma_prep(
     const float *__restrict__ X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
     uint32_t kp, const float *__restrict__ centre, typename Fmt<FMT>::T *__restrict__ XA,
-    typename Fmt<FMT>::T *__restrict__ XB, double *__restrict__ norm2,
+    typename Fmt<FMT>::T *__restrict__ XB, float *__restrict__ cn, double *__restrict__ norm2,
     double *__restrict__ dist_c, double *__restrict__ fold_err,
     unsigned long long *__restrict__ maxima) {
   typedef typename Fmt<FMT>::T T;
@@ -93,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_mfma_prep(
       a[k] = (T)0.0f;
       b[k] = (T)0.0f;
     }
-    a[d] = Fmt<FMT>::inf();
+    cn[p] = __builtin_inff();
     return;
   }
   const float *x = X + p * dp;
@@ -108,21 +107,17 @@ __global__ __launch_bounds__(kBlock) void k_mfma_prep(
     const double e = (double)x[t] - (double)centre[t];
     dc += e * e;
   }
-  // exact pieces of the norm: n = h1 + h2 (+ h3) + residual
-  double r = nn;
-  for (int i = 0; i < Fmt<FMT>::kPieces; ++i) {
-    const T h = quantise<FMT>(r);
-    a[d + i] = h;
-    b[d + i] = (T)1.0f;
-    r -= (double)(float)h;
-  }
-  for (uint32_t k = d + Fmt<FMT>::kPieces; k < kp; ++k) {
+  for (uint32_t k = d; k < kp; ++k) {
     a[k] = (T)0.0f;
     b[k] = (T)0.0f;
   }
+  // the candidate's norm enters the MFMA as its initial accumulator,
+  // rounded to FP32; the rounding is the "fold" error of the bound
+  const float h = (float)nn;
+  cn[p] = h;
   norm2[p] = nn;
   dist_c[p] = __builtin_sqrt(dc);
-  fold_err[p] = __builtin_fabs(r);
+  fold_err[p] = __builtin_fabs(nn - (double)h);
 }
 
 // Maxima of |x - c|, |x~|, n and the fold residual over all points.
@@ -165,9 +160,9 @@ __global__ __launch_bounds__(kBlock) void k_mfma_maxima(uint64_t n, const double
 //   triangle inequality |sqrt(S_q) - sqrt(S)| <= Delta_b =
 //   u (|b-c| + R) + 2 eta sqrt(d), R = max over points of |x-c|.
 //   D = n_a - 2 a~.b~ up to E' = gamma_K(2^-23)(N + F + 2 |b~| Rq) + F + 2^-120
-//   (FP32 accumulation of K exact products in any order, even with
-//   truncating adds; N, Rq, F = maxima of n_a, |a~|, fold residual), and
-//   S_q = D_exact + n_b.
+//   (the MFMA starts from fl32(n_a) and adds K exact products in FP32 in
+//   any order, even with truncating adds; N, Rq, F = maxima of n_a, |a~|
+//   and |n_a - fl32(n_a)|), and S_q = D_exact + n_b.
 // Then
 //   Thi(b) = (sqrt(s_hi) + Delta_b)^2 - n_b + E'   (canonical accept => D <= Thi)
 //   Tlo(b) = (max(0, sqrt(s_lo) - Delta_b))^2 - n_b - E'   (D <= Tlo => accept)
@@ -284,6 +279,22 @@ __device__ __forceinline__ float min16(const float16v &v) {
 #define SJ_PRAGMA_(x) _Pragma(#x)
 #define SJ_UNROLL_(n) SJ_PRAGMA_(unroll n)
 #define SJ_UNROLL(n) SJ_UNROLL_(n)
+
+// Initial accumulator of a 32-row block: element e of a lane belongs to row
+// 8*(e/4) + 4*half + e%4, so the lane reads four aligned groups of four
+// candidate norms.
+__device__ __forceinline__ float16v norm_init(const float *__restrict__ nrm32, uint32_t half) {
+  float16v c;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4v q = *reinterpret_cast<const float4v *>(nrm32 + 8 * g + 4 * half);
+    c[4 * g + 0] = q[0];
+    c[4 * g + 1] = q[1];
+    c[4 * g + 2] = q[2];
+    c[4 * g + 3] = q[3];
+  }
+  return c;
+}
 
 // Does any element of the QB tiles pass its query's upper threshold?
 template <int QB>
@@ -402,7 +413,7 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
 // hit path; the persistent batched kernel holds all its variants in one
 // register allocation and keeps the mask path throughout.
 #ifndef SJ_HIT_ACC_ABOVE_KP
-#define SJ_HIT_ACC_ABOVE_KP 64
+#define SJ_HIT_ACC_ABOVE_KP 48
 #endif
 #ifndef SJ_BATCH_HIT_ACC_ABOVE_KP
 #define SJ_BATCH_HIT_ACC_ABOVE_KP 1024
@@ -441,6 +452,7 @@ struct BlockIter {
 // keys key_hi | pos_q << pshift | pos_c.
 template <int KP, int FMT, int QB>
 __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu, Stage &st,
+                                          float *__restrict__ nrm,
                                           uint64_t *__restrict__ out, uint64_t capacity,
                                           unsigned long long *__restrict__ cursor,
                                           uint64_t &n_recheck) {
@@ -475,25 +487,34 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
   // before the current block's MFMAs so their latency overlaps the math.
   // Rows past the end of the run (at most 31, inside the padded arrays)
   // are dropped in the hit path.
+  // The block's candidate norms (the MFMA's initial accumulator) go
+  // through the wave's 32-float LDS area, from one row per lane to the
+  // accumulator layout.
   V8 A[KS];
   uint32_t c = it.c, ce = it.ce;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) A[ks] = XA[(uint64_t)(c + col) * RV + ks * 2 + half];
+  float nc = v.cn[c + col];
   it.advance();
   for (;;) {
     const bool more = it.valid();
     V8 An[KS];
-    const uint32_t cn = it.c, cen = it.ce;
+    float ncn = 0.0f;
+    const uint32_t cnext = it.c, cen = it.ce;
     if (more) {
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) An[ks] = XA[(uint64_t)(cn + col) * RV + ks * 2 + half];
+      for (int ks = 0; ks < KS; ++ks) An[ks] = XA[(uint64_t)(cnext + col) * RV + ks * 2 + half];
+      ncn = v.cn[cnext + col];
       it.advance();
     }
+    if (half == 0) nrm[col] = nc;
+    __builtin_amdgcn_wave_barrier();
+    const float16v c0 = norm_init(nrm, half);
+    __builtin_amdgcn_wave_barrier();
     float16v acc[QB];
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
-      float16v z = {};
-      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
+      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], c0);
 #pragma unroll
       for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
     }
@@ -507,27 +528,10 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
     if (!more) break;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) A[ks] = An[ks];
-    c = cn;
+    nc = ncn;
+    c = cnext;
     ce = cen;
   }
-}
-
-template <int KP, int FMT, int QB>
-__global__ __launch_bounds__(kBlock) void k_join_mfma(MfmaView v, const WorkUnit *__restrict__ wus,
-                                                      uint64_t n_wu, uint64_t *__restrict__ out,
-                                                      uint64_t capacity,
-                                                      unsigned long long *__restrict__ cursor,
-                                                      unsigned long long *__restrict__ rechecks) {
-  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  const uint32_t w = uniform_u32(threadIdx.x / kWave);
-  const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
-  if (u >= n_wu) return;  // whole wave leaves; no workgroup barrier follows
-  const WorkUnit wu = wus[u];
-  Stage st{&stage_mem[w][0], 0u};
-  uint64_t n_recheck = 0;
-  mfma_unit<KP, FMT, QB>(v, wu, st, out, capacity, cursor, n_recheck);
-  flush(st, out, capacity, cursor);
-  if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
 }
 
 // Workgroup-cooperative form of the same filter for a single join: the 4
@@ -564,6 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   constexpr int PER_THREAD = (CHUNK_VECS + kBlock - 1) / kBlock;
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
   __shared__ V8 tile[2][CHUNK_VECS];
+  __shared__ __align__(16) float tile_n[2][kChunk];  // candidate norms of the chunk
   const uint64_t u = blockIdx.x;
   if (u >= n_wu) return;  // whole workgroup leaves together
   const WorkUnit wu = wus[u];
@@ -603,12 +608,14 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   };
   normalise();
   V8 pre[PER_THREAD];
+  float pre_n = 0.0f;
   auto fetch = [&](uint32_t base) {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
       if (e < (uint32_t)CHUNK_VECS) pre[i] = XA[(uint64_t)base * RV + e];
     }
+    if (threadIdx.x < (uint32_t)kChunk) pre_n = v.cn[base + threadIdx.x];
   };
   auto store = [&](int buf) {
 #pragma unroll
@@ -616,6 +623,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
       const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
       if (e < (uint32_t)CHUNK_VECS) tile[buf][e] = pre[i];
     }
+    if (threadIdx.x < (uint32_t)kChunk) tile_n[buf][threadIdx.x] = pre_n;
   };
   // filter of one 32-row block whose MFMA results are in acc; rows from
   // c0, valid below cend
@@ -634,10 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
     V8 A[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RV + ks * 2 + half];
+    const float16v c0 = norm_init(&tile_n[buf][blk * 32], half);
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
-      float16v z = {};
-      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], z);
+      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], c0);
 #pragma unroll
       for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
     }
@@ -695,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
 
 // query column blocks per wave of the persistent batched kernel
 #ifndef SJ_BATCH_QB
-#define SJ_BATCH_QB 2
+#define SJ_BATCH_QB 1
 #endif
 
 // Many independent joins in one persistent launch.  Every wave takes
@@ -704,10 +712,11 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
 // wave leaves once the queue is exhausted, so the grid drains by itself.
 template <int KP, int FMT>
 __device__ __forceinline__ void batched_dispatch(const MfmaView &v, const WorkUnit &wu, Stage &st,
+                                                 float *__restrict__ nrm,
                                                  uint64_t *__restrict__ out, uint64_t capacity,
                                                  unsigned long long *__restrict__ cursor,
                                                  uint64_t &n_recheck) {
-  mfma_unit<KP, FMT, SJ_BATCH_QB>(v, wu, st, out, capacity, cursor, n_recheck);
+  mfma_unit<KP, FMT, SJ_BATCH_QB>(v, wu, st, nrm, out, capacity, cursor, n_recheck);
 }
 
 __global__ __launch_bounds__(kBlock) void k_join_batched(
@@ -717,6 +726,8 @@ __global__ __launch_bounds__(kBlock) void k_join_batched(
     unsigned long long *__restrict__ rechecks) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
   const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  __shared__ __align__(16) float nrm_mem[kWavesPerBlock][32];
+  float *nrm = &nrm_mem[w][0];
   Stage st{&stage_mem[w][0], 0u};
   uint64_t n_recheck = 0;
   const uint64_t capacity = *capacity_p;
@@ -732,16 +743,16 @@ __global__ __launch_bounds__(kBlock) void k_join_batched(
       MfmaView v = jobs[job].view;
       v.key_hi = (uint64_t)job << 40;
       switch (jobs[job].variant) {
-        case 0: batched_dispatch<16, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 1: batched_dispatch<32, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 2: batched_dispatch<48, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 3: batched_dispatch<64, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 4: batched_dispatch<80, kFmtF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 5: batched_dispatch<16, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 6: batched_dispatch<32, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 7: batched_dispatch<48, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 8: batched_dispatch<64, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
-        case 9: batched_dispatch<80, kFmtBF16>(v, wu, st, out, capacity, cursor, n_recheck); break;
+        case 0: batched_dispatch<16, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 1: batched_dispatch<32, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 2: batched_dispatch<48, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 3: batched_dispatch<64, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 4: batched_dispatch<80, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 5: batched_dispatch<16, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 6: batched_dispatch<32, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 7: batched_dispatch<48, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 8: batched_dispatch<64, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 9: batched_dispatch<80, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
         default: break;
       }
     }
@@ -822,12 +833,7 @@ void launch_fmt(const MfmaLaunch &a, hipStream_t s) {
 
 }  // namespace
 
-int mfma_pieces(int fmt) { return fmt == kFmtF16 ? 2 : 3; }
-
-uint32_t mfma_kp(uint32_t d, int fmt) {
-  const uint32_t k = d + (uint32_t)mfma_pieces(fmt);
-  return (k + 15) / 16 * 16;
-}
+uint32_t mfma_kp(uint32_t d) { return (d + 15) / 16 * 16; }
 
 int mfma_qb(uint32_t) { return SJ_BATCH_QB; }
 
@@ -836,18 +842,19 @@ uint32_t mfma_wg_queries(uint32_t kp) {
 }
 
 void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
-                      uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,
-                      double *dist_c, double *fold_err, unsigned long long *maxima,
-                      hipStream_t s) {
+                      uint32_t kp, const float *centre, void *XA, void *XB, float *cn,
+                      double *norm2, double *dist_c, double *fold_err,
+                      unsigned long long *maxima, hipStream_t s) {
   const uint32_t grid = (uint32_t)((n_pad + kBlock - 1) / kBlock);
   if (!grid) return;
   if (fmt == kFmtF16)
     hipLaunchKernelGGL(k_mfma_prep<kFmtF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
-                       kp, centre, (_Float16 *)XA, (_Float16 *)XB, norm2, dist_c, fold_err,
+                       kp, centre, (_Float16 *)XA, (_Float16 *)XB, cn, norm2, dist_c, fold_err,
                        maxima);
   else
     hipLaunchKernelGGL(k_mfma_prep<kFmtBF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
-                       kp, centre, (__bf16 *)XA, (__bf16 *)XB, norm2, dist_c, fold_err, maxima);
+                       kp, centre, (__bf16 *)XA, (__bf16 *)XB, cn, norm2, dist_c, fold_err,
+                       maxima);
   SJ_HIP(hipGetLastError());
   SJ_HIP(hipMemsetAsync(maxima, 0, 4 * sizeof(unsigned long long), s));
   const uint32_t g2 = (uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);

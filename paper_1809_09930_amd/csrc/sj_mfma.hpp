@@ -19,6 +19,7 @@ struct MfmaBand {
 // Everything a work unit of the matrix-core filter reads.
 struct MfmaView {
   const void *XA, *XB;      // [n_pad][kp] 16-bit operands (candidate rows / query columns)
+  const float *cn;          // [n_pad] candidate norms, the MFMA's initial accumulator
   const float *thi, *tlo;   // per-point thresholds
   const float *X;           // FP32 rows (recheck)
   const uint16_t *inv_perm;
@@ -50,15 +51,15 @@ struct BatchJob {
   uint32_t pad;
 };
 
-int mfma_pieces(int fmt);
-uint32_t mfma_kp(uint32_t d, int fmt);
+uint32_t mfma_kp(uint32_t d);
 int mfma_qb(uint32_t kp);
 // Query slots of one work unit of the single-join matrix kernel (a whole
 // workgroup); the batched kernel uses 32*mfma_qb per wave.
 uint32_t mfma_wg_queries(uint32_t kp);
 void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
-                      uint32_t kp, const float *centre, void *XA, void *XB, double *norm2,
-                      double *dist_c, double *fold_err, unsigned long long *maxima, hipStream_t s);
+                      uint32_t kp, const float *centre, void *XA, void *XB, float *cn,
+                      double *norm2, double *dist_c, double *fold_err,
+                      unsigned long long *maxima, hipStream_t s);
 void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, const double *norm2,
                             const double *dist_c, const unsigned long long *maxima, float *thi,
                             float *tlo, hipStream_t s);

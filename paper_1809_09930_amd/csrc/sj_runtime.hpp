@@ -217,7 +217,7 @@ struct sj_index {
   int fmt = 0;
   uint32_t kp = 0;
   uint64_t n_pad = 0;
-  DevBuf XA, XB, thi, tlo;
+  DevBuf XA, XB, cn, thi, tlo;  // 16-bit operands, FP32 candidate norms, thresholds
   DevBuf wu_m;
   uint64_t n_wu_m = 0, evaluated_sym_m = 0;
   uint32_t tq_m = 128, tc_m = 4096;
