@@ -85,11 +85,25 @@ typedef struct sj_options {
     uint32_t min_batches;   /* minimum number of batches n_b (Section 3.2.2 uses >= 3); 0 or 1 = as few as possible */
     uint32_t autotune;      /* selfjoin_run_batched only: 1 = time candidate tile lengths and queue granularities on the batch and keep the fastest */
     uint64_t mem_budget;    /* device bytes the result buffers may use; 0 = a default share of free device memory */
+    uint32_t fp32_form;     /* SJ_PREC_FP32 arithmetic: enum sj_fp32_form */
+    uint32_t reserved0;     /* must be 0 */
 } sj_options;
+
+/* How the FP32 filter evaluates squared distances.  Both are exact filters
+ * (their FP32 error is bounded and pairs inside the bound are rechecked in
+ * FP64); they differ in speed only.
+ *   DIFFERENCE: sum of (a_t - b_t)^2, two vector operations per dimension.
+ *   NORM:       |a|^2 + |b|^2 - 2 a.b from per-point prefix norms, one fused
+ *               multiply-add per dimension; its error grows with the norms, so
+ *               AUTO takes it only up to 16 dimensions and when the band
+ *               stays narrow against eps^2. */
+enum sj_fp32_form { SJ_FP32_AUTO = 0, SJ_FP32_DIFFERENCE = 1, SJ_FP32_NORM = 2 };
 
 /* Fills *opts with the defaults: k = 0 (auto, 4..8), reorder = 1,
  * shortc = 1, precision = SJ_PREC_FP32, batch_pairs = 0, min_batches = 0,
- * mem_budget = 0. */
+ * mem_budget = 0, fp32_form = SJ_FP32_AUTO.  Callers built against an
+ * older header may pass a shorter struct (struct_size); missing fields take
+ * their defaults. */
 void selfjoin_default_options(sj_options *opts);
 
 /*
@@ -152,7 +166,7 @@ typedef struct sj_info {
     float    ms_sort;         /* device time of result sorting of the last run */
     float    ms_run;          /* device time of the whole last run */
     uint32_t join_launches;   /* launches of the distance kernel in the last run */
-    uint32_t reserved;
+    uint32_t fp32_form;       /* form of the FP32 filter (enum sj_fp32_form; 0 on the matrix-core path) */
 } sj_info;
 
 /* info->struct_size must be set by the caller. */

@@ -408,6 +408,49 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
   SJ_HIP(hipStreamSynchronize(s));
 }
 
+// Form of the FP32 filter: the norm form when asked for, or (automatic) up
+// to 16 padded dimensions when its error margin for a pair of mean squared
+// norm stays below a small fraction of eps^2 (a wider band only sends more
+// pairs to the FP64 recheck; either form gives the same result).  Above 16
+// dimensions its extra checkpoint work made it slower than the difference
+// form in every measured case.
+constexpr double kNormBandMax = 0.005;
+constexpr uint32_t kNormAutoMaxDp = 16;
+
+void choose_fp32_form(sj_index &ix, hipStream_t s) {
+  ix.norm_form = false;
+  ix.info.fp32_form = SJ_FP32_DIFFERENCE;
+  if (ix.opt.fp32_form == SJ_FP32_DIFFERENCE || ix.n == 0) return;
+  if (ix.opt.fp32_form == SJ_FP32_AUTO && ix.dp > kNormAutoMaxDp) return;
+  const double g64 = gamma_n((double)ix.d + 2.0, std::ldexp(1.0, -53));
+  const double margin = std::ldexp(1.0, -50);
+  const double s_hi = ix.eps2 / (1.0 - g64) * (1.0 + margin);
+  const double s_lo = ix.eps2 / (1.0 + g64) * (1.0 - margin);
+  const double kappa = 4.0 * gamma_n((double)ix.dp + 16.0, std::ldexp(1.0, -24));
+  if (!(s_hi < 1e30)) return;  // keep the difference form for huge thresholds
+  const uint64_t row = (uint64_t)norm_table_row(ix.dp);
+  ix.norm_qa.alloc(ix.n * row * 4);
+  ix.norm_cr.alloc((ix.n + 1) * row * 4);  // + one row the join kernel may read ahead
+  ScratchScope scope;  // the read-back below synchronises the stream
+  TmpBuf nsum;
+  nsum.alloc(8);
+  SJ_HIP(hipMemsetAsync(nsum.p, 0, 8, s));
+  launch_norm_tables(ix.X.as<float>(), ix.n, ix.dp, s_hi, s_lo, kappa, ix.norm_qa.as<float>(),
+                     ix.norm_cr.as<float>(), nsum.as<double>(), s);
+  double h = 0.0;
+  SJ_HIP(hipMemcpyAsync(&h, nsum.p, 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  const double mean = h / (double)ix.n;
+  const bool narrow = kappa * (6.0 * mean + 2.0 * s_hi) <= kNormBandMax * ix.eps2;
+  if (ix.opt.fp32_form == SJ_FP32_NORM || narrow) {
+    ix.norm_form = true;
+    ix.info.fp32_form = SJ_FP32_NORM;
+  } else {
+    ix.norm_qa.reset();
+    ix.norm_cr.reset();
+  }
+}
+
 void fill_defaults(sj_options *o) {
   std::memset(o, 0, sizeof(*o));
   o->precision = SJ_PREC_FP32;
@@ -499,7 +542,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   t.prod.alloc((n + 1) * 8);
   ix.cell_key.alloc((n + 1) * 8);
   ix.cell_start.alloc((n + 1) * 4);
-  ix.X.alloc(n * ix.dp * 4);
+  ix.X.alloc((n + 1) * ix.dp * 4);  // + one row the join kernel may read ahead
   ix.orig_id.alloc(n * 4);
   ix.pos_of.alloc(n * 4);
 
@@ -548,7 +591,8 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   // candidate runs and the work units of the symmetric full join
   ix.n_runs_sym = build_runs(ix, 1, ix.run_off_sym, ix.runs_sym, t, s);
   ix.n_runs_full = build_runs(ix, 0, ix.run_off_full, ix.runs_full, t, s);
-  ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp);
+  if (ix.opt.precision == SJ_PREC_FP32) choose_fp32_form(ix, s);
+  ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form);
   uint64_t ev = 0;
   DevBuf probe;
   build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s);
@@ -614,7 +658,10 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
   a.capacity = cap;
   a.cursor = ix.counters.as<unsigned long long>();
   a.rechecks = ix.counters.as<unsigned long long>() + 1;
-  a.rq = fp32_rq_for(ix.dp);
+  a.rq = fp32_rq_for(ix.dp, ix.norm_form);
+  a.norm = ix.norm_form ? 1 : 0;
+  a.QA = ix.norm_qa.as<float>();
+  a.CR = ix.norm_cr.as<float>();
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
   if (ix.prec != SJ_PREC_FP32) {
@@ -941,6 +988,8 @@ sj_options checked_options(const float *points, uint64_t n, uint32_t d, double e
     o.struct_size = sizeof(o);
   }
   if (o.precision > SJ_PREC_BF16) fail(SJ_ERR_INVALID_ARG, "unknown precision");
+  if (o.fp32_form > SJ_FP32_NORM) fail(SJ_ERR_INVALID_ARG, "unknown fp32_form");
+  if (o.reserved0 != 0) fail(SJ_ERR_INVALID_ARG, "sj_options.reserved0 must be 0");
   if (o.k < 0) fail(SJ_ERR_INVALID_ARG, "k must be >= 0");
   return o;
 }

@@ -132,10 +132,18 @@ struct JoinLaunch {
   unsigned long long *cursor;    // pairs produced (may exceed capacity)
   unsigned long long *rechecks;  // FP64 rechecks performed
   int rq;                   // queries per lane (1, 2 or 4); units hold 64*rq queries
+  int norm;                 // 1: norm form with the tables QA / CR
+  const float *QA, *CR;     // [n][norm_table_row(dp)] query / candidate tables
 };
 
 // Queries per lane the FP32 kernel uses for padded dimension dp.
-int fp32_rq_for(uint32_t dp);
+int fp32_rq_for(uint32_t dp, bool norm);
+// Floats per point in each norm-form table.
+int norm_table_row(uint32_t dp);
+// Builds the norm-form tables of the cell-ordered rows X ([n][dp]) for the
+// bounds s_hi / s_lo and margin factor kappa; *nsum += sum of squared norms.
+void launch_norm_tables(const float *X, uint64_t n, uint32_t dp, double s_hi, double s_lo,
+                        double kappa, float *QA, float *CR, double *nsum, hipStream_t s);
 // Padded dimension count the kernels support for d (0 if unsupported).
 uint32_t padded_dim(uint32_t d);
 void launch_join_fp32(const JoinLaunch &a, hipStream_t s);

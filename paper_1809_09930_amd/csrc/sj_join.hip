@@ -26,6 +26,8 @@
 // a wave-private LDS stage; a full stage is flushed with one atomic on the
 // global cursor and coalesced stores.  Pairs past `capacity` are counted
 // but not stored (the host then grows the buffer and reruns).
+#include <type_traits>
+
 #include "sj_internal.hpp"
 
 namespace sj {
@@ -49,12 +51,45 @@ constexpr int kStage = 512;  // u64 keys staged per wave
 #ifndef SJ_SHORTC_STEP
 #define SJ_SHORTC_STEP 8
 #endif
+// Dimension counts after which the short-circuit test runs (the last one is
+// DP itself); the norm form keeps prefix norms at exactly these counts.
+constexpr int shortc_first(int dp) {
+  return dp < (dp <= 24 ? SJ_SHORTC_FIRST_SMALL : SJ_SHORTC_FIRST)
+             ? dp
+             : (dp <= 24 ? SJ_SHORTC_FIRST_SMALL : SJ_SHORTC_FIRST);
+}
+constexpr int shortc_step(int dp) { return dp <= 24 ? SJ_SHORTC_STEP_SMALL : SJ_SHORTC_STEP; }
+constexpr int n_checkpoints(int dp) {
+  return 1 + (dp - shortc_first(dp) + shortc_step(dp) - 1) / shortc_step(dp);
+}
+constexpr int checkpoint_dim(int dp, int k) {
+  return shortc_first(dp) + k * shortc_step(dp) < dp ? shortc_first(dp) + k * shortc_step(dp)
+                                                     : dp;
+}
+// floats per point in the norm form's two tables (checkpoints + 1, padded)
+constexpr int norm_row(int dp) {
+  return n_checkpoints(dp) + 1 <= 2 ? 2 : (n_checkpoints(dp) + 1 <= 4 ? 4 : (n_checkpoints(dp) + 1 <= 8 ? 8 : 16));
+}
+static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 floats");
+
 // Query points per lane by padded dimension (register blocking).
 #ifndef SJ_FP32_RQ_SMALL
 #define SJ_FP32_RQ_SMALL 2  // dp <= 24
 #endif
 #ifndef SJ_FP32_RQ_MID
 #define SJ_FP32_RQ_MID 1    // dp <= 64
+#endif
+// candidate loop: 0 plain, 1 with a one-candidate look-ahead of the first
+// test's values, 2 the same unrolled by two
+#ifndef SJ_SWEEP_MODE
+#define SJ_SWEEP_MODE 1
+#endif
+// the same for the norm form
+#ifndef SJ_NORM_RQ_SMALL
+#define SJ_NORM_RQ_SMALL 4
+#endif
+#ifndef SJ_NORM_RQ_MID
+#define SJ_NORM_RQ_MID 1
 #endif
 
 // Canonical predicate on positions a, b of the cell-ordered rows.
@@ -97,54 +132,114 @@ __device__ __forceinline__ void stage_flush(WaveStage &st, uint64_t *__restrict_
 
 template <int DP, int RQ>
 struct Lanes {
-  float q[RQ][DP];
+  float q[RQ][DP];   // difference form: the query; norm form: -2 x the query
   uint32_t pos[RQ];  // cell-order position of each query (0xffffffff: empty slot)
   uint32_t id[RQ];   // caller index of each query
-  float init[RQ];    // 0 for a live slot, +inf for an empty one
+  float init[RQ];    // difference form: 0 for a live slot, +inf for an empty one
 };
 
-template <int DP, int RQ, bool kFilter, bool kCount>
-__device__ __forceinline__ void eval_candidate(
-    const Lanes<DP, RQ> &L, uint32_t c, const float *__restrict__ X,
-    const uint32_t *__restrict__ orig_id, const uint16_t *__restrict__ inv_perm, uint32_t d,
-    float lo, float hi, double eps2, bool symmetric, bool shortc,
+template <int DP, int RQ, bool kNorm>
+struct NormLanes {  // norm form: the query's increments of its accumulator
+  float qa[RQ][n_checkpoints(DP) + 1];
+};
+template <int DP, int RQ>
+struct NormLanes<DP, RQ, false> {};
+
+// The candidate values the first test needs (its first coordinates, and the
+// first table value in the norm form), loaded one candidate ahead so the
+// scalar loads overlap the previous candidate's arithmetic.  The arrays
+// hold one row more than there are points, so the look-ahead past the last
+// candidate of a run stays inside them.
+template <int DP, bool kNorm>
+struct Head {
+  float cv[shortc_first(DP)];
+  float ct0;
+};
+template <int DP, bool kNorm>
+__device__ __forceinline__ Head<DP, kNorm> load_head(const float *__restrict__ crow,
+                                                     const float *__restrict__ ccr) {
+  Head<DP, kNorm> h;
+#pragma unroll
+  for (int t = 0; t < shortc_first(DP); ++t) h.cv[t] = crow[t];
+  h.ct0 = kNorm ? ccr[0] : 0.0f;
+  return h;
+}
+
+// Final decision for query group r of a wave against candidate c: m = lanes
+// not rejected, lo_m = lanes proven accepted; the rest of m is rechecked with
+// the canonical FP64 predicate.  Accepted pairs are staged (both orders in
+// symmetric mode), or only counted.
+template <int DP, int RQ, bool kCount>
+__device__ __forceinline__ void classify_emit(
+    const Lanes<DP, RQ> &L, int r, uint32_t c, uint64_t m, uint64_t lo_m,
+    const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
+    const uint16_t *__restrict__ inv_perm, uint32_t d, double eps2, bool symmetric,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
-  constexpr int kFirst0 = DP <= 24 ? SJ_SHORTC_FIRST_SMALL : SJ_SHORTC_FIRST;
-  constexpr int kFirst = DP < kFirst0 ? DP : kFirst0;
-  constexpr int kStep = DP <= 24 ? SJ_SHORTC_STEP_SMALL : SJ_SHORTC_STEP;
-  const float *__restrict__ crow = X + (uint64_t)c * DP;
+  if (m == 0) return;
+  if (kCount) {
+    n_count += (uint64_t)__builtin_popcountll(m);
+    return;
+  }
+  uint64_t acc = m & lo_m;
+  const uint64_t band = m & ~acc;
+  if (band) {
+    bool ok = false;
+    if ((band >> lane_id()) & 1ull) ok = canonical_within(X, L.pos[r], c, inv_perm, d, DP, eps2);
+    acc |= ballot(ok);
+    n_recheck += (uint64_t)__builtin_popcountll(band);
+  }
+  if (acc == 0) return;
+  // emit (query, candidate), and (candidate, query) too in symmetric mode
+  const uint32_t cid = orig_id[c];
+  const bool e1 = (acc >> lane_id()) & 1ull;
+  const bool e2 = e1 && symmetric && L.pos[r] != c;
+  const uint64_t m2 = ballot(e2);
+  const uint32_t total = (uint32_t)(__builtin_popcountll(acc) + __builtin_popcountll(m2));
+  if (st.cnt + total > (uint32_t)kStage) stage_flush(st, out, capacity, cursor);
+  const uint32_t off = st.cnt + lanes_below(acc) + lanes_below(m2);
+  if (e1) {
+    st.buf[off] = ((uint64_t)L.id[r] << 32) | cid;
+    if (e2) st.buf[off + 1] = ((uint64_t)cid << 32) | L.id[r];
+  }
+  st.cnt += total;
+}
+
+template <int DP, int RQ, bool kFilter, bool kCount, bool kSC>
+__device__ __forceinline__ void eval_candidate(
+    const Lanes<DP, RQ> &L, const Head<DP, false> &hd, uint32_t c,
+    const float *__restrict__ crow, const float *__restrict__ X,
+    const uint32_t *__restrict__ orig_id, const uint16_t *__restrict__ inv_perm, uint32_t d,
+    float lo, float hi, double eps2, bool symmetric, WaveStage &st, uint64_t *__restrict__ out,
+    uint64_t capacity, unsigned long long *__restrict__ cursor, uint64_t &n_recheck,
+    uint64_t &n_count) {
+  constexpr int kFirst = shortc_first(DP);
+  constexpr int kStep = shortc_step(DP);
   float s[RQ];
 #pragma unroll
   for (int r = 0; r < RQ; ++r) {
     s[r] = L.init[r];
     if (kFilter) s[r] = (L.pos[r] <= c) ? s[r] : __builtin_inff();
   }
-  uint32_t alive = (1u << RQ) - 1u;
-
   // dimensions [0, kFirst) for every group
-  {
-    float cv[kFirst];
 #pragma unroll
-    for (int t = 0; t < kFirst; ++t) cv[t] = crow[t];
+  for (int r = 0; r < RQ; ++r) {
 #pragma unroll
-    for (int r = 0; r < RQ; ++r) {
-#pragma unroll
-      for (int t = 0; t < kFirst; ++t) {
-        const float diff = L.q[r][t] - cv[t];
-        s[r] = __builtin_fmaf(diff, diff, s[r]);
-      }
+    for (int t = 0; t < kFirst; ++t) {
+      const float diff = L.q[r][t] - hd.cv[t];
+      s[r] = __builtin_fmaf(diff, diff, s[r]);
     }
   }
-  // remaining dimensions in steps of kStep, each preceded by the test
+  // remaining dimensions in steps of kStep, each preceded by the test; the
+  // wave leaves the candidate once no lane of any group is below hi
 #pragma unroll
   for (int t0 = kFirst; t0 < DP; t0 += kStep) {
-    if (shortc) {
+    if (kSC) {
+      // one compare on the lanes' minimum: no scalar mask arithmetic
+      float mn = s[0];
 #pragma unroll
-      for (int r = 0; r < RQ; ++r)
-        if ((alive >> r) & 1u)
-          if (ballot(s[r] <= hi) == 0) alive &= ~(1u << r);
-      if (alive == 0) return;
+      for (int r = 1; r < RQ; ++r) mn = __builtin_fminf(mn, s[r]);
+      if (ballot(mn <= hi) == 0) return;
     }
     // the last step is shorter when kStep does not divide DP (the bounds
     // are compile-time constants once the loops are unrolled)
@@ -154,64 +249,107 @@ __device__ __forceinline__ void eval_candidate(
       if (t0 + t < DP) cv[t] = crow[t0 + t];
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
-      if ((alive >> r) & 1u) {
 #pragma unroll
-        for (int t = 0; t < kStep; ++t) {
-          if (t0 + t < DP) {
-            const float diff = L.q[r][t0 + t] - cv[t];
-            s[r] = __builtin_fmaf(diff, diff, s[r]);
-          }
+      for (int t = 0; t < kStep; ++t) {
+        if (t0 + t < DP) {
+          const float diff = L.q[r][t0 + t] - cv[t];
+          s[r] = __builtin_fmaf(diff, diff, s[r]);
         }
       }
     }
   }
-
   // classification: s > hi rejects, s <= lo accepts, the band is rechecked
+  {
+    float mn = s[0];
+#pragma unroll
+    for (int r = 1; r < RQ; ++r) mn = __builtin_fminf(mn, s[r]);
+    if (ballot(mn <= hi) == 0) return;
+  }
 #pragma unroll
   for (int r = 0; r < RQ; ++r) {
-    if (!((alive >> r) & 1u)) continue;
     const uint64_t m = ballot(s[r] <= hi);
     if (m == 0) continue;
-    if (kCount) {
-      n_count += (uint64_t)__builtin_popcountll(m);
-      continue;
+    classify_emit<DP, RQ, kCount>(L, r, c, m, ballot(s[r] <= lo), X, orig_id, inv_perm, d, eps2,
+                                  symmetric, st, out, capacity, cursor, n_recheck, n_count);
+  }
+}
+
+// Norm form of the same filter.  Each lane's accumulator starts from its
+// query's first table value and takes one fused multiply-add per dimension
+// with -2 x the query coordinate; at checkpoint k it holds (up to a bounded
+// FP32 error) |q|^2_k - 2 q.c_k - s_hi - mu_q,k, and the pair is rejected once
+// it exceeds the candidate's table value -|c|^2_k + mu_c,k, i.e. once the
+// exact partial sum of squares provably exceeds s_hi.  Between checkpoints
+// the accumulator moves to the next reference by one addition; the final
+// test against the candidate's lower value proves acceptance.  The tables
+// and the margins mu come from k_norm_tables.
+template <int DP, int RQ, bool kFilter, bool kCount, bool kSC>
+__device__ __forceinline__ void eval_candidate_norm(
+    const Lanes<DP, RQ> &L, const NormLanes<DP, RQ, true> &N, const Head<DP, true> &hd,
+    uint32_t c, const float *__restrict__ crow, const float *__restrict__ cr,
+    const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
+    const uint16_t *__restrict__ inv_perm, uint32_t d, double eps2, bool symmetric,
+    WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
+    unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
+  constexpr int K = n_checkpoints(DP);
+  float a[RQ];
+#pragma unroll
+  for (int r = 0; r < RQ; ++r) {
+    a[r] = N.qa[r][0];
+    if (kFilter) a[r] = (L.pos[r] <= c) ? a[r] : __builtin_inff();
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int t0 = k == 0 ? 0 : checkpoint_dim(DP, k - 1);
+    const int t1 = checkpoint_dim(DP, k);
+    float cv[DP];  // the candidate's coordinates [t0, t1)
+#pragma unroll
+    for (int t = 0; t < DP; ++t)
+      if (t >= t0 && t < t1) cv[t] = k == 0 ? hd.cv[t < shortc_first(DP) ? t : 0] : crow[t];
+#pragma unroll
+    for (int r = 0; r < RQ; ++r) {
+      if (k > 0) a[r] += N.qa[r][k];
+#pragma unroll
+      for (int t = 0; t < DP; ++t)
+        if (t >= t0 && t < t1) a[r] = __builtin_fmaf(L.q[r][t], cv[t], a[r]);
     }
-    uint64_t acc = m & ballot(s[r] <= lo);
-    const uint64_t band = m & ~acc;
-    if (band) {
-      bool ok = false;
-      if ((band >> lane_id()) & 1ull)
-        ok = canonical_within(X, L.pos[r], c, inv_perm, d, DP, eps2);
-      acc |= ballot(ok);
-      n_recheck += (uint64_t)__builtin_popcountll(band);
+    if (kSC && k + 1 < K) {
+      const float ctk = k == 0 ? hd.ct0 : cr[k];
+      float mn = a[0];
+#pragma unroll
+      for (int r = 1; r < RQ; ++r) mn = __builtin_fminf(mn, a[r]);
+      if (ballot(mn <= ctk) == 0) return;
     }
-    if (acc == 0) continue;
-    // emit (query, candidate), and (candidate, query) too in symmetric mode
-    const uint32_t cid = orig_id[c];
-    const bool e1 = (acc >> lane_id()) & 1ull;
-    const bool e2 = e1 && symmetric && L.pos[r] != c;
-    const uint64_t m2 = ballot(e2);
-    const uint32_t total = (uint32_t)(__builtin_popcountll(acc) + __builtin_popcountll(m2));
-    if (st.cnt + total > (uint32_t)kStage) stage_flush(st, out, capacity, cursor);
-    const uint32_t off = st.cnt + lanes_below(acc) + lanes_below(m2);
-    if (e1) {
-      st.buf[off] = ((uint64_t)L.id[r] << 32) | cid;
-      if (e2) st.buf[off + 1] = ((uint64_t)cid << 32) | L.id[r];
-    }
-    st.cnt += total;
+  }
+  const float rej = K == 1 ? hd.ct0 : cr[K - 1];
+  const float acc_t = cr[K];
+  {
+    float mn = a[0];
+#pragma unroll
+    for (int r = 1; r < RQ; ++r) mn = __builtin_fminf(mn, a[r]);
+    if (ballot(mn <= rej) == 0) return;
+  }
+#pragma unroll
+  for (int r = 0; r < RQ; ++r) {
+    const uint64_t m = ballot(a[r] <= rej);
+    if (m == 0) continue;
+    classify_emit<DP, RQ, kCount>(L, r, c, m, ballot(a[r] + N.qa[r][K] <= acc_t), X, orig_id,
+                                  inv_perm, d, eps2, symmetric, st, out, capacity, cursor,
+                                  n_recheck, n_count);
   }
 }
 
 // One wave = one work unit.  kCount: count the pairs the filter cannot
 // reject (s <= hi) instead of emitting them.
-template <int DP, int RQ, bool kCount>
+template <int DP, int RQ, bool kCount, bool kNorm, bool kSC>
 __device__ __forceinline__ void join_body(
     const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
     const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,
     const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, float lo,
-    float hi, double eps2, int symmetric, int shortc, uint64_t *__restrict__ out,
+    float hi, double eps2, int symmetric, uint64_t *__restrict__ out,
     uint64_t capacity, unsigned long long *__restrict__ cursor,
-    unsigned long long *__restrict__ rechecks, uint64_t (*stage_mem)[kStage]) {
+    unsigned long long *__restrict__ rechecks, uint64_t (*stage_mem)[kStage],
+    const float *__restrict__ QA, const float *__restrict__ CR) {
   const uint32_t w = uniform_u32(threadIdx.x / kWave);
   const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
   if (u >= n_wu) return;  // whole wave leaves; no workgroup barrier follows
@@ -219,6 +357,7 @@ __device__ __forceinline__ void join_body(
   const uint32_t l = lane_id();
 
   Lanes<DP, RQ> L;
+  NormLanes<DP, RQ, kNorm> NL;
 #pragma unroll
   for (int r = 0; r < RQ; ++r) {
     const uint32_t slot = wu.q0 + (uint32_t)r * kWave + l;
@@ -228,13 +367,20 @@ __device__ __forceinline__ void join_body(
     L.id[r] = live ? orig_id[p] : 0u;
     L.init[r] = live ? 0.0f : __builtin_inff();
     const float4 *row = reinterpret_cast<const float4 *>(X + (uint64_t)p * DP);
+    const float sc = kNorm ? -2.0f : 1.0f;  // exact scaling
 #pragma unroll
     for (int t = 0; t < DP / 4; ++t) {
       const float4 v = row[t];
-      L.q[r][4 * t + 0] = v.x;
-      L.q[r][4 * t + 1] = v.y;
-      L.q[r][4 * t + 2] = v.z;
-      L.q[r][4 * t + 3] = v.w;
+      L.q[r][4 * t + 0] = sc * v.x;
+      L.q[r][4 * t + 1] = sc * v.y;
+      L.q[r][4 * t + 2] = sc * v.z;
+      L.q[r][4 * t + 3] = sc * v.w;
+    }
+    if constexpr (kNorm) {
+      const float *qa = QA + (uint64_t)p * norm_row(DP);
+#pragma unroll
+      for (int k = 0; k <= n_checkpoints(DP); ++k) NL.qa[r][k] = live ? qa[k] : 0.0f;
+      if (!live) NL.qa[r][0] = __builtin_inff();
     }
   }
   // in symmetric contiguous mode candidates below q1 need the per-lane
@@ -243,19 +389,67 @@ __device__ __forceinline__ void join_body(
 
   WaveStage st{kCount ? nullptr : &stage_mem[w][0], 0u};
   uint64_t n_recheck = 0, n_count = 0;
-  const bool sym = symmetric != 0, sc = shortc != 0;
+  const bool sym = symmetric != 0;
 
   for (uint32_t r = wu.run_first; r <= wu.run_last; ++r) {
     const uint2 run = runs[r];
     const uint32_t cb = (r == wu.run_first) ? wu.c_begin : run.x;
     const uint32_t ce = (r == wu.run_last) ? wu.c_end : run.y;
     const uint32_t mid = cb < filt_end ? (ce < filt_end ? ce : filt_end) : cb;
-    for (uint32_t c = cb; c < mid; ++c)
-      eval_candidate<DP, RQ, true, kCount>(L, c, X, orig_id, inv_perm, d, lo, hi, eps2, sym, sc,
-                                           st, out, capacity, cursor, n_recheck, n_count);
-    for (uint32_t c = mid; c < ce; ++c)
-      eval_candidate<DP, RQ, false, kCount>(L, c, X, orig_id, inv_perm, d, lo, hi, eps2, sym, sc,
-                                            st, out, capacity, cursor, n_recheck, n_count);
+    // candidates [from, to) with the per-lane filter or without; the head
+    // of candidate c + 1 is loaded before candidate c is evaluated
+    auto sweep = [&](uint32_t from, uint32_t to, auto filter) __attribute__((always_inline)) {
+      constexpr bool kF = decltype(filter)::value;
+      constexpr int NR = norm_row(DP);
+      if (from >= to) return;
+      const float *crow = X + (uint64_t)from * DP;
+      const float *ccr = kNorm ? CR + (uint64_t)from * NR : nullptr;
+      auto eval = [&](const Head<DP, kNorm> &h, uint32_t c) __attribute__((always_inline)) {
+        if constexpr (kNorm)
+          eval_candidate_norm<DP, RQ, kF, kCount, kSC>(L, NL, h, c, crow, ccr, X, orig_id,
+                                                       inv_perm, d, eps2, sym, st, out, capacity,
+                                                       cursor, n_recheck, n_count);
+        else
+          eval_candidate<DP, RQ, kF, kCount, kSC>(L, h, c, crow, X, orig_id, inv_perm, d, lo, hi,
+                                                  eps2, sym, st, out, capacity, cursor, n_recheck,
+                                                  n_count);
+      };
+      auto next = [&]() __attribute__((always_inline)) {
+        crow += DP;
+        if (kNorm) ccr += NR;
+      };
+#if SJ_SWEEP_MODE == 2
+      // two heads in alternation, so a look-ahead never overwrites the head
+      // in use
+      Head<DP, kNorm> h0 = load_head<DP, kNorm>(crow, ccr), h1;
+      uint32_t c = from;
+      for (;;) {
+        h1 = load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
+        eval(h0, c);
+        if (++c >= to) break;
+        next();
+        h0 = load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
+        eval(h1, c);
+        if (++c >= to) break;
+        next();
+      }
+#elif SJ_SWEEP_MODE == 1
+      Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
+      for (uint32_t c = from; c < to; ++c) {
+        const Head<DP, kNorm> hn = load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
+        eval(h, c);
+        h = hn;
+        next();
+      }
+#else
+      for (uint32_t c = from; c < to; ++c) {
+        eval(load_head<DP, kNorm>(crow, ccr), c);
+        next();
+      }
+#endif
+    };
+    sweep(cb, mid, std::true_type{});
+    sweep(mid, ce, std::false_type{});
   }
   stage_flush(st, out, capacity, cursor);
   if (l == 0) {
@@ -268,23 +462,101 @@ __device__ __forceinline__ void join_body(
   const float *__restrict__ X, const uint32_t *__restrict__ orig_id,                            \
       const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,   \
       const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, float lo, \
-      float hi, double eps2, int symmetric, int shortc, uint64_t *__restrict__ out,             \
+      float hi, double eps2, int symmetric, uint64_t *__restrict__ out,                         \
       uint64_t capacity, unsigned long long *__restrict__ cursor,                               \
-      unsigned long long *__restrict__ rechecks
+      unsigned long long *__restrict__ rechecks, const float *__restrict__ QA,                  \
+      const float *__restrict__ CR
 
 // The self-join distance kernel: emits result pairs.
-template <int DP, int RQ>
+template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_join_fp32(SJ_JOIN_PARAMS) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  join_body<DP, RQ, false>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi, eps2,
-                           symmetric, shortc, out, capacity, cursor, rechecks, stage_mem);
+  join_body<DP, RQ, false, kNorm, kSC>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
+                                       eps2, symmetric, out, capacity, cursor, rechecks,
+                                       stage_mem, QA, CR);
 }
 
 // The estimation kernel (count only) used to size result buffers.
-template <int DP, int RQ>
+template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_count_fp32(SJ_JOIN_PARAMS) {
-  join_body<DP, RQ, true>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi, eps2,
-                          symmetric, shortc, out, capacity, cursor, rechecks, nullptr);
+  join_body<DP, RQ, true, kNorm, kSC>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
+                                      eps2, symmetric, out, capacity, cursor, rechecks, nullptr,
+                                      QA, CR);
+}
+
+// Tables of the norm form, one row of norm_row(DP) floats per point p (the
+// remaining entries are 0).  With N_k = sum over the first checkpoint_dim(k)
+// coordinates of x^2 (FP64), s_hi / s_lo the bounds on the exact squared
+// distance implied by canonical acceptance / rejection, and margins
+// mu_q = kappa (4 N_k + 2 s_hi), mu_c = 2 kappa N_k:
+//   QA[p][0]   = rd(N_0 - s_hi - mu_q,0)             the accumulator's start
+//   QA[p][k]   = rd(T_k - sum of QA[p][0..k-1])       step to reference k
+//               (T_k = N_k - s_hi - mu_q,k)
+//   QA[p][K]   = ru(N_K-1 - s_lo + mu_q,K-1 - T_K-1')  shift to the accept test
+//   CR[p][k]   = ru(-N_k + mu_c,k)                     reject above this
+//   CR[p][K]   = rd(-N_K-1 - mu_c,K-1)                  accept at or below this
+// (rd / ru: rounding to FP32 towards -inf / +inf).  The accumulated FP32
+// error of the accumulator at checkpoint k is at most
+// gamma(|start| + sum |steps| + 2 sum |q_t c_t|) <= gamma (4 N_q + 2 s_hi +
+// 2 mu + N_c) since the references increase with k; kappa = 4 gamma_{DP+16}
+// (2^-24) covers it on both sides, and every rounding above is directed so
+// that it only makes a rejection or an acceptance harder.  *nsum collects
+// the sum over points of N_K-1 (the caller's choice of form uses the mean).
+__device__ __forceinline__ float rd_f32(double v) {
+  float f = (float)v;
+  if ((double)f > v) f = __builtin_bit_cast(float, f > 0.0f ? __builtin_bit_cast(uint32_t, f) - 1u
+                                                   : (f == 0.0f ? 0x80000001u
+                                                               : __builtin_bit_cast(uint32_t, f) + 1u));
+  return f;
+}
+__device__ __forceinline__ float ru_f32(double v) { return -rd_f32(-v); }
+
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_norm_tables(const float *__restrict__ X, uint64_t n,
+                                                        double s_hi, double s_lo, double kappa,
+                                                        float *__restrict__ QA,
+                                                        float *__restrict__ CR,
+                                                        double *__restrict__ nsum) {
+  constexpr int K = n_checkpoints(DP);
+  constexpr int NR = norm_row(DP);
+  const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  double N = 0.0;
+  if (p < n) {
+    const float *row = X + p * DP;
+    float *qa = QA + p * NR;
+    float *cr = CR + p * NR;
+    double running = 0.0;
+    int k = 0;
+#pragma unroll
+    for (int t = 0; t < DP; ++t) {
+      const double x = (double)row[t];
+      N += x * x;
+      if (t + 1 == checkpoint_dim(DP, k)) {
+        // the absolute term covers flushed subnormal results
+        const double tiny = (double)(DP + 16) * 0x1p-124;
+        const double mq = kappa * (4.0 * N + 2.0 * s_hi) + tiny;
+        const double mc = 2.0 * kappa * N + tiny;
+        const double T = N - s_hi - mq;
+        const float step = rd_f32(T - running);
+        qa[k] = step;
+        running += (double)step;
+        cr[k] = ru_f32(-N + mc);
+        if (k == K - 1) {
+          qa[K] = ru_f32(N - s_lo + mq - running);
+          cr[K] = rd_f32(-N - mc);
+        }
+        ++k;
+      }
+    }
+#pragma unroll
+    for (int j = K + 1; j < NR; ++j) {
+      qa[j] = 0.0f;
+      cr[j] = 0.0f;
+    }
+  }
+  // block sum of N for the mean
+  for (int off = 32; off > 0; off >>= 1) N += __shfl_xor(N, off);
+  if (lane_id() == 0 && N != 0.0) atomicAdd(nsum, N);
 }
 
 __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ keys,
@@ -315,19 +587,41 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ 
   }
 }
 
-template <int DP>
-void launch_dp(const JoinLaunch &a, hipStream_t s) {
+template <int DP, bool kNorm, bool kSC>
+void launch_form(const JoinLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
   if (grid == 0) return;
-  constexpr int kRq = DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1);
+  constexpr int kRq = kNorm ? (DP <= 24 ? SJ_NORM_RQ_SMALL : (DP <= 64 ? SJ_NORM_RQ_MID : 1))
+                            : (DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1));
   if (a.count_only)
-    hipLaunchKernelGGL((k_count_fp32<DP, kRq>), dim3(grid), dim3(kBlock), 0, s, a.X, a.orig_id,
-                       a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi, a.eps2,
-                       a.symmetric, a.shortc, a.out, a.capacity, a.cursor, a.rechecks);
+    hipLaunchKernelGGL((k_count_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
+                       a.orig_id, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
+                       a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks, a.QA, a.CR);
   else
-    hipLaunchKernelGGL((k_join_fp32<DP, kRq>), dim3(grid), dim3(kBlock), 0, s, a.X, a.orig_id,
-                       a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi, a.eps2,
-                       a.symmetric, a.shortc, a.out, a.capacity, a.cursor, a.rechecks);
+    hipLaunchKernelGGL((k_join_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
+                       a.orig_id, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
+                       a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks, a.QA, a.CR);
+  SJ_HIP(hipGetLastError());
+}
+
+template <int DP>
+void launch_dp(const JoinLaunch &a, hipStream_t s) {
+  if (a.norm) {
+    if (a.shortc) launch_form<DP, true, true>(a, s);
+    else launch_form<DP, true, false>(a, s);
+  } else {
+    if (a.shortc) launch_form<DP, false, true>(a, s);
+    else launch_form<DP, false, false>(a, s);
+  }
+}
+
+template <int DP>
+void launch_tables_dp(const float *X, uint64_t n, double s_hi, double s_lo, double kappa,
+                      float *QA, float *CR, double *nsum, hipStream_t s) {
+  const uint32_t grid = (uint32_t)((n + kBlock - 1) / kBlock);
+  if (!grid) return;
+  hipLaunchKernelGGL(k_norm_tables<DP>, dim3(grid), dim3(kBlock), 0, s, X, n, s_hi, s_lo, kappa,
+                     QA, CR, nsum);
   SJ_HIP(hipGetLastError());
 }
 
@@ -339,7 +633,43 @@ uint32_t padded_dim(uint32_t d) {
   return (d + 15) / 16 * 16;
 }
 
-int fp32_rq_for(uint32_t dp) { return dp <= 24 ? SJ_FP32_RQ_SMALL : (dp <= 64 ? SJ_FP32_RQ_MID : 1); }
+int fp32_rq_for(uint32_t dp, bool norm) {
+  if (norm) return dp <= 24 ? SJ_NORM_RQ_SMALL : (dp <= 64 ? SJ_NORM_RQ_MID : 1);
+  return dp <= 24 ? SJ_FP32_RQ_SMALL : (dp <= 64 ? SJ_FP32_RQ_MID : 1);
+}
+
+int norm_table_row(uint32_t dp) {
+  switch (dp) {
+    case 8: return norm_row(8);
+    case 16: return norm_row(16);
+    case 24: return norm_row(24);
+    case 32: return norm_row(32);
+    case 48: return norm_row(48);
+    case 64: return norm_row(64);
+    case 80: return norm_row(80);
+    case 96: return norm_row(96);
+    case 112: return norm_row(112);
+    case 128: return norm_row(128);
+    default: return 0;
+  }
+}
+
+void launch_norm_tables(const float *X, uint64_t n, uint32_t dp, double s_hi, double s_lo,
+                        double kappa, float *QA, float *CR, double *nsum, hipStream_t s) {
+  switch (dp) {
+    case 8: launch_tables_dp<8>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 16: launch_tables_dp<16>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 24: launch_tables_dp<24>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 32: launch_tables_dp<32>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 48: launch_tables_dp<48>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 64: launch_tables_dp<64>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 80: launch_tables_dp<80>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 96: launch_tables_dp<96>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 112: launch_tables_dp<112>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    case 128: launch_tables_dp<128>(X, n, s_hi, s_lo, kappa, QA, CR, nsum, s); break;
+    default: fail(SJ_ERR_INVALID_ARG, "unsupported padded dimension");
+  }
+}
 
 void launch_join_fp32(const JoinLaunch &a, hipStream_t s) {
   switch (a.dp) {

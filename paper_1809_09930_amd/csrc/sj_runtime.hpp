@@ -218,6 +218,8 @@ struct sj_index {
   uint32_t kp = 0;
   uint64_t n_pad = 0;
   DevBuf XA, XB, cn, thi, tlo;  // 16-bit operands, FP32 candidate norms, thresholds
+  bool norm_form = false;       // FP32 filter in norm form
+  DevBuf norm_qa, norm_cr;      // its per-point tables
   DevBuf wu_m;
   uint64_t n_wu_m = 0, evaluated_sym_m = 0;
   uint32_t tq_m = 128, tc_m = 4096;

@@ -26,6 +26,11 @@ SJ_PREC_FP16 = 1
 SJ_PREC_BF16 = 2
 PRECISIONS = {"fp32": SJ_PREC_FP32, "fp16": SJ_PREC_FP16, "bf16": SJ_PREC_BF16}
 
+SJ_FP32_AUTO = 0
+SJ_FP32_DIFFERENCE = 1
+SJ_FP32_NORM = 2
+FP32_FORMS = {"auto": SJ_FP32_AUTO, "difference": SJ_FP32_DIFFERENCE, "norm": SJ_FP32_NORM}
+
 EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_run",
             "selfjoin_fetch_pairs", "selfjoin_get_info", "selfjoin_get_perm",
             "selfjoin_free", "selfjoin_last_error", "selfjoin_run_batched",
@@ -44,7 +49,9 @@ class SjOptions(ctypes.Structure):
                 ("batch_pairs", ctypes.c_uint64),
                 ("min_batches", ctypes.c_uint32),
                 ("autotune", ctypes.c_uint32),
-                ("mem_budget", ctypes.c_uint64)]
+                ("mem_budget", ctypes.c_uint64),
+                ("fp32_form", ctypes.c_uint32),
+                ("reserved0", ctypes.c_uint32)]
 
 
 class SjInfo(ctypes.Structure):
@@ -66,7 +73,7 @@ class SjInfo(ctypes.Structure):
                 ("ms_sort", ctypes.c_float),
                 ("ms_run", ctypes.c_float),
                 ("join_launches", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("fp32_form", ctypes.c_uint32)]
 
 
 class SjJob(ctypes.Structure):
@@ -174,7 +181,7 @@ def _stream_handle(stream):
 def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = True,
                          shortc: bool = True, batch_pairs: int = 0, min_batches: int = 0,
                          mem_budget: int = 0, k_min: int = 4, k_max: int = 8,
-                         precision="fp32", stream=None):
+                         precision="fp32", fp32_form="auto", stream=None):
     """Build the grid index over a float32 [n, d] tensor (CUDA or CPU).
     Returns an opaque handle (int)."""
     import torch
@@ -191,6 +198,7 @@ def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = Tru
     o.min_batches = int(min_batches)
     o.mem_budget = int(mem_budget)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.fp32_form = FP32_FORMS[fp32_form] if isinstance(fp32_form, str) else int(fp32_form)
     h = ctypes.c_void_p()
     n, d = points.shape
     ptr = points.data_ptr() if points.numel() else None

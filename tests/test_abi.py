@@ -90,3 +90,33 @@ def test_bad_option_struct_size(lib):
     rc = lib.selfjoin_build_index(ctypes.cast(buf, ctypes.c_void_p), 2, 4, 0.5, ctypes.byref(o),
                                   None, ctypes.byref(h))
     assert rc == selfjoin.SJ_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("field,value,msg", [("fp32_form", 3, "fp32_form"),
+                                             ("reserved0", 1, "reserved0"),
+                                             ("precision", 7, "precision")])
+def test_bad_option_values(lib, field, value, msg):
+    from paper_1809_09930_amd import selfjoin
+    o = selfjoin.default_options()
+    setattr(o, field, value)
+    h = ctypes.c_void_p()
+    buf = (ctypes.c_float * 8)()
+    rc = lib.selfjoin_build_index(ctypes.cast(buf, ctypes.c_void_p), 2, 4, 0.5, ctypes.byref(o),
+                                  None, ctypes.byref(h))
+    assert rc == selfjoin.SJ_ERR_INVALID_ARG
+    assert msg in lib.selfjoin_last_error().decode()
+    assert h.value is None
+
+
+def test_short_option_struct_takes_defaults(lib):
+    """A caller built against the header before fp32_form passes the shorter
+    struct; the call validates like the defaults (it reaches the argument
+    checks, which reject the NULL handle pointer here)."""
+    from paper_1809_09930_amd import selfjoin
+    o = selfjoin.default_options()
+    o.struct_size = selfjoin.SjOptions.fp32_form.offset
+    buf = (ctypes.c_float * 8)()
+    rc = lib.selfjoin_build_index(ctypes.cast(buf, ctypes.c_void_p), 2, 4, 0.5, ctypes.byref(o),
+                                  None, None)
+    assert rc == selfjoin.SJ_ERR_INVALID_ARG
+    assert "struct_size" not in lib.selfjoin_last_error().decode()

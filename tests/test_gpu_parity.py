@@ -351,3 +351,57 @@ def test_full_size_workloads_sampled_rows(workload, target, prec):
             assert int(oi[st + int(c)]) != r
         off += int(c)
     assert info["candidates"] >= total
+
+
+@pytest.mark.parametrize("form", ["difference", "norm"])
+@pytest.mark.parametrize("n,d,seed,target", [
+    (3000, 16, 1, 32), (2500, 8, 2, 20), (1999, 18, 3, 40), (1500, 64, 4, 16),
+    (777, 90, 5, 12), (640, 128, 6, 10), (1000, 1, 7, 5), (4097, 24, 9, 3)])
+def test_fp32_forms_match_oracle(form, n, d, seed, target):
+    """Both evaluations of the FP32 filter, forced, on the same inputs."""
+    P = datagen.uniform_grid(n, d, seed)
+    info = assert_same_as_oracle(P, calibrated(P, target), fp32_form=form)
+    assert info["fp32_form"] == {"difference": 1, "norm": 2}[form]
+
+
+@pytest.mark.parametrize("form", ["difference", "norm"])
+def test_fp32_forms_band_and_ties(form):
+    """Pairs at eps * (1 + k 2^-20) and exact ties: the norm form's wider
+    band must send them to the FP64 recheck and still agree with the oracle;
+    clustered data with offsets far from the origin as well."""
+    u = 2.0 ** -24
+    rng = np.random.default_rng(91)
+    base = datagen.uniform_grid(400, 6, 92)
+    eps = 0.1
+    extra = []
+    for p in base[:200]:
+        axis = rng.integers(0, 6)
+        k = rng.integers(-3, 4)
+        q = p.astype(np.float64).copy()
+        q[axis] += eps * (1 + k * 2.0 ** -20)
+        extra.append(np.round(q / u) * u)
+    P = np.concatenate([base, np.array(extra, dtype=np.float32)])
+    info = assert_same_as_oracle(P, eps, fp32_form=form)
+    assert info["rechecks"] > 0
+    ties = np.array([[0, 0, 0, 0], [3000 * u, 4000 * u, 0, 0],
+                     [3000 * u, 3999 * u, 89 * u, 0], [3000 * u, 4000 * u, u, 0]],
+                    dtype=np.float32)
+    P = np.concatenate([ties, datagen.uniform_grid(500, 4, 31)])
+    assert_same_as_oracle(P, 5000 * u, fp32_form=form)
+    std = datagen.decaying_std(12, 0.2, 0.002, 93)
+    P = (datagen.gaussian_mixture(3000, 12, 10, std, 93) + np.float32(1.5)).astype(np.float32)
+    assert_same_as_oracle(P, calibrated(P, 30), fp32_form=form)
+    assert_same_as_oracle(P, calibrated(P, 30), fp32_form=form, shortc=False)
+
+
+def test_fp32_form_automatic_choice():
+    """Automatic choice: the norm form on unit-range data up to 16
+    dimensions, the difference form above 16 dimensions or when eps is tiny
+    against the squared norms."""
+    P = datagen.uniform_grid(2000, 16, 95)
+    assert gpu_join(P, calibrated(P, 20))[3]["fp32_form"] == 2
+    R = datagen.uniform_grid(2000, 24, 96)
+    assert gpu_join(R, calibrated(R, 20))[3]["fp32_form"] == 1
+    Q = (P * np.float32(1e-3) + np.float32(100.0)).astype(np.float32)  # tiny eps, large norms
+    info = assert_same_as_oracle(Q, calibrated(Q, 20))
+    assert info["fp32_form"] == 1
