@@ -635,6 +635,10 @@ MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist,
 }
 
 // One launch of the distance kernel over a set of work units.
+bool debug_undersize();
+uint64_t read_counter(sj_index &ix, int which, hipStream_t s);
+constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
+
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
                  const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
                  hipStream_t s, float *ms) {
@@ -675,7 +679,32 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     m.capacity = count_only ? 0 : cap;
     m.cursor = a.cursor;
     m.rechecks = a.rechecks;
-    launch_join_mfma(m, s);
+    if (count_only) {
+      launch_join_mfma(m, s);  // band pairs rechecked in place
+    } else {
+      // band pairs are collected during the join and rechecked afterwards,
+      // one per lane; a band list that overflowed is grown and the join rerun
+      unsigned long long *band_cursor = ix.counters.as<unsigned long long>() + 2;
+      const uint64_t want = debug_undersize() ? 16 : std::max(kBandStart, ix.band_hint);
+      if (ix.band_cap < want) {
+        ix.band_cap = want;
+        ix.band.alloc(ix.band_cap * 8);
+      }
+      for (int attempt = 0;; ++attempt) {
+        SJ_HIP(hipMemsetAsync(band_cursor, 0, 8, s));
+        m.view.band = ix.band.as<uint64_t>();
+        m.view.band_cap = ix.band_cap;
+        m.view.band_cursor = band_cursor;
+        launch_join_mfma(m, s);
+        launch_band_recheck(m.view, out, cap, a.cursor, a.rechecks, s);
+        const uint64_t nb = read_counter(ix, 2, s);
+        if (nb <= ix.band_cap) break;
+        if (attempt == 2) fail(SJ_ERR_DEVICE, "band list size did not settle");
+        ix.band_cap = nb + nb / 8;
+        ix.band.alloc(ix.band_cap * 8);
+        SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));  // the join starts over
+      }
+    }
   } else {
     launch_join_fp32(a, s);
   }
@@ -714,8 +743,14 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
   join_launch(ix, wu, nwu, ix.runs_full, ql.as<uint32_t>(), 0, 1, nullptr, 0, s, ms);
   const uint64_t cnt = read_counter(ix, 0, s);
-  const double est = (double)cnt * (double)n / (double)nq;
-  return (uint64_t)std::ceil(est);
+  const double scale = (double)n / (double)nq;
+  if (mf) {
+    // band pairs of the sample (rechecked in place here) size the deferred
+    // recheck list of the join
+    const double band = (double)read_counter(ix, 1, s) * scale;
+    ix.band_hint = (uint64_t)std::ceil(band * 1.25) + (1u << 16);
+  }
+  return (uint64_t)std::ceil((double)cnt * scale);
 }
 
 uint64_t default_budget() {

@@ -261,6 +261,17 @@ __device__ __forceinline__ void flush(Stage &st, uint64_t *__restrict__ out, uin
   st.cnt = 0;
 }
 
+// Where the hit path sends band pairs: a per-wave LDS stage flushed to the
+// deferred-recheck list, or (buf == null) nowhere: the pair is rechecked in
+// place.
+constexpr int kBandStage = 128;
+struct BandSink {
+  uint64_t *buf;
+  uint64_t cap;
+  unsigned long long *cursor;
+  Stage st;
+};
+
 __device__ __forceinline__ float min16(const float16v &v) {
   float a = __builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]);
   float b = __builtin_fminf(__builtin_fminf(v[3], v[4]), v[5]);
@@ -314,7 +325,7 @@ template <int QB>
 __device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const float (&th)[QB],
                                            const float (&tl)[QB], const uint32_t (&qpos)[QB],
                                            uint32_t c0, uint32_t cend, uint32_t half,
-                                           const MfmaView &v, Stage &st,
+                                           const MfmaView &v, Stage &st, BandSink &bs,
                                            uint64_t *__restrict__ out, uint64_t capacity,
                                            unsigned long long *__restrict__ cursor,
                                            uint64_t &n_recheck) {
@@ -343,8 +354,16 @@ __device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const floa
       const bool band = ok && !acc_ok;
       const uint64_t bm = ballot(band);
       if (bm) {
-        if (band) acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
-        n_recheck += (uint64_t)__builtin_popcountll(bm);
+        if (bs.buf) {  // deferred: the pair waits in the band list
+          const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
+          if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
+          if (band) bs.st.buf[bs.st.cnt + lanes_below(bm)] = ((uint64_t)qpos[j] << 32) | cp;
+          bs.st.cnt += nb;
+        } else {
+          if (band)
+            acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+          n_recheck += (uint64_t)__builtin_popcountll(bm);
+        }
       }
       const uint64_t am = ballot(acc_ok);
       if (am == 0) continue;
@@ -373,7 +392,7 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
                                                const float (&tl)[QB],
                                                const uint32_t (&qpos)[QB], uint32_t c0,
                                                uint32_t cend, uint32_t half, const MfmaView &v,
-                                               Stage &st, uint64_t *__restrict__ out,
+                                               Stage &st, BandSink &bs, uint64_t *__restrict__ out,
                                                uint64_t capacity,
                                                unsigned long long *__restrict__ cursor,
                                                uint64_t &n_recheck) {
@@ -390,8 +409,16 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
       const bool band = ok && !acc_ok;
       const uint64_t bm = ballot(band);
       if (bm) {
-        if (band) acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
-        n_recheck += (uint64_t)__builtin_popcountll(bm);
+        if (bs.buf) {  // deferred: the pair waits in the band list
+          const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
+          if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
+          if (band) bs.st.buf[bs.st.cnt + lanes_below(bm)] = ((uint64_t)qpos[j] << 32) | cp;
+          bs.st.cnt += nb;
+        } else {
+          if (band)
+            acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+          n_recheck += (uint64_t)__builtin_popcountll(bm);
+        }
       }
       const uint64_t am = ballot(acc_ok);
       if (am == 0) continue;
@@ -480,6 +507,7 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
 
+  BandSink bs{nullptr, 0, nullptr, Stage{nullptr, 0u}};  // band pairs are rechecked in place
   BlockIter it;
   it.init(wu, v.runs);
   if (!it.valid()) return;
@@ -520,10 +548,11 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
     }
     if (ballot(tiles_any<QB>(acc, th))) {
       if constexpr (KP > SJ_BATCH_HIT_ACC_ABOVE_KP)
-        tiles_hits_acc<QB>(acc, th, tl, qpos, c, ce, half, v, st, out, capacity, cursor,
+        tiles_hits_acc<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
                            n_recheck);
       else
-        tiles_hits<QB>(acc, th, tl, qpos, c, ce, half, v, st, out, capacity, cursor, n_recheck);
+        tiles_hits<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
+                       n_recheck);
     }
     if (!more) break;
 #pragma unroll
@@ -569,6 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
   __shared__ V8 tile[2][CHUNK_VECS];
   __shared__ __align__(16) float tile_n[2][kChunk];  // candidate norms of the chunk
+  __shared__ uint64_t band_mem[kWavesPerBlock][kBandStage];
   const uint64_t u = blockIdx.x;
   if (u >= n_wu) return;  // whole workgroup leaves together
   const WorkUnit wu = wus[u];
@@ -594,6 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
   Stage st{&stage_mem[w][0], 0u};
+  BandSink bs{v.band, v.band_cap, v.band_cursor, Stage{&band_mem[w][0], 0u}};
   uint64_t n_recheck = 0;
 
   // chunk walk (uniform over the workgroup)
@@ -631,10 +662,10 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
                       uint32_t cend) __attribute__((always_inline)) {
     if (ballot(tiles_any<QB>(acc, th))) {
       if constexpr (KP > SJ_HIT_ACC_ABOVE_KP)
-        tiles_hits_acc<QB>(acc, th, tl, qpos, c0, cend, half, v, st, out, capacity, cursor,
+        tiles_hits_acc<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
                            n_recheck);
       else
-        tiles_hits<QB>(acc, th, tl, qpos, c0, cend, half, v, st, out, capacity, cursor,
+        tiles_hits<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
                        n_recheck);
     }
   };
@@ -697,8 +728,51 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   (void)prev_end;
   (void)have_prev;
 #endif
+  if (bs.buf) flush(bs.st, bs.buf, bs.cap, bs.cursor);
   flush(st, out, capacity, cursor);
   if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+// Deferred FP64 recheck of the band pairs of a launch: one pair per lane,
+// all lanes busy, instead of the few band lanes of one tile element at a
+// time.  Accepted pairs are staged and appended like the join's own.
+__global__ __launch_bounds__(kBlock) void k_band_recheck(
+    MfmaView v, const unsigned long long *__restrict__ band_count, uint64_t *__restrict__ out,
+    uint64_t capacity, unsigned long long *__restrict__ cursor,
+    unsigned long long *__restrict__ rechecks) {
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  Stage st{&stage_mem[w][0], 0u};
+  const uint64_t total = *band_count;
+  const uint64_t count = total < v.band_cap ? total : v.band_cap;
+  const bool sym = v.symmetric != 0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (uint64_t)w * kWave; base < count;
+       base += stride) {
+    const uint64_t i = base + lane_id();
+    bool ok = false;
+    uint32_t q = 0, c = 0;
+    if (i < count) {
+      const uint64_t key = v.band[i];
+      q = (uint32_t)(key >> 32);
+      c = (uint32_t)key;
+      ok = canonical_within_m(v.X, q, c, v.inv_perm, v.d, v.dp, v.eps2);
+    }
+    const uint64_t am = ballot(ok);
+    if (am == 0) continue;
+    const bool two = ok && sym && q != c;
+    const uint64_t m2 = ballot(two);
+    const uint32_t n = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+    if (st.cnt + n > (uint32_t)kStage) flush(st, out, capacity, cursor);
+    const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+    if (ok) {
+      st.buf[off] = v.key_hi | ((uint64_t)q << v.pshift) | c;
+      if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)c << v.pshift) | q;
+    }
+    st.cnt += n;
+  }
+  flush(st, out, capacity, cursor);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && count) atomicAdd(rechecks, (unsigned long long)count);
 }
 
 // query column blocks per wave of the persistent batched kernel
@@ -926,6 +1000,16 @@ void launch_job_bounds(const uint64_t *keys, const unsigned long long *count,
                        unsigned long long *last, uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL(k_job_bounds, dim3(grid), dim3(kBlock), 0, s, keys, count, capacity, first,
                      last);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_band_recheck(const MfmaView &v, uint64_t *out, uint64_t capacity,
+                         unsigned long long *cursor, unsigned long long *rechecks, hipStream_t s) {
+  int dev = 0, cus = 256;
+  SJ_HIP(hipGetDevice(&dev));
+  SJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  hipLaunchKernelGGL(k_band_recheck, dim3((uint32_t)cus * 4), dim3(kBlock), 0, s, v,
+                     v.band_cursor, out, capacity, cursor, rechecks);
   SJ_HIP(hipGetLastError());
 }
 

@@ -30,6 +30,11 @@ struct MfmaView {
   int symmetric;
   uint32_t pshift;          // key = key_hi | pos_q << pshift | pos_c
   uint64_t key_hi;
+  // Deferred FP64 rechecks: band pairs (pos_q << 32 | pos_c) are appended
+  // here and rechecked by launch_band_recheck; null: rechecked in place.
+  uint64_t *band;
+  uint64_t band_cap;
+  unsigned long long *band_cursor;
 };
 
 struct MfmaLaunch {
@@ -65,6 +70,11 @@ void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, co
                             float *tlo, hipStream_t s);
 // Emits keys of cell-order positions (launch_pos_to_id maps them to
 // caller indices in place).
+// Rechecks the band pairs collected by a launch with view.band set (their
+// count is read on the device, at most view.band_cap) and appends the
+// accepted ones to out like the join does; *rechecks += their count.
+void launch_band_recheck(const MfmaView &v, uint64_t *out, uint64_t capacity,
+                         unsigned long long *cursor, unsigned long long *rechecks, hipStream_t s);
 void launch_join_mfma(const MfmaLaunch &a, hipStream_t s);
 void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, hipStream_t s);
 

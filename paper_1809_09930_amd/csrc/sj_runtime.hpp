@@ -218,6 +218,9 @@ struct sj_index {
   uint32_t kp = 0;
   uint64_t n_pad = 0;
   DevBuf XA, XB, cn, thi, tlo;  // 16-bit operands, FP32 candidate norms, thresholds
+  DevBuf band;                  // deferred recheck list of the matrix-core join
+  uint64_t band_cap = 0;
+  uint64_t band_hint = 0;       // its expected size from the sampled count
   bool norm_form = false;       // FP32 filter in norm form
   DevBuf norm_qa, norm_cr;      // its per-point tables
   DevBuf wu_m;
@@ -248,8 +251,9 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms);
 uint64_t default_budget();
 MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist, int sym);
 // Fault injection from the host: SJ_DEBUG_UNDERSIZE=1 makes the first
-// result buffer of every run far too small, so the device-side overflow
-// detection and the resize-and-rerun path are exercised.
+// result buffer of every run (and the first band list of the matrix-core
+// join) far too small, so the device-side overflow detection and the
+// resize-and-rerun paths are exercised.
 bool debug_undersize();
 
 template <typename F>

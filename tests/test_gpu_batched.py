@@ -101,9 +101,11 @@ def test_overflow_detected_and_rerun(monkeypatch):
     from test_gpu_parity import assert_same_as_oracle
     P = datagen.uniform_grid(3000, 16, 5)
     eps, _ = oracle.calibrate_eps(P, 30, np.arange(0, 3000, 3))
-    for prec in ("fp32", "fp16"):
-        assert_same_as_oracle(P, eps, precision=prec)
+    for prec in ("fp32", "fp16", "bf16"):
+        info = assert_same_as_oracle(P, eps, precision=prec)
         assert_same_as_oracle(P, eps, precision=prec, batch_pairs=20000)
+        if prec == "bf16":
+            assert info["rechecks"] > 16  # the 16-slot band list overflowed
 
 
 def test_batched_argument_errors():
