@@ -49,7 +49,10 @@ struct sj_batch {
   sj::DevBuf wus;        // all jobs' work units
   uint64_t n_wu = 0;
   sj::DevBuf keys[2], radix_tmp;
-  sj::DevBuf ctl;        // [0] cursor, [1] rechecks, [2] capacity, [3] queue (u32 in the low half)
+  sj::DevBuf ctl;        // [0] cursor, [1] rechecks, [2] capacity, [3] queue (u32 in the low half),
+                         // [4] band-list cursor
+  sj::DevBuf band;       // deferred recheck list
+  uint64_t band_cap = 0;
   sj::DevBuf first, last;  // per-job bounds in the sorted keys
   uint64_t capacity = 0;
   uint32_t tc = 4096, grab = 1;
@@ -162,12 +165,16 @@ void alloc_outputs(sj_batch &b, uint64_t cap, hipStream_t s) {
 void record(sj_batch &b, hipStream_t s) {
   const size_t nj = b.jobs.size();
   launch_fill_u64(ctl_ptr(b, 0), 2, 0ull, s);  // cursor, rechecks
-  launch_fill_u64(ctl_ptr(b, 3), 1, 0ull, s);  // queue
+  launch_fill_u64(ctl_ptr(b, 3), 2, 0ull, s);  // queue, band-list cursor
   launch_fill_u64(b.first.as<unsigned long long>(), nj, 0ull, s);
   launch_fill_u64(b.last.as<unsigned long long>(), nj, 0ull, s);
   launch_join_batched(b.jobs_d.as<BatchJob>(), b.wus.as<WorkUnit>(), b.n_wu, b.grab,
                       reinterpret_cast<unsigned int *>(ctl_ptr(b, 3)), b.keys[0].as<uint64_t>(),
-                      ctl_ptr(b, 2), ctl_ptr(b, 0), ctl_ptr(b, 1), b.grid, s);
+                      ctl_ptr(b, 2), ctl_ptr(b, 0), ctl_ptr(b, 1), b.grid,
+                      b.band.as<uint64_t>(), b.band_cap, ctl_ptr(b, 4), s);
+  launch_band_recheck_batched(b.jobs_d.as<BatchJob>(), b.band.as<uint64_t>(), ctl_ptr(b, 4),
+                              b.band_cap, b.keys[0].as<uint64_t>(), ctl_ptr(b, 2), ctl_ptr(b, 0),
+                              ctl_ptr(b, 1), b.grid, s);
   const uint32_t g = (uint32_t)std::min<uint64_t>((b.capacity + kBlock - 1) / kBlock, 16384);
   launch_pos_to_id_batched(b.keys[0].as<uint64_t>(), ctl_ptr(b, 0), ctl_ptr(b, 2),
                            b.jobs_d.as<BatchJob>(), g, s);
@@ -217,12 +224,16 @@ uint64_t read_ctl(sj_batch &b, int i) {
 // Time one launch of the persistent join alone (results discarded).
 float time_join(sj_batch &b) {
   launch_fill_u64(ctl_ptr(b, 0), 2, 0ull, b.cs);
-  launch_fill_u64(ctl_ptr(b, 3), 1, 0ull, b.cs);
+  launch_fill_u64(ctl_ptr(b, 3), 2, 0ull, b.cs);
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, b.cs));
   launch_join_batched(b.jobs_d.as<BatchJob>(), b.wus.as<WorkUnit>(), b.n_wu, b.grab,
                       reinterpret_cast<unsigned int *>(ctl_ptr(b, 3)), b.keys[0].as<uint64_t>(),
-                      ctl_ptr(b, 2), ctl_ptr(b, 0), ctl_ptr(b, 1), b.grid, b.cs);
+                      ctl_ptr(b, 2), ctl_ptr(b, 0), ctl_ptr(b, 1), b.grid,
+                      b.band.as<uint64_t>(), b.band_cap, ctl_ptr(b, 4), b.cs);
+  launch_band_recheck_batched(b.jobs_d.as<BatchJob>(), b.band.as<uint64_t>(), ctl_ptr(b, 4),
+                              b.band_cap, b.keys[0].as<uint64_t>(), ctl_ptr(b, 2), ctl_ptr(b, 0),
+                              ctl_ptr(b, 1), b.grid, b.cs);
   SJ_HIP(hipEventRecord(e1.e, b.cs));
   SJ_HIP(hipEventSynchronize(e1.e));
   return elapsed_ms(e0, e1);
@@ -358,6 +369,13 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
   // pre-size the shared output from every job's sampled count
   uint64_t cap = 1u << 20;
   for (uint32_t j = 0; j < njobs; ++j) cap += b.est[j] + b.est[j] / 8;
+  // the band list from the jobs' sampled band counts
+  uint64_t band_cap = 1u << 16;
+  for (uint32_t j = 0; j < njobs; ++j)
+    if (b.jobs[j]->n) band_cap += b.jobs[j]->band_hint;
+  if (debug_undersize()) band_cap = 16;
+  b.band_cap = band_cap;
+  b.band.alloc(band_cap * 8);
   // job table
   std::vector<BatchJob> table(njobs);
   for (uint32_t j = 0; j < njobs; ++j) {
@@ -390,15 +408,22 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
   auto t2 = std::chrono::steady_clock::now();
   if (autotune_on) autotune(b);
   auto t3 = std::chrono::steady_clock::now();
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  for (int attempt = 0; attempt < 4; ++attempt) {
     capture(b);
     b.info.ms_graph = replay(b);
+    const uint64_t nb = read_ctl(b, 4);
+    if (nb > b.band_cap) {  // band list overflowed: exact size, capture again
+      if (attempt == 3) fail(SJ_ERR_DEVICE, "batched band list size did not settle");
+      b.band_cap = nb;
+      b.band.alloc(nb * 8);
+      continue;
+    }
     const uint64_t got = read_ctl(b, 0);
     if (got <= b.capacity) {
       b.total = got;
       break;
     }
-    if (attempt == 2) fail(SJ_ERR_DEVICE, "batched result count did not settle");
+    if (attempt == 3) fail(SJ_ERR_DEVICE, "batched result count did not settle");
     alloc_outputs(b, got, b.cs);  // exact now
   }
   b.rechecks = read_ctl(b, 1);

@@ -357,7 +357,9 @@ __device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const floa
         if (bs.buf) {  // deferred: the pair waits in the band list
           const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
           if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
-          if (band) bs.st.buf[bs.st.cnt + lanes_below(bm)] = ((uint64_t)qpos[j] << 32) | cp;
+          if (band)
+            bs.st.buf[bs.st.cnt + lanes_below(bm)] =
+                v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
           bs.st.cnt += nb;
         } else {
           if (band)
@@ -412,7 +414,9 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
         if (bs.buf) {  // deferred: the pair waits in the band list
           const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
           if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
-          if (band) bs.st.buf[bs.st.cnt + lanes_below(bm)] = ((uint64_t)qpos[j] << 32) | cp;
+          if (band)
+            bs.st.buf[bs.st.cnt + lanes_below(bm)] =
+                v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
           bs.st.cnt += nb;
         } else {
           if (band)
@@ -479,7 +483,7 @@ struct BlockIter {
 // keys key_hi | pos_q << pshift | pos_c.
 template <int KP, int FMT, int QB>
 __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu, Stage &st,
-                                          float *__restrict__ nrm,
+                                          BandSink &bs, float *__restrict__ nrm,
                                           uint64_t *__restrict__ out, uint64_t capacity,
                                           unsigned long long *__restrict__ cursor,
                                           uint64_t &n_recheck) {
@@ -507,7 +511,6 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
     for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
   }
 
-  BandSink bs{nullptr, 0, nullptr, Stage{nullptr, 0u}};  // band pairs are rechecked in place
   BlockIter it;
   it.init(wu, v.runs);
   if (!it.valid()) return;
@@ -786,23 +789,26 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck(
 // wave leaves once the queue is exhausted, so the grid drains by itself.
 template <int KP, int FMT>
 __device__ __forceinline__ void batched_dispatch(const MfmaView &v, const WorkUnit &wu, Stage &st,
-                                                 float *__restrict__ nrm,
+                                                 BandSink &bs, float *__restrict__ nrm,
                                                  uint64_t *__restrict__ out, uint64_t capacity,
                                                  unsigned long long *__restrict__ cursor,
                                                  uint64_t &n_recheck) {
-  mfma_unit<KP, FMT, SJ_BATCH_QB>(v, wu, st, nrm, out, capacity, cursor, n_recheck);
+  mfma_unit<KP, FMT, SJ_BATCH_QB>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck);
 }
 
 __global__ __launch_bounds__(kBlock) void k_join_batched(
     const BatchJob *__restrict__ jobs, const WorkUnit *__restrict__ wus, uint64_t n_wu,
     uint32_t grab, unsigned int *__restrict__ queue, uint64_t *__restrict__ out,
     const unsigned long long *__restrict__ capacity_p, unsigned long long *__restrict__ cursor,
-    unsigned long long *__restrict__ rechecks) {
+    unsigned long long *__restrict__ rechecks, uint64_t *__restrict__ band, uint64_t band_cap,
+    unsigned long long *__restrict__ band_cursor) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  __shared__ uint64_t band_mem[kWavesPerBlock][kBandStage];
   const uint32_t w = uniform_u32(threadIdx.x / kWave);
   __shared__ __align__(16) float nrm_mem[kWavesPerBlock][32];
   float *nrm = &nrm_mem[w][0];
   Stage st{&stage_mem[w][0], 0u};
+  BandSink bs{band, band_cap, band_cursor, Stage{&band_mem[w][0], 0u}};
   uint64_t n_recheck = 0;
   const uint64_t capacity = *capacity_p;
   for (;;) {
@@ -817,22 +823,68 @@ __global__ __launch_bounds__(kBlock) void k_join_batched(
       MfmaView v = jobs[job].view;
       v.key_hi = (uint64_t)job << 40;
       switch (jobs[job].variant) {
-        case 0: batched_dispatch<16, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 1: batched_dispatch<32, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 2: batched_dispatch<48, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 3: batched_dispatch<64, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 4: batched_dispatch<80, kFmtF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 5: batched_dispatch<16, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 6: batched_dispatch<32, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 7: batched_dispatch<48, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 8: batched_dispatch<64, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
-        case 9: batched_dispatch<80, kFmtBF16>(v, wu, st, nrm, out, capacity, cursor, n_recheck); break;
+        case 0: batched_dispatch<16, kFmtF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 1: batched_dispatch<32, kFmtF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 2: batched_dispatch<48, kFmtF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 3: batched_dispatch<64, kFmtF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 4: batched_dispatch<80, kFmtF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 5: batched_dispatch<16, kFmtBF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 6: batched_dispatch<32, kFmtBF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 7: batched_dispatch<48, kFmtBF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 8: batched_dispatch<64, kFmtBF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
+        case 9: batched_dispatch<80, kFmtBF16>(v, wu, st, bs, nrm, out, capacity, cursor, n_recheck); break;
         default: break;
       }
     }
   }
   flush(st, out, capacity, cursor);
+  if (bs.buf) flush(bs.st, bs.buf, bs.cap, bs.cursor);
   if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
+// Deferred recheck of a batched launch's band pairs (job << 40 | pos_q << 20
+// | pos_c), one per lane, each with its own job's rows.
+__global__ __launch_bounds__(kBlock) void k_band_recheck_batched(
+    const BatchJob *__restrict__ jobs, const uint64_t *__restrict__ band,
+    const unsigned long long *__restrict__ band_count, uint64_t band_cap,
+    uint64_t *__restrict__ out, const unsigned long long *__restrict__ capacity_p,
+    unsigned long long *__restrict__ cursor, unsigned long long *__restrict__ rechecks) {
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  Stage st{&stage_mem[w][0], 0u};
+  const uint64_t capacity = *capacity_p;
+  const uint64_t total = *band_count;
+  const uint64_t count = total < band_cap ? total : band_cap;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  constexpr uint64_t kMask = (1ull << 20) - 1ull;
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (uint64_t)w * kWave; base < count;
+       base += stride) {
+    const uint64_t i = base + lane_id();
+    bool ok = false, two = false;
+    uint64_t key = 0, rkey = 0;
+    if (i < count) {
+      key = band[i];
+      const uint32_t job = (uint32_t)(key >> 40);
+      const uint32_t q = (uint32_t)((key >> 20) & kMask), c = (uint32_t)(key & kMask);
+      const MfmaView &v = jobs[job].view;
+      ok = canonical_within_m(v.X, q, c, v.inv_perm, v.d, v.dp, v.eps2);
+      two = ok && v.symmetric && q != c;
+      rkey = ((uint64_t)job << 40) | ((uint64_t)c << 20) | q;
+    }
+    const uint64_t am = ballot(ok);
+    if (am == 0) continue;
+    const uint64_t m2 = ballot(two);
+    const uint32_t n = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+    if (st.cnt + n > (uint32_t)kStage) flush(st, out, capacity, cursor);
+    const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+    if (ok) {
+      st.buf[off] = key;
+      if (two) st.buf[off + 1] = rkey;
+    }
+    st.cnt += n;
+  }
+  flush(st, out, capacity, cursor);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && count) atomicAdd(rechecks, (unsigned long long)count);
 }
 
 // Batched keys job << 40 | pos_q << 20 | pos_c -> job << 40 | id_q << 20 | id_c,
@@ -981,9 +1033,20 @@ int batched_blocks_per_cu() {
 void launch_join_batched(const BatchJob *jobs, const WorkUnit *wus, uint64_t n_wu, uint32_t grab,
                          unsigned int *queue, uint64_t *out, const unsigned long long *capacity,
                          unsigned long long *cursor, unsigned long long *rechecks, uint32_t grid,
+                         uint64_t *band, uint64_t band_cap, unsigned long long *band_cursor,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_join_batched, dim3(grid), dim3(kBlock), 0, s, jobs, wus, n_wu, grab, queue,
-                     out, capacity, cursor, rechecks);
+                     out, capacity, cursor, rechecks, band, band_cap, band_cursor);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_band_recheck_batched(const BatchJob *jobs, const uint64_t *band,
+                                 const unsigned long long *band_count, uint64_t band_cap,
+                                 uint64_t *out, const unsigned long long *capacity,
+                                 unsigned long long *cursor, unsigned long long *rechecks,
+                                 uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_band_recheck_batched, dim3(grid), dim3(kBlock), 0, s, jobs, band,
+                     band_count, band_cap, out, capacity, cursor, rechecks);
   SJ_HIP(hipGetLastError());
 }
 

@@ -85,7 +85,15 @@ int batched_blocks_per_cu();
 void launch_join_batched(const BatchJob *jobs, const WorkUnit *wus, uint64_t n_wu, uint32_t grab,
                          unsigned int *queue, uint64_t *out, const unsigned long long *capacity,
                          unsigned long long *cursor, unsigned long long *rechecks, uint32_t grid,
+                         uint64_t *band, uint64_t band_cap, unsigned long long *band_cursor,
                          hipStream_t s);
+// Deferred FP64 recheck of the band list of a batched launch (band == null
+// in launch_join_batched: rechecked in place instead).
+void launch_band_recheck_batched(const BatchJob *jobs, const uint64_t *band,
+                                 const unsigned long long *band_count, uint64_t band_cap,
+                                 uint64_t *out, const unsigned long long *capacity,
+                                 unsigned long long *cursor, unsigned long long *rechecks,
+                                 uint32_t grid, hipStream_t s);
 void launch_pos_to_id_batched(uint64_t *keys, const unsigned long long *count,
                               const unsigned long long *capacity, const BatchJob *jobs,
                               uint32_t grid, hipStream_t s);
