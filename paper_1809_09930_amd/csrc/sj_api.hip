@@ -104,6 +104,11 @@ constexpr double kWidthSlack = 1.0 + 1.0 / (1 << 20);  // cell side = eps * (1 +
 #define SJ_WU_BY_STRETCH 1
 #endif
 constexpr bool kWuByStretch = SJ_WU_BY_STRETCH != 0;  // join work units in stretch order
+// mean points per cell below which the matrix-core single join uses per-wave units
+#ifndef SJ_WAVE_UNITS_BELOW
+#define SJ_WAVE_UNITS_BELOW 128
+#endif
+constexpr double kWaveUnitsBelow = SJ_WAVE_UNITS_BELOW;
 
 // Fine (Morton) ordering inside cells: dimensions and bits per dimension.
 #ifndef SJ_FINE_DIMS
@@ -602,11 +607,16 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   if (ix.opt.precision != SJ_PREC_FP32) {
     mfma_prepare(ix, s);
     ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);         // per wave (batched kernel)
-    const uint32_t tq_wg = mfma_wg_queries(ix.kp);    // per workgroup (single join)
     ix.tc_m = choose_tc(ev, ix.tq_m);
-    const uint32_t tc_wg = std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
-    ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, tq_wg, tc_wg,
-                                ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch);
+    // single join: workgroup units, or per-wave units when the cells are
+    // much smaller than a workgroup's query slots
+    const uint32_t tq_wg = mfma_wg_queries(ix.kp);
+    ix.mfma_per_wave = ix.ncell > 0 && (double)ix.n / (double)ix.ncell < kWaveUnitsBelow;
+    ix.tq_single = ix.mfma_per_wave ? mfma_wave_queries() : tq_wg;
+    ix.tc_single = ix.mfma_per_wave ? choose_tc(ev, ix.tq_single)
+                                    : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
+    ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_single,
+                                ix.tc_single, ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch);
   }
 
   SJ_HIP(hipEventRecord(ev1.e, s));
@@ -679,6 +689,7 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     m.capacity = count_only ? 0 : cap;
     m.cursor = a.cursor;
     m.rechecks = a.rechecks;
+    m.per_wave = ix.mfma_per_wave ? 1 : 0;
     if (count_only) {
       launch_join_mfma(m, s);  // band pairs rechecked in place
     } else {
@@ -738,8 +749,8 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   // capacity 0); the FP32 path has a count-only kernel
   const bool mf = ix.prec != SJ_PREC_FP32;
   const uint64_t nwu = build_workunits(ix, 0, ql.as<uint32_t>(), nq, ix.run_off_full,
-                                       ix.runs_full, mf ? mfma_wg_queries(ix.kp) : ix.tq,
-                                       mf ? ix.tc_m * 4 : 4096, wu, &ev, s);
+                                       ix.runs_full, mf ? ix.tq_single : ix.tq,
+                                       mf ? ix.tc_single : 4096, wu, &ev, s);
   SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
   join_launch(ix, wu, nwu, ix.runs_full, ql.as<uint32_t>(), 0, 1, nullptr, 0, s, ms);
   const uint64_t cnt = read_counter(ix, 0, s);
@@ -855,8 +866,8 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
       uint64_t ev = 0;
       const bool mf = ix.prec != SJ_PREC_FP32;
       const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
-                                           ix.runs_full, mf ? mfma_wg_queries(ix.kp) : ix.tq,
-                                           mf ? ix.tc_m * 4 : ix.tc, wu, &ev, s, kWuByStretch);
+                                           ix.runs_full, mf ? ix.tq_single : ix.tq,
+                                           mf ? ix.tc_single : ix.tc, wu, &ev, s, kWuByStretch);
       evaluated += ev;
       Slot &sl = slots[slot & 1];
       if (sl.busy) {

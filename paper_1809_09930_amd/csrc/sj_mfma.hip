@@ -566,6 +566,36 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
   }
 }
 
+// Per-wave form for indexes with small cells: every wave takes a work unit
+// of its own (32 * SJ_WAVE_QB queries of one cell) and streams that unit's
+// candidates itself, so cells much smaller than a workgroup's 256 queries do
+// not leave most matrix columns empty.
+#ifndef SJ_WAVE_QB
+#define SJ_WAVE_QB 1
+#endif
+template <int KP, int FMT>
+__global__ __launch_bounds__(kBlock) void k_join_mfma_wave(MfmaView v,
+                                                           const WorkUnit *__restrict__ wus,
+                                                           uint64_t n_wu, uint64_t *__restrict__ out,
+                                                           uint64_t capacity,
+                                                           unsigned long long *__restrict__ cursor,
+                                                           unsigned long long *__restrict__ rechecks) {
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  __shared__ uint64_t band_mem[kWavesPerBlock][kBandStage];
+  __shared__ __align__(16) float nrm_mem[kWavesPerBlock][32];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
+  if (u >= n_wu) return;  // whole wave leaves; no workgroup barrier follows
+  const WorkUnit wu = wus[u];
+  Stage st{&stage_mem[w][0], 0u};
+  BandSink bs{v.band, v.band_cap, v.band_cursor, Stage{&band_mem[w][0], 0u}};
+  uint64_t n_recheck = 0;
+  mfma_unit<KP, FMT, SJ_WAVE_QB>(v, wu, st, bs, &nrm_mem[w][0], out, capacity, cursor, n_recheck);
+  flush(st, out, capacity, cursor);
+  if (bs.buf) flush(bs.st, bs.buf, bs.cap, bs.cursor);
+  if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
 // Workgroup-cooperative form of the same filter for a single join: the 4
 // waves of a workgroup own 4 x 32*QB query columns of one work unit and
 // share every candidate chunk of kChunk rows, which is fetched from memory
@@ -934,10 +964,12 @@ void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   if (!grid) return;
   constexpr int QB = KP <= 64 ? SJ_WG_QB_SMALL : SJ_WG_QB_LARGE;
   MfmaView v = a.view;
-  // one workgroup per work unit (4 waves x 32*QB queries)
-  hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB>), dim3((uint32_t)a.n_wu), dim3(kBlock), 0, s, v,
-                     a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
-  (void)grid;
+  if (a.per_wave)  // one wave per work unit
+    hipLaunchKernelGGL((k_join_mfma_wave<KP, FMT>), dim3(grid), dim3(kBlock), 0, s, v, a.wu,
+                       a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
+  else  // one workgroup per work unit (4 waves x 32*QB queries)
+    hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB>), dim3((uint32_t)a.n_wu), dim3(kBlock), 0, s,
+                       v, a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
   SJ_HIP(hipGetLastError());
 }
 
@@ -962,6 +994,8 @@ void launch_fmt(const MfmaLaunch &a, hipStream_t s) {
 uint32_t mfma_kp(uint32_t d) { return (d + 15) / 16 * 16; }
 
 int mfma_qb(uint32_t) { return SJ_BATCH_QB; }
+
+uint32_t mfma_wave_queries() { return 32u * SJ_WAVE_QB; }
 
 uint32_t mfma_wg_queries(uint32_t kp) {
   return (uint32_t)(kWavesPerBlock * 32 * (kp <= 64 ? SJ_WG_QB_SMALL : SJ_WG_QB_LARGE));

@@ -46,6 +46,7 @@ struct MfmaLaunch {
   uint64_t *out;
   uint64_t capacity;
   unsigned long long *cursor, *rechecks;
+  int per_wave;  // 1: one wave per work unit (units of mfma_wave_queries())
 };
 
 // One job of a batched launch.
@@ -61,6 +62,8 @@ int mfma_qb(uint32_t kp);
 // Query slots of one work unit of the single-join matrix kernel (a whole
 // workgroup); the batched kernel uses 32*mfma_qb per wave.
 uint32_t mfma_wg_queries(uint32_t kp);
+// Query slots of one work unit of the per-wave single-join kernel.
+uint32_t mfma_wave_queries();
 void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
                       uint32_t kp, const float *centre, void *XA, void *XB, float *cn,
                       double *norm2, double *dist_c, double *fold_err,

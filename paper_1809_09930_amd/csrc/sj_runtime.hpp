@@ -218,6 +218,8 @@ struct sj_index {
   uint32_t kp = 0;
   uint64_t n_pad = 0;
   DevBuf XA, XB, cn, thi, tlo;  // 16-bit operands, FP32 candidate norms, thresholds
+  bool mfma_per_wave = false;   // matrix-core single join with per-wave units
+  uint32_t tq_single = 0, tc_single = 0;  // its unit shape (queries, candidates)
   DevBuf band;                  // deferred recheck list of the matrix-core join
   uint64_t band_cap = 0;
   uint64_t band_hint = 0;       // its expected size from the sampled count
