@@ -169,6 +169,18 @@ typedef struct sj_info {
     uint32_t fp32_form;       /* form of the FP32 filter (enum sj_fp32_form; 0 on the matrix-core path) */
 } sj_info;
 
+/*
+ * Row starts of the result as a CSR neighbour table (the neighbour table
+ * of Algorithm 1, constructNeighborTable): offsets[i] = index of the first
+ * pair (i, .) in the sorted result, offsets[n] = |R|.  With the j column of
+ * selfjoin_fetch_pairs (out_i = NULL) as the neighbour array, the neighbours
+ * of point i are neighbours[offsets[i] .. offsets[i+1]).  Every point is its
+ * own neighbour, so no row is empty.
+ *   offsets  host or device, n + 1 entries, caller-owned.
+ * Errors: SJ_ERR_STATE before a successful run, SJ_ERR_INVALID_ARG for NULL.
+ */
+int selfjoin_fetch_offsets(sj_index *idx, uint64_t *offsets, void *stream);
+
 /* info->struct_size must be set by the caller. */
 int selfjoin_get_info(const sj_index *idx, sj_info *info);
 

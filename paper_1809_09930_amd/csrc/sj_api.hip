@@ -953,6 +953,58 @@ void run(sj_index &ix, hipStream_t s) {
   ix.ran = true;
 }
 
+// Device pointer to the sorted keys [g, g + c): the device-resident result,
+// or a copy of them from the host batches into stage.
+const uint64_t *stage_keys(sj_index &ix, uint64_t g, uint64_t c, DevBuf &stage, hipStream_t s) {
+  if (!ix.on_host) return ix.pairs.as<uint64_t>() + g;
+  stage.ensure(c * 8);
+  uint64_t off = 0, copied = 0, gg = g;
+  for (size_t b = 0; b < ix.host_res.size() && copied < c; ++b) {
+    const uint64_t bc = ix.host_cnt[b];
+    if (gg >= off + bc) {
+      off += bc;
+      continue;
+    }
+    const uint64_t from = gg - off;
+    const uint64_t take = std::min(bc - from, c - copied);
+    SJ_HIP(hipMemcpyAsync(stage.as<uint64_t>() + copied,
+                          static_cast<uint64_t *>(ix.host_res[b].p) + from, take * 8,
+                          hipMemcpyHostToDevice, s));
+    copied += take;
+    gg += take;
+    off += bc;
+  }
+  return stage.as<uint64_t>();
+}
+
+// CSR row starts of the sorted result (Algorithm 1's neighbour table):
+// offsets[i] = index of the first pair (i, .), offsets[n] = |R|.  Every
+// point is its own neighbour, so every row is non-empty.
+void fetch_offsets(sj_index &ix, uint64_t *offsets, hipStream_t s) {
+  if (!ix.ran) fail(SJ_ERR_STATE, "fetch before a successful run");
+  const uint64_t n = ix.n;
+  const bool dev = is_device_pointer(offsets);
+  DevBuf tmp, stage;
+  uint64_t *doff = offsets;
+  if (!dev) {
+    tmp.alloc((n + 1) * 8);
+    doff = tmp.as<uint64_t>();
+  }
+  const uint64_t total = ix.total;
+  SJ_HIP(hipMemcpyAsync(doff + n, &total, 8, hipMemcpyHostToDevice, s));
+  const uint64_t chunk = ix.on_host ? (1ull << 24) : std::max<uint64_t>(total, 1);
+  uint64_t prev = ~0ull;
+  for (uint64_t g = 0; g < total; g += chunk) {
+    const uint64_t c = std::min(chunk, total - g);
+    const uint64_t *src = stage_keys(ix, g, c, stage, s);
+    launch_row_offsets(src, c, g, prev, doff, s);
+    SJ_HIP(hipMemcpyAsync(&prev, src + c - 1, 8, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+  }
+  if (!dev) SJ_HIP(hipMemcpyAsync(offsets, doff, (n + 1) * 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+}
+
 void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint32_t *oj,
            float *od, uint64_t *n_written, hipStream_t s) {
   if (!ix.ran) fail(SJ_ERR_STATE, "fetch before a successful run");
@@ -968,27 +1020,7 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   while (done < cnt) {
     const uint64_t c = std::min(chunk, cnt - done);
     const uint64_t g = first + done;  // global index of the chunk's first pair
-    const uint64_t *src = nullptr;
-    if (!ix.on_host) {
-      src = ix.pairs.as<uint64_t>() + g;
-    } else {
-      // locate the batch holding pair g, copy up to c keys from host storage
-      keys_stage.ensure(c * 8);
-      uint64_t off = 0, copied = 0, gg = g;
-      for (size_t b = 0; b < ix.host_res.size() && copied < c; ++b) {
-        const uint64_t bc = ix.host_cnt[b];
-        if (gg >= off + bc) { off += bc; continue; }
-        const uint64_t from = gg - off;
-        const uint64_t take = std::min(bc - from, c - copied);
-        SJ_HIP(hipMemcpyAsync(keys_stage.as<uint64_t>() + copied,
-                              static_cast<uint64_t *>(ix.host_res[b].p) + from, take * 8,
-                              hipMemcpyHostToDevice, s));
-        copied += take;
-        gg += take;
-        off += bc;
-      }
-      src = keys_stage.as<uint64_t>();
-    }
+    const uint64_t *src = stage_keys(ix, g, c, keys_stage, s);
     if (all_dev) {
       launch_unpack(src, c, oi ? oi + done : nullptr, oj ? oj + done : nullptr,
                     od ? od + done : nullptr, ix.X.as<float>(), ix.pos_of.as<uint32_t>(),
@@ -1081,6 +1113,13 @@ int selfjoin_fetch_pairs(sj_index *idx, uint64_t first, uint64_t max_pairs, uint
     if (!idx || !n_written) fail(SJ_ERR_INVALID_ARG, "NULL argument");
     sj::fetch(*idx, first, max_pairs, out_i, out_j, out_dist, n_written,
               static_cast<hipStream_t>(stream));
+  });
+}
+
+int selfjoin_fetch_offsets(sj_index *idx, uint64_t *offsets, void *stream) {
+  return sj::guarded([&] {
+    if (!idx || !offsets) fail(SJ_ERR_INVALID_ARG, "NULL argument");
+    sj::fetch_offsets(*idx, offsets, static_cast<hipStream_t>(stream));
   });
 }
 

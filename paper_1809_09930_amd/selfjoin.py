@@ -32,7 +32,8 @@ SJ_FP32_NORM = 2
 FP32_FORMS = {"auto": SJ_FP32_AUTO, "difference": SJ_FP32_DIFFERENCE, "norm": SJ_FP32_NORM}
 
 EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_run",
-            "selfjoin_fetch_pairs", "selfjoin_get_info", "selfjoin_get_perm",
+            "selfjoin_fetch_pairs", "selfjoin_fetch_offsets", "selfjoin_get_info",
+            "selfjoin_get_perm",
             "selfjoin_free", "selfjoin_last_error", "selfjoin_run_batched",
             "selfjoin_batch_replay", "selfjoin_batch_range", "selfjoin_batch_fetch",
             "selfjoin_batch_get_info", "selfjoin_batch_free")
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.selfjoin_run.argtypes = [vp, vp, ctypes.POINTER(u64)]
     lib.selfjoin_run.restype = ctypes.c_int
     lib.selfjoin_fetch_pairs.argtypes = [vp, u64, u64, vp, vp, vp, ctypes.POINTER(u64), vp]
+    lib.selfjoin_fetch_offsets.argtypes = [vp, vp, vp]
+    lib.selfjoin_fetch_offsets.restype = ctypes.c_int
     lib.selfjoin_fetch_pairs.restype = ctypes.c_int
     lib.selfjoin_get_info.argtypes = [vp, ctypes.POINTER(SjInfo)]
     lib.selfjoin_get_info.restype = ctypes.c_int
@@ -229,6 +232,16 @@ def selfjoin_fetch_pairs(handle, first: int, out_i=None, out_j=None, out_dist=No
                                                ptr(out_j), ptr(out_dist), ctypes.byref(nw),
                                                _stream_handle(stream)))
     return nw.value
+
+
+def selfjoin_fetch_offsets(handle, offsets, stream=None) -> None:
+    """CSR row starts of the sorted result into an int64 tensor of n + 1
+    entries (CUDA or CPU): the neighbours of point i are the j column
+    [offsets[i], offsets[i + 1])."""
+    if not offsets.is_contiguous():
+        raise ValueError("offsets must be contiguous")
+    _check(load_library().selfjoin_fetch_offsets(handle, offsets.data_ptr(),
+                                                 _stream_handle(stream)))
 
 
 def selfjoin_get_info(handle) -> dict:

@@ -78,6 +78,8 @@ def test_null_handles_are_rejected(lib):
     nw = ctypes.c_uint64()
     assert lib.selfjoin_fetch_pairs(None, 0, 1, None, None, None, ctypes.byref(nw),
                                     None) == selfjoin.SJ_ERR_INVALID_ARG
+    off = (ctypes.c_uint64 * 4)()
+    assert lib.selfjoin_fetch_offsets(None, off, None) == selfjoin.SJ_ERR_INVALID_ARG
     lib.selfjoin_free(None)
 
 

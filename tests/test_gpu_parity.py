@@ -405,3 +405,29 @@ def test_fp32_form_automatic_choice():
     Q = (P * np.float32(1e-3) + np.float32(100.0)).astype(np.float32)  # tiny eps, large norms
     info = assert_same_as_oracle(Q, calibrated(Q, 20))
     assert info["fp32_form"] == 1
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(precision="fp16"), dict(batch_pairs=3000),
+                                  dict(min_batches=4, precision="bf16")])
+def test_csr_neighbour_table(opts):
+    """Row starts plus the j column form the neighbour table: row i holds
+    exactly the oracle's neighbours of i, in ascending order."""
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.uniform_grid(2200, 12, 71)
+    eps = calibrated(P, 25)
+    oi, oj = oracle.bruteforce(P, eps)
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps, **opts)
+    try:
+        total = sj.selfjoin_run(h)
+        nb = torch.empty(total, dtype=torch.int32, device="cuda")
+        sj.selfjoin_fetch_pairs(h, 0, None, nb, None, max_pairs=total)
+        off_d = torch.empty(len(P) + 1, dtype=torch.int64, device="cuda")
+        sj.selfjoin_fetch_offsets(h, off_d)
+        off_h = torch.empty(len(P) + 1, dtype=torch.int64)
+        sj.selfjoin_fetch_offsets(h, off_h)
+    finally:
+        sj.selfjoin_free(h)
+    want = np.searchsorted(oi, np.arange(len(P) + 1), side="left")
+    assert np.array_equal(off_d.cpu().numpy(), want)
+    assert np.array_equal(off_h.numpy(), want)
+    assert np.array_equal(nb.cpu().numpy().view(np.uint32), oj)
