@@ -450,6 +450,19 @@ __global__ void k_cell_products(uint64_t ncell, const uint32_t *__restrict__ cel
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
 
+// Row starts of the sorted result: offsets[i] = index of the first pair
+// (i, .) for every i that occurs in keys [g0, g0 + count) of the whole
+// sorted key list; prev is the key before g0 (~0 when g0 == 0).
+__global__ __launch_bounds__(kBlock) void k_row_offsets(const uint64_t *__restrict__ keys,
+                                                        uint64_t count, uint64_t g0, uint64_t prev,
+                                                        uint64_t *__restrict__ offsets) {
+  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= count) return;
+  const uint64_t i = keys[e] >> 32;
+  const uint64_t before = e ? keys[e - 1] : prev;
+  if (before == ~0ull || (before >> 32) != i) offsets[i] = g0 + e;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -565,6 +578,15 @@ void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint
   if (!ncell) return;
   hipLaunchKernelGGL(k_cell_products, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, ncell,
                      cell_start, cand_sum, out);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_row_offsets(const uint64_t *keys, uint64_t count, uint64_t g0, uint64_t prev,
+                        uint64_t *offsets, hipStream_t s) {
+  if (!count) return;
+  const uint32_t grid = (uint32_t)((count + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_row_offsets, dim3(grid), dim3(kBlock), 0, s, keys, count, g0, prev,
+                     offsets);
   SJ_HIP(hipGetLastError());
 }
 

@@ -78,4 +78,9 @@ void launch_gather_wu(const WorkUnit *src, const uint64_t *keys, uint64_t n, Wor
 void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
                           uint64_t *out, hipStream_t s);
 
+// offsets[i] = global index of the first key (i << 32 | .) among the sorted
+// keys [g0, g0 + count); prev = the key before g0, or ~0 for g0 == 0.
+void launch_row_offsets(const uint64_t *keys, uint64_t count, uint64_t g0, uint64_t prev,
+                        uint64_t *offsets, hipStream_t s);
+
 }  // namespace sj

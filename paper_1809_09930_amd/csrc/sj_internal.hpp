@@ -151,10 +151,6 @@ void launch_join_fp32(const JoinLaunch &a, hipStream_t s);
 // Unpack sorted keys [first, first+count) to (i, j) columns and optionally
 // recompute FP32 distances.
 // Keys are (i << ishift) | j with both fields `ishift` bits wide.
-// offsets[i] = global index of the first key (i << 32 | .) among the sorted
-// keys [g0, g0 + count); prev = the key before g0, or ~0 for g0 == 0.
-void launch_row_offsets(const uint64_t *keys, uint64_t count, uint64_t g0, uint64_t prev,
-                        uint64_t *offsets, hipStream_t s);
 void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i,
                    uint32_t *out_j, float *out_dist, const float *X,
                    const uint32_t *pos_of, const uint16_t *inv_perm,

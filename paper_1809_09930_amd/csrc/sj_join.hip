@@ -587,19 +587,6 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ 
   }
 }
 
-// Row starts of the sorted result: offsets[i] = index of the first pair
-// (i, .) for every i that occurs in keys [g0, g0 + count) of the whole
-// sorted key list; prev is the key before g0 (~0 when g0 == 0).
-__global__ __launch_bounds__(kBlock) void k_row_offsets(const uint64_t *__restrict__ keys,
-                                                        uint64_t count, uint64_t g0, uint64_t prev,
-                                                        uint64_t *__restrict__ offsets) {
-  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= count) return;
-  const uint64_t i = keys[e] >> 32;
-  const uint64_t before = e ? keys[e - 1] : prev;
-  if (before == ~0ull || (before >> 32) != i) offsets[i] = g0 + e;
-}
-
 template <int DP, bool kNorm, bool kSC>
 void launch_form(const JoinLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -698,15 +685,6 @@ void launch_join_fp32(const JoinLaunch &a, hipStream_t s) {
     case 128: launch_dp<128>(a, s); break;
     default: fail(SJ_ERR_INVALID_ARG, "unsupported padded dimension");
   }
-}
-
-void launch_row_offsets(const uint64_t *keys, uint64_t count, uint64_t g0, uint64_t prev,
-                        uint64_t *offsets, hipStream_t s) {
-  if (!count) return;
-  const uint32_t grid = (uint32_t)((count + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_row_offsets, dim3(grid), dim3(kBlock), 0, s, keys, count, g0, prev,
-                     offsets);
-  SJ_HIP(hipGetLastError());
 }
 
 void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i, uint32_t *out_j,
