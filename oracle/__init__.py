@@ -15,6 +15,7 @@ Accelerated Similarity Self-Join for Multi-Dimensional Data", it follows):
 * ``rows_smallest``   K smallest distances per row (C; eps calibration).
 * ``bruteforce_np``   O1': numpy twin of O1 (same rounding sequence).
 * ``exact_int_join``  O0: exact integer join for data on a 2^-g grid.
+* ``join``            O1q: nested-loop general join Q join_eps E (C).
 * ``reorder_perm``    REORDER: variance-ranked dimension order.
 """
 from __future__ import annotations
@@ -57,6 +58,8 @@ def _load():
                           ctypes.c_int64)
     lib.oracle_bruteforce.argtypes = [P, u64, u32, f64, P, P, P, P, u64]
     lib.oracle_bruteforce.restype = i64
+    lib.oracle_join.argtypes = [P, u64, P, u64, u32, f64, P, P, P, P, u64]
+    lib.oracle_join.restype = i64
     lib.oracle_rows.argtypes = [P, u64, u32, f64, P, u64, P, P, P, u64]
     lib.oracle_rows.restype = i64
     lib.oracle_rows_smallest.argtypes = [P, u64, u32, P, u64, u32, P]
@@ -108,6 +111,32 @@ def bruteforce(P, eps: float, with_dist: bool = False):
     os_ = np.empty(total, dtype=np.float64) if with_dist else None
     got = lib.oracle_bruteforce(_ptr(P), n, d, float(eps), None, _ptr(oi),
                                 _ptr(oj), _ptr(os_), total)
+    assert got == total
+    return (oi, oj, os_) if with_dist else (oi, oj)
+
+
+def join(Q, E, eps: float, with_dist: bool = False):
+    """O1q (Section 3.1, the similarity join Q join_eps E): every pair (q, e)
+    of a row of Q and a row of E with the FP64 canonical squared distance
+    <= fl(eps*eps), in ascending (q, e) order.  The self-join is join(P, P).
+    Returns (q, e) or (q, e, s) as numpy arrays."""
+    Q = _points(Q)
+    E = _points(E)
+    m, d = Q.shape
+    n, d2 = E.shape
+    if m and n and d != d2:
+        raise ValueError("Q and E must have the same number of dimensions")
+    d = d if m else d2
+    lib = _load()
+    total = lib.oracle_join(_ptr(Q), m, _ptr(E), n, d, float(eps), None,
+                            None, None, None, 0)
+    if total < 0:
+        raise MemoryError("oracle_join failed")
+    oi = np.empty(total, dtype=np.uint32)
+    oj = np.empty(total, dtype=np.uint32)
+    os_ = np.empty(total, dtype=np.float64) if with_dist else None
+    got = lib.oracle_join(_ptr(Q), m, _ptr(E), n, d, float(eps), None,
+                          _ptr(oi), _ptr(oj), _ptr(os_), total)
     assert got == total
     return (oi, oj, os_) if with_dist else (oi, oj)
 
@@ -221,21 +250,24 @@ def bruteforce_np(P, eps: float):
     return np.concatenate(out_i), np.concatenate(out_j)
 
 
-def exact_int_join(A, T: int):
+def exact_int_join(A, T: int, B=None):
     """O0: the join in exact integer arithmetic for data on a 2^-g grid.
     A = P * 2^g as int64, T = floor(eps2 * 2^(2g)); pair iff
-    sum_t (A_i,t - A_j,t)^2 <= T.  The caller keeps |A| < 2^30 and d small
-    enough that the int64 sums cannot overflow (asserted).  Returns (i, j)."""
+    sum_t (A_i,t - A_j,t)^2 <= T.  With B given, the general join A join B
+    (rows i of A, rows j of B) instead of the self-join of A.  The caller
+    keeps |A|, |B| < 2^30 and d small enough that the int64 sums cannot
+    overflow (asserted).  Returns (i, j)."""
     A = np.ascontiguousarray(A, dtype=np.int64)
+    B = A if B is None else np.ascontiguousarray(B, dtype=np.int64)
     n, d = A.shape
-    if n:
-        span = int(A.max()) - int(A.min())
+    if n and len(B):
+        span = max(int(A.max()), int(B.max())) - min(int(A.min()), int(B.min()))
         assert span * span * d < 2 ** 62, "int64 sums could overflow"
     out_i, out_j = [], []
     for i in range(n):
-        acc = np.zeros(n, dtype=np.int64)
+        acc = np.zeros(len(B), dtype=np.int64)
         for t in range(d):
-            diff = A[:, t] - A[i, t]
+            diff = B[:, t] - A[i, t]
             acc += diff * diff
         js = np.nonzero(acc <= T)[0]
         out_i.append(np.full(len(js), i, dtype=np.uint32))

@@ -99,6 +99,54 @@ int64_t oracle_bruteforce(const float *P, uint64_t n, uint32_t d, double eps,
     return (int64_t)total;
 }
 
+/* ---------------------------------------------------------------------------
+ * O1q: the general similarity join Q join_eps E of Section 3.1 (the self-join
+ * is the case Q = E): every pair (q, e), q a row of Q and e a row of E, with
+ * the canonical squared distance <= fl(eps*eps), nested loops over all m*n
+ * pairs, output in ascending (q, e) order.  Same count/fill passes and
+ * return convention as O1.
+ * ------------------------------------------------------------------------- */
+int64_t oracle_join(const float *Q, uint64_t m, const float *E, uint64_t n,
+                    uint32_t d, double eps, uint64_t *row_counts,
+                    uint32_t *out_i, uint32_t *out_j, double *out_s,
+                    uint64_t cap)
+{
+    const double eps2 = eps * eps;
+    uint64_t *cnt = (uint64_t *)calloc(m ? m : 1, sizeof(uint64_t));
+    if (!cnt) return -2;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < (int64_t)m; ++q) {
+        uint64_t c = 0;
+        for (uint64_t e = 0; e < n; ++e)
+            if (canon_sq(Q + (uint64_t)q * d, E + e * d, d) <= eps2) ++c;
+        cnt[q] = c;
+    }
+    uint64_t total = 0;
+    for (uint64_t q = 0; q < m; ++q) {
+        if (row_counts) row_counts[q] = cnt[q];
+        uint64_t c = cnt[q];
+        cnt[q] = total;
+        total += c;
+    }
+    if (out_j == NULL) { free(cnt); return (int64_t)total; }
+    if (total > cap) { free(cnt); return -1; }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < (int64_t)m; ++q) {
+        uint64_t w = cnt[q];
+        for (uint64_t e = 0; e < n; ++e) {
+            double s = canon_sq(Q + (uint64_t)q * d, E + e * d, d);
+            if (s <= eps2) {
+                if (out_i) out_i[w] = (uint32_t)q;
+                out_j[w] = (uint32_t)e;
+                if (out_s) out_s[w] = s;
+                ++w;
+            }
+        }
+    }
+    free(cnt);
+    return (int64_t)total;
+}
+
 /* O1 restricted to a list of query rows: the full row of each listed query
  * (all j in ascending order).  Same predicate and ordering as above. */
 int64_t oracle_rows(const float *P, uint64_t n, uint32_t d, double eps,

@@ -327,3 +327,95 @@ def test_calibration_hits_the_target_on_its_sample():
     # one ulp less epsilon loses at least one pair of the sample
     cnt2, _ = oracle.rows(P, float(np.nextafter(eps, 0)), q)
     assert cnt2.sum() < cnt.sum()
+
+
+# --------------------------------------------------------------------------
+# O1q: the general join Q join_eps E (Section 3.1; the self-join is E join E)
+# --------------------------------------------------------------------------
+def _r2(k):
+    """Number of integer points (x, y) with x^2 + y^2 = k, from Jacobi's
+    two-square formula r2(k) = 4 (d1(k) - d3(k)), d1 / d3 counting the
+    divisors of k that are 1 / 3 mod 4 (r2(0) = 1)."""
+    if k == 0:
+        return 1
+    d1 = sum(1 for t in range(1, k + 1) if k % t == 0 and t % 4 == 1)
+    d3 = sum(1 for t in range(1, k + 1) if k % t == 0 and t % 4 == 3)
+    return 4 * (d1 - d3)
+
+
+@pytest.mark.parametrize("eps", [1.0, 2.0, 3.0, 5 ** 0.5, 8 ** 0.5, 10 ** 0.5, 2.5, 0.5])
+def test_join_lattice_counts_follow_the_two_square_formula(eps):
+    """Queries at integer points of the plane against the integer lattice
+    [-6, 6]^2: each query's neighbour count is the number of lattice points
+    in the closed disc of squared radius fl(eps*eps), i.e. the sum of r2(k)
+    over integers k <= fl(eps*eps) (ties at exactly eps are included)."""
+    g = np.arange(-6, 7, dtype=np.float32)
+    E = np.array([(x, y) for x in g for y in g], dtype=np.float32)
+    Q = np.array([(0, 0), (1, 0), (-2, 1), (3, 3)], dtype=np.float32)
+    eps2 = eps * eps
+    K = int(np.floor(eps2))
+    expect = sum(_r2(k) for k in range(0, K + 1))
+    qi, ej = oracle.join(Q, E, eps)
+    counts = np.bincount(qi, minlength=len(Q))
+    assert counts.tolist() == [expect] * len(Q)
+    # and every reported pair is really within eps in exact arithmetic
+    d2 = ((Q[qi].astype(np.int64) - E[ej].astype(np.int64)) ** 2).sum(1)
+    assert (d2 <= K).all()
+
+
+@pytest.mark.parametrize("m,n,d,seed,shift", [
+    (300, 500, 2, 11, 0.0), (400, 700, 5, 12, 0.25), (250, 900, 16, 13, 0.5),
+    (200, 300, 40, 14, 0.0)])
+def test_join_equals_exact_integer_join_of_two_sets(m, n, d, seed, shift):
+    """On 2^-g grid data the join equals the exact integer join; the query
+    set is drawn separately and shifted so part of it lies outside E's box."""
+    g = datagen.GRID_UNIFORM
+    E = datagen.uniform_grid(n, d, seed, g)
+    Q = datagen.uniform_grid(m, d, seed + 100, g) + np.float32(shift)
+    eps, _ = oracle.calibrate_eps(E, 12, np.arange(0, n, 3))
+    T = int(np.floor(eps * eps * float(2 ** (2 * g))))
+    A = (Q.astype(np.float64) * float(2 ** g)).astype(np.int64)
+    B = (E.astype(np.float64) * float(2 ** g)).astype(np.int64)
+    exact = pairset(*oracle.exact_int_join(A, T, B))
+    qi, ej = oracle.join(Q, E, eps)
+    assert pairset(qi, ej) == exact
+    key = qi.astype(np.uint64) << np.uint64(32) | ej.astype(np.uint64)
+    assert (np.diff(key.astype(np.int64)) > 0).all()
+    if shift == 0.0:
+        assert len(exact) > m  # the case is not vacuous
+
+
+def test_join_special_cases_self_join_and_transpose():
+    """Q = E gives the self-join; swapping the sets transposes the pairs
+    (the squared difference of two floats is the same in either order)."""
+    E = datagen.uniform_grid(600, 8, 21)
+    Q = datagen.uniform_grid(350, 8, 22)
+    eps, _ = oracle.calibrate_eps(E, 20, np.arange(0, 600, 4))
+    si, sj = oracle.bruteforce(E, eps)
+    ji, jj = oracle.join(E, E, eps)
+    assert np.array_equal(si, ji) and np.array_equal(sj, jj)
+    a = pairset(*oracle.join(Q, E, eps))
+    b = pairset(*oracle.join(E, Q, eps))
+    assert a == {(y, x) for x, y in b}
+    assert len(a) > 0
+
+
+@pytest.mark.parametrize("m,n,d,seed", [(500, 2000, 3, 31), (400, 1500, 24, 32)])
+def test_join_matches_scipy_kdtree_ball_query(m, n, d, seed):
+    sp = pytest.importorskip("scipy.spatial")
+    E = datagen.uniform_grid(n, d, seed)
+    Q = datagen.uniform_grid(m, d, seed + 7)
+    eps, _ = oracle.calibrate_eps(E, 15, np.arange(0, n, 5))
+    tree = sp.cKDTree(E.astype(np.float64))
+    theirs = set()
+    for q, js in enumerate(tree.query_ball_point(Q.astype(np.float64), eps, p=2.0)):
+        theirs.update((q, j) for j in js)
+    assert pairset(*oracle.join(Q, E, eps)) == theirs
+
+
+def test_join_empty_sides():
+    E = datagen.uniform_grid(50, 4, 41)
+    z = np.zeros((0, 4), np.float32)
+    for Q, EE in ((z, E), (E, z), (z, z)):
+        qi, ej = oracle.join(Q, EE, 0.3)
+        assert len(qi) == 0 and len(ej) == 0
