@@ -172,14 +172,44 @@ typedef struct sj_info {
 /*
  * Row starts of the result as a CSR neighbour table (the neighbour table
  * of Algorithm 1, constructNeighborTable): offsets[i] = index of the first
- * pair (i, .) in the sorted result, offsets[n] = |R|.  With the j column of
- * selfjoin_fetch_pairs (out_i = NULL) as the neighbour array, the neighbours
- * of point i are neighbours[offsets[i] .. offsets[i+1]).  Every point is its
- * own neighbour, so no row is empty.
+ * pair (i, .) in the sorted result (the number of pairs of rows below i),
+ * offsets[n] = |R|.  With the j column of selfjoin_fetch_pairs (out_i =
+ * NULL) as the neighbour array, the neighbours of point i are
+ * neighbours[offsets[i] .. offsets[i+1]).  In a self-join every point is its
+ * own neighbour, so no row is empty; a query handle's rows may be.
  *   offsets  host or device, n + 1 entries, caller-owned.
  * Errors: SJ_ERR_STATE before a successful run, SJ_ERR_INVALID_ARG for NULL.
  */
 int selfjoin_fetch_offsets(sj_index *idx, uint64_t *offsets, void *stream);
+
+/*
+ * The general similarity join Q join_eps E (Section 3.1: the self-join is the
+ * case Q = E): every pair (q, e) of a query point q of Q and an indexed
+ * point e of E with dist(q, e) <= epsilon, under the canonical predicate
+ * above (caller's dimension order, FP64).  E is an index built by
+ * selfjoin_build_index, whose epsilon, k, grid, dimension order, precision
+ * and options the join uses; Q is binned into E's grid and searched against
+ * E's cells (Algorithm 1's kernel with the query points taken from Q).
+ *   entries  the index of E.  It is only read: it may still be run and
+ *            fetched itself, and several query handles may share it, but it
+ *            must not be freed before every query handle built on it.
+ *   queries  host or device, row-major float32 [m][d] (d = E's d),
+ *            caller-owned; read during the call only.
+ *   m        query count (0 allowed: an empty result), m <= 2^32 - 1.
+ *   out      receives the query handle, an sj_index of its own: selfjoin_run
+ *            joins Q with E; selfjoin_fetch_pairs returns (i, j) = (query row,
+ *            row of E) sorted by (i, j), with no self pairs unless Q and E
+ *            share points; selfjoin_fetch_offsets returns m + 1 row starts
+ *            (rows may be empty); selfjoin_get_info reports n = m;
+ *            selfjoin_get_perm returns E's order.  Release with selfjoin_free.
+ * Errors: SJ_ERR_INVALID_ARG for NULL arguments, NaN/Inf query coordinates,
+ * entries that is itself a query handle, a current device other than E's,
+ * or (FP16 index only) an epsilon so large against E's range that query
+ * coordinates could leave the FP16 range (build E with SJ_PREC_BF16 or
+ * SJ_PREC_FP32 then); SJ_ERR_OUT_OF_MEMORY; SJ_ERR_DEVICE.
+ */
+int selfjoin_build_query(const sj_index *entries, const float *queries, uint64_t m,
+                         void *stream, sj_index **out);
 
 /* info->struct_size must be set by the caller. */
 int selfjoin_get_info(const sj_index *idx, sj_info *info);

@@ -180,6 +180,9 @@ struct BuildTmp {  // temporaries of the grid builds (thread scratch)
   TmpBuf nbr_count, cand_sum, prod;
 };
 
+uint64_t build_neighbors(sj_index &ix, const sj_index &E, NbrParams np, BuildTmp &t,
+                         hipStream_t s, bool keep);
+
 // Keys, sort, gather, compaction and neighbour counts for geometry g.
 // Returns the candidate count C and fills ncell.
 uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t, hipStream_t s,
@@ -202,17 +205,27 @@ uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t
   SJ_HIP(hipMemcpyAsync(&h_ncell, d_ncell, 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
   ix.ncell = h_ncell;
-  const uint64_t nc = ix.ncell;
+  return build_neighbors(ix, ix, g.np, t, s, keep);
+}
 
-  NbrParams np = g.np;
+// Adjacent non-empty cells of ix's cells in E's cell table (E = ix in a
+// self-join; np of E's grid).  Returns the candidate count C, the sum over
+// ix's points of the sizes of their adjacent cells of E; with keep, fills
+// ix.nbr_off / ix.nbr_cell.
+uint64_t build_neighbors(sj_index &ix, const sj_index &E, NbrParams np, BuildTmp &t,
+                         hipStream_t s, bool keep) {
+  const uint64_t nc = ix.ncell;
+  const uint64_t ne = E.ncell;
   const uint64_t kFence = 8192;
   uint64_t fs = 1;
-  while ((nc + fs - 1) / fs > kFence) fs <<= 1;
+  while ((ne + fs - 1) / fs > kFence) fs <<= 1;
   np.fstride = (uint32_t)fs;
-  np.nfence = (uint32_t)((nc + fs - 1) / fs);
+  np.nfence = (uint32_t)((ne + fs - 1) / fs);
   SJ_HIP(hipMemsetAsync(t.nbr_count.p, 0, (nc + 1) * 4, s));
-  launch_neighbors(0, ix.cell_key.as<uint64_t>(), ix.cell_start.as<uint32_t>(), nc, np,
-                   t.nbr_count.as<uint32_t>(), t.cand_sum.as<uint64_t>(), nullptr, nullptr, s);
+  SJ_HIP(hipMemsetAsync(t.cand_sum.p, 0, (nc + 1) * 8, s));
+  launch_neighbors(0, ix.cell_key.as<uint64_t>(), nc, E.cell_key.as<uint64_t>(),
+                   E.cell_start.as<uint32_t>(), ne, np, t.nbr_count.as<uint32_t>(),
+                   t.cand_sum.as<uint64_t>(), nullptr, nullptr, s);
   launch_cell_products(nc, ix.cell_start.as<uint32_t>(), t.cand_sum.as<uint64_t>(),
                        t.prod.as<uint64_t>(), s);
   uint64_t *d_c = reinterpret_cast<uint64_t *>(t.small.as<char>() + 8);
@@ -229,8 +242,9 @@ uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t
     SJ_HIP(hipStreamSynchronize(s));
     ix.n_nbr = h_nn;
     ix.nbr_cell.alloc((uint64_t)h_nn * 4);
-    launch_neighbors(1, ix.cell_key.as<uint64_t>(), ix.cell_start.as<uint32_t>(), nc, np,
-                     nullptr, nullptr, ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(), s);
+    launch_neighbors(1, ix.cell_key.as<uint64_t>(), nc, E.cell_key.as<uint64_t>(),
+                     E.cell_start.as<uint32_t>(), ne, np, nullptr, nullptr,
+                     ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(), s);
   }
   SJ_HIP(hipStreamSynchronize(s));
   return h_c;
@@ -243,8 +257,9 @@ uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &
   TmpBuf cnt;
   cnt.alloc((nc + 1) * 4);
   SJ_HIP(hipMemsetAsync(cnt.p, 0, (nc + 1) * 4, s));
-  launch_runs(0, sym, nc, ix.cell_start.as<uint32_t>(), ix.nbr_off.as<uint32_t>(),
-              ix.nbr_cell.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, s);
+  const uint32_t *ecs = entries_of(ix).cell_start.as<uint32_t>();  // candidate cells
+  launch_runs(0, sym, nc, ecs, ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(),
+              cnt.as<uint32_t>(), nullptr, nullptr, s);
   off.alloc((nc + 1) * 4);
   uint32_t *d_tot = t.small.as<uint32_t>() + 8;
   exclusive_scan_u32(cnt.as<uint32_t>(), off.as<uint32_t>(), nc + 1, d_tot, t.scan.p, s);
@@ -252,8 +267,8 @@ uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &
   SJ_HIP(hipMemcpyAsync(&h_tot, d_tot, 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
   runs.alloc((uint64_t)h_tot * sizeof(uint2));
-  launch_runs(1, sym, nc, ix.cell_start.as<uint32_t>(), ix.nbr_off.as<uint32_t>(),
-              ix.nbr_cell.as<uint32_t>(), nullptr, off.as<uint32_t>(), runs.as<uint2>(), s);
+  launch_runs(1, sym, nc, ecs, ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(), nullptr,
+              off.as<uint32_t>(), runs.as<uint2>(), s);
   return h_tot;
 }
 
@@ -388,12 +403,13 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
   ix.thi.alloc(np * 4);
   ix.tlo.alloc(np * 4);
   ScratchScope scope;  // ends after the final synchronisation below
-  TmpBuf cdev, norm2, distc, fold, maxima;
+  TmpBuf cdev, norm2, distc, fold;
   cdev.alloc(d * 4);
   norm2.alloc(np * 8);
   distc.alloc(np * 8);
   fold.alloc(np * 8);
-  maxima.alloc(64);
+  ix.mfma_max.alloc(64);  // kept: the thresholds of query handles use them
+  DevBuf &maxima = ix.mfma_max;
   SJ_HIP(hipMemcpyAsync(cdev.p, centre.data(), d * 4, hipMemcpyHostToDevice, s));
   launch_mfma_prep(fmt, ix.X.as<float>(), ix.n, np, d, ix.dp, ix.kp, cdev.as<float>(), ix.XA.p,
                    ix.XB.p, ix.cn.as<float>(), norm2.as<double>(), distc.as<double>(),
@@ -410,6 +426,8 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
   band.s_lo = ix.eps2 / (1.0 + g64);
   launch_mfma_thresholds(ix.n, np, band, norm2.as<double>(), distc.as<double>(),
                          maxima.as<unsigned long long>(), ix.thi.as<float>(), ix.tlo.as<float>(), s);
+  ix.mfma_centre = centre;
+  ix.mfma_band = band;
   SJ_HIP(hipStreamSynchronize(s));
 }
 
@@ -422,16 +440,27 @@ void mfma_prepare(sj_index &ix, hipStream_t s) {
 constexpr double kNormBandMax = 0.005;
 constexpr uint32_t kNormAutoMaxDp = 16;
 
+// Bounds and margin factor of the norm-form tables (see k_norm_tables).
+struct NormParams {
+  double s_hi, s_lo, kappa;
+};
+NormParams norm_params(const sj_index &ix) {
+  const double g64 = gamma_n((double)ix.d + 2.0, std::ldexp(1.0, -53));
+  const double margin = std::ldexp(1.0, -50);
+  NormParams p;
+  p.s_hi = ix.eps2 / (1.0 - g64) * (1.0 + margin);
+  p.s_lo = ix.eps2 / (1.0 + g64) * (1.0 - margin);
+  p.kappa = 4.0 * gamma_n((double)ix.dp + 16.0, std::ldexp(1.0, -24));
+  return p;
+}
+
 void choose_fp32_form(sj_index &ix, hipStream_t s) {
   ix.norm_form = false;
   ix.info.fp32_form = SJ_FP32_DIFFERENCE;
   if (ix.opt.fp32_form == SJ_FP32_DIFFERENCE || ix.n == 0) return;
   if (ix.opt.fp32_form == SJ_FP32_AUTO && ix.dp > kNormAutoMaxDp) return;
-  const double g64 = gamma_n((double)ix.d + 2.0, std::ldexp(1.0, -53));
-  const double margin = std::ldexp(1.0, -50);
-  const double s_hi = ix.eps2 / (1.0 - g64) * (1.0 + margin);
-  const double s_lo = ix.eps2 / (1.0 + g64) * (1.0 - margin);
-  const double kappa = 4.0 * gamma_n((double)ix.dp + 16.0, std::ldexp(1.0, -24));
+  const NormParams np = norm_params(ix);
+  const double s_hi = np.s_hi, s_lo = np.s_lo, kappa = np.kappa;
   if (!(s_hi < 1e30)) return;  // keep the difference form for huge thresholds
   const uint64_t row = (uint64_t)norm_table_row(ix.dp);
   ix.norm_qa.alloc(ix.n * row * 4);
@@ -591,7 +620,9 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     }
   }
   ix.k = g.k;
+  ix.geom = g;
   ix.candidates = build_grid(ix, P, g, t, s, true);
+  ix.n_near = n;
 
   // candidate runs and the work units of the symmetric full join
   ix.n_runs_sym = build_runs(ix, 1, ix.run_off_sym, ix.runs_sym, t, s);
@@ -624,14 +655,200 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   ix.info.ms_build = elapsed_ms(ev0, ev1);
 }
 
+// The general join Q join_eps E (Section 3.1; the self-join is E join E):
+// the queries are binned into E's grid (same k, cell side and origin, the
+// dimension order of E's variance reorder), each query cell searches its
+// 3^k adjacent cells in E's cell table, and the distance kernels compare
+// query rows of q against candidate rows of E, one direction only.
+void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream_t s) {
+  ScratchScope scope;  // temporaries live until the final event synchronisation
+  Event ev0, ev1;
+  SJ_HIP(hipEventRecord(ev0.e, s));
+  const uint64_t m = q.n;
+  const uint32_t d = E.d;
+  q.entries = &E;
+  q.d = d;
+  q.dp = E.dp;
+  q.eps = E.eps;
+  q.eps2 = E.eps2;
+  q.opt = E.opt;
+  q.perm = E.perm;
+  q.inv_perm = E.inv_perm;
+  q.dmin = E.dmin;
+  q.dmax = E.dmax;
+  q.lo32 = E.lo32;
+  q.hi32 = E.hi32;
+  q.k = E.k;
+  q.geom = E.geom;
+  q.prec = E.prec;
+  q.fmt = E.fmt;
+  q.kp = E.kp;
+  q.norm_form = E.norm_form;
+  q.info.fp32_form = E.info.fp32_form;
+  q.tq = E.tq;
+  q.counters.alloc(64);
+  q.perm_d.alloc(d * 4);
+  q.inv_perm_d.alloc(d * 2);
+  SJ_HIP(hipMemcpyAsync(q.perm_d.p, q.perm.data(), d * 4, hipMemcpyHostToDevice, s));
+  SJ_HIP(hipMemcpyAsync(q.inv_perm_d.p, q.inv_perm.data(), d * 2, hipMemcpyHostToDevice, s));
+  q.n_near = 0;
+  q.ncell = 0;
+  auto finish = [&] {
+    SJ_HIP(hipEventRecord(ev1.e, s));
+    SJ_HIP(hipEventSynchronize(ev1.e));
+    q.info.ms_build = elapsed_ms(ev0, ev1);
+  };
+  if (m == 0) return finish();
+  TmpBuf staged;
+  const float *P = queries;
+  if (!is_device_pointer(queries)) {
+    staged.alloc(m * d * sizeof(float));
+    SJ_HIP(hipMemcpyAsync(staged.p, queries, m * d * sizeof(float), hipMemcpyHostToDevice, s));
+    P = staged.as<float>();
+  }
+  {  // finiteness of the queries
+    TmpBuf st;
+    st.alloc(d * 8 + 64);
+    uint32_t *gmin = st.as<uint32_t>(), *gmax = gmin + d, *bad = gmax + d;
+    launch_minmax(P, m, d, gmin, gmax, bad, s);
+    uint32_t hbad = 0;
+    SJ_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (hbad) fail(SJ_ERR_INVALID_ARG, "queries contain NaN or Inf coordinates");
+  }
+  if (E.n == 0) return finish();  // nothing to find
+  const Geometry &g = E.geom;
+  // queries more than two cell sides outside E's range in some dimension
+  // have no neighbour (k_query_keys); the rest lie within that margin
+  const double margin = 2.0 * g.kp.w;
+  std::vector<double> bounds(2 * (size_t)d);
+  for (uint32_t t = 0; t < d; ++t) {
+    bounds[t] = E.dmin[t] - margin;
+    bounds[d + t] = E.dmax[t] + margin;
+  }
+  if (E.prec != SJ_PREC_FP32 && E.fmt == kFmtF16) {
+    // the near queries' centred coordinates stay below 16384, so -2 x~ fits FP16
+    double reach = 0.0;
+    for (uint32_t r = 0; r < d; ++r) {
+      const uint32_t t = E.perm[r];
+      const double c = (double)E.mfma_centre[r];
+      reach = std::max(reach, std::max(std::fabs(bounds[d + t] - c), std::fabs(bounds[t] - c)));
+    }
+    if (!(reach * (1.0 + 1e-6) <= 16384.0))
+      fail(SJ_ERR_INVALID_ARG,
+           "epsilon is too large against the FP16 range of this index; build it with "
+           "SJ_PREC_BF16 or SJ_PREC_FP32 for this query join");
+  }
+  BuildTmp t;
+  t.keys[0].alloc(m * 8);
+  t.keys[1].alloc(m * 8);
+  t.ids[0].alloc(m * 4);
+  t.ids[1].alloc(m * 4);
+  t.flag.alloc(m * 4);
+  t.radix.alloc(radix_tmp_bytes(m));
+  t.scan.alloc(scan_tmp_bytes(m + 1) + 256);
+  t.small.alloc(256);
+  t.nbr_count.alloc((m + 1) * 4);
+  t.cand_sum.alloc((m + 1) * 8);
+  t.prod.alloc((m + 1) * 8);
+  TmpBuf bd;
+  bd.alloc(bounds.size() * 8);
+  SJ_HIP(hipMemcpyAsync(bd.p, bounds.data(), bounds.size() * 8, hipMemcpyHostToDevice, s));
+  unsigned long long *d_far = reinterpret_cast<unsigned long long *>(t.small.as<char>() + 64);
+  SJ_HIP(hipMemsetAsync(d_far, 0, 8, s));
+  const uint64_t far_key = 1ull << g.key_bits;  // above every key of key_bits bits
+  launch_query_keys(P, m, d, g.kp, bd.as<double>(), bd.as<double>() + d, far_key,
+                    t.keys[0].as<uint64_t>(), t.ids[0].as<uint32_t>(), d_far, s);
+  uint64_t *kb[2] = {t.keys[0].as<uint64_t>(), t.keys[1].as<uint64_t>()};
+  uint32_t *vb[2] = {t.ids[0].as<uint32_t>(), t.ids[1].as<uint32_t>()};
+  std::vector<int> shifts;
+  for (uint32_t b = 0; b <= g.key_bits; b += 8) shifts.push_back((int)b);
+  radix_sort_u64(kb, vb, m, shifts.data(), (int)shifts.size(), t.radix.p, s);
+  q.X.alloc((m + 1) * q.dp * 4);
+  q.orig_id.alloc(m * 4);
+  q.pos_of.alloc(m * 4);
+  launch_gather(P, m, d, q.dp, q.perm_d.as<uint32_t>(), vb[0], q.X.as<float>(),
+                q.orig_id.as<uint32_t>(), q.pos_of.as<uint32_t>(), s);
+  unsigned long long h_far = 0;
+  SJ_HIP(hipMemcpyAsync(&h_far, d_far, 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  q.n_near = m - h_far;  // far queries sort last: positions [n_near, m)
+  q.cell_key.alloc((q.n_near + 1) * 8);
+  q.cell_start.alloc((q.n_near + 1) * 4);
+  if (q.n_near) {
+    uint32_t *d_ncell = t.small.as<uint32_t>();
+    launch_compact(kb[0], q.n_near, g.fine_bits, t.flag.as<uint32_t>(), d_ncell,
+                   q.cell_key.as<uint64_t>(), q.cell_start.as<uint32_t>(), t.scan.p, s);
+    uint32_t h_ncell = 0;
+    SJ_HIP(hipMemcpyAsync(&h_ncell, d_ncell, 4, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    q.ncell = h_ncell;
+  }
+  if (q.ncell == 0) return finish();
+  q.candidates = build_neighbors(q, E, g.np, t, s, true);
+  q.n_runs_full = build_runs(q, 0, q.run_off_full, q.runs_full, t, s);
+  if (q.norm_form) {  // the queries' table of the norm form (E holds the candidates')
+    const NormParams np = norm_params(q);
+    const uint64_t row = (uint64_t)norm_table_row(q.dp);
+    q.norm_qa.alloc(q.n_near * row * 4);
+    TmpBuf cr, nsum;
+    cr.alloc((q.n_near + 1) * row * 4);
+    nsum.alloc(8);
+    SJ_HIP(hipMemsetAsync(nsum.p, 0, 8, s));
+    launch_norm_tables(q.X.as<float>(), q.n_near, q.dp, np.s_hi, np.s_lo, np.kappa,
+                       q.norm_qa.as<float>(), cr.as<float>(), nsum.as<double>(), s);
+  }
+  uint64_t ev = 0;
+  DevBuf probe;
+  build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq, 16384, probe, &ev, s);
+  q.tc = choose_tc(ev, q.tq);
+  if (q.prec == SJ_PREC_FP32) {
+    q.n_wu = build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq, q.tc, q.wu,
+                             &q.evaluated_sym, s, kWuByStretch);
+  } else {
+    // the queries' operands and thresholds against E's centring and maxima
+    q.n_pad = (q.n_near + 31) / 32 * 32 + 64;
+    const uint64_t np = q.n_pad;
+    q.XB.alloc(np * q.kp * 2);
+    q.thi.alloc(np * 4);
+    q.tlo.alloc(np * 4);
+    TmpBuf xa, cn, cdev, norm2, distc, fold, maxima;
+    xa.alloc(np * q.kp * 2);
+    cn.alloc(np * 4);
+    cdev.alloc(d * 4);
+    norm2.alloc(np * 8);
+    distc.alloc(np * 8);
+    fold.alloc(np * 8);
+    maxima.alloc(64);
+    SJ_HIP(hipMemcpyAsync(cdev.p, E.mfma_centre.data(), d * 4, hipMemcpyHostToDevice, s));
+    launch_mfma_prep(q.fmt, q.X.as<float>(), q.n_near, np, d, q.dp, q.kp, cdev.as<float>(), xa.p,
+                     q.XB.p, cn.as<float>(), norm2.as<double>(), distc.as<double>(),
+                     fold.as<double>(), maxima.as<unsigned long long>(), s);
+    launch_mfma_thresholds(q.n_near, np, E.mfma_band, norm2.as<double>(), distc.as<double>(),
+                           E.mfma_max.as<unsigned long long>(), q.thi.as<float>(),
+                           q.tlo.as<float>(), s);
+    const uint32_t tq_wg = mfma_wg_queries(q.kp);
+    q.mfma_per_wave = (double)q.n_near / (double)q.ncell < kWaveUnitsBelow;
+    q.tq_single = q.mfma_per_wave ? mfma_wave_queries() : tq_wg;
+    q.tc_single = q.mfma_per_wave ? choose_tc(ev, q.tq_single)
+                                  : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
+    q.n_wu_m = build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq_single,
+                               q.tc_single, q.wu_m, &q.evaluated_sym_m, s, kWuByStretch);
+    q.evaluated_sym = q.evaluated_sym_m;
+  }
+  finish();
+}
+
 MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist, int sym) {
+  const sj_index &E = entries_of(ix);  // candidates; ix holds the queries
   MfmaView v{};
-  v.XA = ix.XA.p;
+  v.XA = E.XA.p;
   v.XB = ix.XB.p;
-  v.cn = ix.cn.as<float>();
+  v.cn = E.cn.as<float>();
   v.thi = ix.thi.as<float>();
   v.tlo = ix.tlo.as<float>();
-  v.X = ix.X.as<float>();
+  v.X = E.X.as<float>();
+  v.Xq = ix.X.as<float>();
   v.inv_perm = ix.inv_perm_d.as<uint16_t>();
   v.runs = runs;
   v.qlist = qlist;
@@ -652,9 +869,12 @@ constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
                  const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
                  hipStream_t s, float *ms) {
+  const sj_index &E = entries_of(ix);  // candidates; ix holds the queries
   JoinLaunch a{};
-  a.X = ix.X.as<float>();
-  a.orig_id = ix.orig_id.as<uint32_t>();
+  a.X = E.X.as<float>();
+  a.orig_id = E.orig_id.as<uint32_t>();
+  a.Xq = ix.X.as<float>();
+  a.qid = ix.orig_id.as<uint32_t>();
   a.inv_perm = ix.inv_perm_d.as<uint16_t>();
   a.wu = wu.as<WorkUnit>();
   a.n_wu = n_wu;
@@ -675,7 +895,7 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
   a.rq = fp32_rq_for(ix.dp, ix.norm_form);
   a.norm = ix.norm_form ? 1 : 0;
   a.QA = ix.norm_qa.as<float>();
-  a.CR = ix.norm_cr.as<float>();
+  a.CR = E.norm_cr.as<float>();
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
   if (ix.prec != SJ_PREC_FP32) {
@@ -735,7 +955,7 @@ uint64_t read_counter(sj_index &ix, int which, hipStream_t s) {
 // a count-only pass over a fraction of the points).  Counts pairs the FP32
 // filter cannot reject, so it is an upper-bound estimate.
 uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
-  const uint64_t n = ix.n;
+  const uint64_t n = ix.n_near;  // query positions in cells
   const uint64_t target = 8192;
   const uint64_t stride = n <= target ? 1 : n / target;
   const uint64_t nq = (n + stride - 1) / stride;
@@ -774,8 +994,9 @@ uint64_t default_budget() {
 }
 
 void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s) {
-  const uint32_t bits = bits_for(ix.n ? ix.n - 1 : 0);
-  std::vector<int> sh = digit_shifts(bits, bits);
+  const uint64_t ne = entries_of(ix).n;
+  const uint32_t ibits = bits_for(ix.n ? ix.n - 1 : 0), jbits = bits_for(ne ? ne - 1 : 0);
+  std::vector<int> sh = digit_shifts(jbits, ibits);
   DevBuf tmp;
   tmp.alloc(radix_tmp_bytes(cnt));
   uint64_t *kb[2] = {a.as<uint64_t>(), b.as<uint64_t>()};
@@ -792,8 +1013,9 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
     ix.pairs.alloc(cap * 8);
     SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
     const bool m = ix.prec != SJ_PREC_FP32;
-    join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, ix.runs_sym, nullptr, 1, 0,
-                ix.pairs.as<uint64_t>(), cap, s, &ms_join);
+    const bool self = !ix.entries;  // a self-join's units are symmetric
+    join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, self ? ix.runs_sym : ix.runs_full,
+                nullptr, self ? 1 : 0, 0, ix.pairs.as<uint64_t>(), cap, s, &ms_join);
     ix.info.join_launches++;
     const uint64_t got = read_counter(ix, 0, s);
     if (got <= cap) {
@@ -807,7 +1029,9 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
   ix.info.ms_join += ms_join;
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
-  if (ix.prec != SJ_PREC_FP32) launch_pos_to_id(ix.pairs.as<uint64_t>(), ix.total, ix.orig_id.as<uint32_t>(), s);
+  if (ix.prec != SJ_PREC_FP32)
+    launch_pos_to_id(ix.pairs.as<uint64_t>(), ix.total, ix.orig_id.as<uint32_t>(),
+                     entries_of(ix).orig_id.as<uint32_t>(), s);
   other.alloc(ix.total * 8);
   sort_pairs(ix, ix.pairs, other, ix.total, s);
   SJ_HIP(hipEventRecord(e1.e, s));
@@ -891,7 +1115,9 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
       sl.tmp2.ensure(std::max<uint64_t>(got, 1) * 8);
       Event e0, e1;
       SJ_HIP(hipEventRecord(e0.e, s));
-      if (mf) launch_pos_to_id(sl.keys.as<uint64_t>(), got, ix.orig_id.as<uint32_t>(), s);
+      if (mf)
+        launch_pos_to_id(sl.keys.as<uint64_t>(), got, ix.orig_id.as<uint32_t>(),
+                         entries_of(ix).orig_id.as<uint32_t>(), s);
       sort_pairs(ix, sl.keys, sl.tmp2, got, s);
       SJ_HIP(hipEventRecord(e1.e, s));
       PinnedBuf hb;
@@ -927,7 +1153,7 @@ void run(sj_index &ix, hipStream_t s) {
   ix.pairs.reset();
   ix.host_res.clear();
   ix.host_cnt.clear();
-  if (ix.n == 0) {
+  if (ix.n == 0 || ix.n_near == 0 || ix.ncell == 0) {
     ix.total = 0;
     ix.info.batches = 0;
   } else {
@@ -978,29 +1204,35 @@ const uint64_t *stage_keys(sj_index &ix, uint64_t g, uint64_t c, DevBuf &stage, 
 }
 
 // CSR row starts of the sorted result (Algorithm 1's neighbour table):
-// offsets[i] = index of the first pair (i, .), offsets[n] = |R|.  Every
-// point is its own neighbour, so every row is non-empty.
+// offsets[i] = index of the first pair (i, .), offsets[n] = |R|, from the
+// pairs per row (counted on the device, chunk by chunk) by an exclusive
+// scan.  In a self-join every point is its own neighbour, so no row is
+// empty; a query join's rows may be.
 void fetch_offsets(sj_index &ix, uint64_t *offsets, hipStream_t s) {
   if (!ix.ran) fail(SJ_ERR_STATE, "fetch before a successful run");
   const uint64_t n = ix.n;
   const bool dev = is_device_pointer(offsets);
+  ScratchScope scope;  // the stream is synchronised before returning
+  TmpBuf counts, scan, total_d;
   DevBuf tmp, stage;
   uint64_t *doff = offsets;
   if (!dev) {
     tmp.alloc((n + 1) * 8);
     doff = tmp.as<uint64_t>();
   }
+  counts.alloc((n + 1) * 8);
+  scan.alloc(scan_tmp_bytes(n + 1) + 64);
+  total_d.alloc(64);
+  SJ_HIP(hipMemsetAsync(counts.p, 0, (n + 1) * 8, s));
   const uint64_t total = ix.total;
-  SJ_HIP(hipMemcpyAsync(doff + n, &total, 8, hipMemcpyHostToDevice, s));
   const uint64_t chunk = ix.on_host ? (1ull << 24) : std::max<uint64_t>(total, 1);
-  uint64_t prev = ~0ull;
   for (uint64_t g = 0; g < total; g += chunk) {
     const uint64_t c = std::min(chunk, total - g);
     const uint64_t *src = stage_keys(ix, g, c, stage, s);
-    launch_row_offsets(src, c, g, prev, doff, s);
-    SJ_HIP(hipMemcpyAsync(&prev, src + c - 1, 8, hipMemcpyDeviceToHost, s));
-    SJ_HIP(hipStreamSynchronize(s));
+    launch_row_counts(src, c, counts.as<unsigned long long>(), s);
+    SJ_HIP(hipStreamSynchronize(s));  // the stage is reused by the next chunk
   }
+  exclusive_scan_u64(counts.as<uint64_t>(), doff, n + 1, total_d.as<uint64_t>(), scan.p, s);
   if (!dev) SJ_HIP(hipMemcpyAsync(offsets, doff, (n + 1) * 8, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
 }
@@ -1010,6 +1242,7 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   if (!ix.ran) fail(SJ_ERR_STATE, "fetch before a successful run");
   if (first > ix.total) fail(SJ_ERR_RANGE, "first is beyond the result");
   const uint64_t cnt = std::min(max_pairs, ix.total - first);
+  const sj_index &E = entries_of(ix);  // the j column's points
   const bool dev_i = !oi || is_device_pointer(oi);
   const bool dev_j = !oj || is_device_pointer(oj);
   const bool dev_d = !od || is_device_pointer(od);
@@ -1024,14 +1257,16 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
     if (all_dev) {
       launch_unpack(src, c, oi ? oi + done : nullptr, oj ? oj + done : nullptr,
                     od ? od + done : nullptr, ix.X.as<float>(), ix.pos_of.as<uint32_t>(),
-                    ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s);
+                    E.X.as<float>(), E.pos_of.as<uint32_t>(), ix.inv_perm_d.as<uint16_t>(), ix.d,
+                    ix.dp, s);
     } else {
       si.ensure(c * 4);
       sj2.ensure(c * 4);
       sd.ensure(c * 4);
       launch_unpack(src, c, oi ? si.as<uint32_t>() : nullptr, oj ? sj2.as<uint32_t>() : nullptr,
                     od ? sd.as<float>() : nullptr, ix.X.as<float>(), ix.pos_of.as<uint32_t>(),
-                    ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s);
+                    E.X.as<float>(), E.pos_of.as<uint32_t>(), ix.inv_perm_d.as<uint16_t>(), ix.d,
+                    ix.dp, s);
       if (oi) SJ_HIP(hipMemcpyAsync(oi + done, si.p, c * 4, hipMemcpyDefault, s));
       if (oj) SJ_HIP(hipMemcpyAsync(oj + done, sj2.p, c * 4, hipMemcpyDefault, s));
       if (od) SJ_HIP(hipMemcpyAsync(od + done, sd.p, c * 4, hipMemcpyDefault, s));
@@ -1096,6 +1331,26 @@ int selfjoin_build_index(const float *points, uint64_t n, uint32_t d, double eps
     ix->info.struct_size = sizeof(sj_info);
     sj::build(*ix, points, static_cast<hipStream_t>(stream));
     *out = ix.release();
+  });
+}
+
+int selfjoin_build_query(const sj_index *entries, const float *queries, uint64_t m,
+                         void *stream, sj_index **out) {
+  return sj::guarded([&] {
+    if (!out || !entries) fail(SJ_ERR_INVALID_ARG, "NULL argument");
+    if (entries->entries) fail(SJ_ERR_INVALID_ARG, "entries is itself a query handle");
+    if (m > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "m must be below 2^32");
+    if (m > 0 && !queries) fail(SJ_ERR_INVALID_ARG, "queries is NULL");
+    int dev = 0;
+    SJ_HIP(hipGetDevice(&dev));
+    if (dev != entries->device)
+      fail(SJ_ERR_INVALID_ARG, "the current device is not the device of entries");
+    std::unique_ptr<sj_index> q(new sj_index());
+    q->device = dev;
+    q->n = m;
+    q->info.struct_size = sizeof(sj_info);
+    sj::build_query(*q, *entries, queries, static_cast<hipStream_t>(stream));
+    *out = q.release();
   });
 }
 

@@ -510,8 +510,8 @@ int selfjoin_batch_fetch(sj_batch *b, uint32_t job, uint64_t first, uint64_t max
     if (cnt) {
       if (all_dev) {
         sj::launch_unpack(src, cnt, out_i, out_j, out_dist, ix.X.as<float>(),
-                          ix.pos_of.as<uint32_t>(), ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s,
-                          20);
+                          ix.pos_of.as<uint32_t>(), ix.X.as<float>(), ix.pos_of.as<uint32_t>(),
+                          ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s, 20);
       } else {
         sj::DevBuf si, sjj, sd;
         si.alloc(cnt * 4);
@@ -519,8 +519,9 @@ int selfjoin_batch_fetch(sj_batch *b, uint32_t job, uint64_t first, uint64_t max
         sd.alloc(cnt * 4);
         sj::launch_unpack(src, cnt, out_i ? si.as<uint32_t>() : nullptr,
                           out_j ? sjj.as<uint32_t>() : nullptr, out_dist ? sd.as<float>() : nullptr,
-                          ix.X.as<float>(), ix.pos_of.as<uint32_t>(), ix.inv_perm_d.as<uint16_t>(),
-                          ix.d, ix.dp, s, 20);
+                          ix.X.as<float>(), ix.pos_of.as<uint32_t>(), ix.X.as<float>(),
+                          ix.pos_of.as<uint32_t>(), ix.inv_perm_d.as<uint16_t>(), ix.d, ix.dp, s,
+                          20);
         if (out_i) SJ_HIP(hipMemcpyAsync(out_i, si.p, cnt * 4, hipMemcpyDefault, s));
         if (out_j) SJ_HIP(hipMemcpyAsync(out_j, sjj.p, cnt * 4, hipMemcpyDefault, s));
         if (out_dist) SJ_HIP(hipMemcpyAsync(out_dist, sd.p, cnt * 4, hipMemcpyDefault, s));

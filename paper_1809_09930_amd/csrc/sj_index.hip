@@ -113,16 +113,11 @@ __global__ __launch_bounds__(kBlock) void k_variance(const float *__restrict__ P
 // ---------------------------------------------------------------------------
 // a3: linearised cell key over the first k reordered dimensions.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_cellkey(const float *__restrict__ P, uint64_t n,
-                                                    uint32_t d, KeyParams kp,
-                                                    uint64_t *__restrict__ keys,
-                                                    uint32_t *__restrict__ ids) {
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ uint64_t sort_key(const float *__restrict__ x, const KeyParams &kp) {
   uint64_t key = 0;
   for (uint32_t r = 0; r < kp.k; ++r) {
-    const double x = (double)P[i * d + kp.dim[r]];
-    double c = floor((x - kp.org[r]) / kp.w);
+    const double xv = (double)x[kp.dim[r]];
+    double c = floor((xv - kp.org[r]) / kp.w);
     c = c < 0.0 ? 0.0 : c;
     uint64_t ci = (uint64_t)c;
     ci = ci > kp.cmax[r] ? kp.cmax[r] : ci;
@@ -133,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_cellkey(const float *__restrict__ P,
     uint32_t f[kFineMaxDims];
     const uint32_t fmax = (1u << kp.fb) - 1u;
     for (uint32_t r = 0; r < kp.fm; ++r) {
-      double v = ((double)P[i * d + kp.fdim[r]] - kp.forg[r]) * kp.fscale[r];
+      double v = ((double)x[kp.fdim[r]] - kp.forg[r]) * kp.fscale[r];
       v = v < 0.0 ? 0.0 : v;
       uint32_t q = (uint32_t)v;
       f[r] = q > fmax ? fmax : q;
@@ -141,8 +136,48 @@ __global__ __launch_bounds__(kBlock) void k_cellkey(const float *__restrict__ P,
     for (int b = (int)kp.fb - 1; b >= 0; --b)
       for (uint32_t r = 0; r < kp.fm; ++r) fine = (fine << 1) | ((f[r] >> b) & 1u);
   }
-  keys[i] = (key << (kp.fm * kp.fb)) | fine;
+  return (key << (kp.fm * kp.fb)) | fine;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cellkey(const float *__restrict__ P, uint64_t n,
+                                                    uint32_t d, KeyParams kp,
+                                                    uint64_t *__restrict__ keys,
+                                                    uint32_t *__restrict__ ids) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = sort_key(P + i * d, kp);
   ids[i] = (uint32_t)i;
+}
+
+// Keys of query points in the grid of an indexed set E (the general join
+// Q join_eps E of Section 3.1).  A query with some coordinate more than
+// two cell widths outside E's range [lo_t, hi_t] (lo = lo_t - 2w and
+// hi = hi_t + 2w here, caller's dimension order) is farther than eps from
+// every point of E: it gets far_key, which sorts after every cell key, and
+// is counted in *n_far.  The others are clamped into E's grid like E's own
+// points; a clamped query searches cells that include all of its true
+// neighbour cells.
+__global__ __launch_bounds__(kBlock) void k_query_keys(const float *__restrict__ Q, uint64_t m,
+                                                       uint32_t d, KeyParams kp,
+                                                       const double *__restrict__ lo,
+                                                       const double *__restrict__ hi,
+                                                       uint64_t far_key,
+                                                       uint64_t *__restrict__ keys,
+                                                       uint32_t *__restrict__ ids,
+                                                       unsigned long long *__restrict__ n_far) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool far = false;
+  if (i < m) {
+    const float *x = Q + i * d;
+    for (uint32_t t = 0; t < d; ++t) {
+      const double v = (double)x[t];
+      far = far || v < lo[t] || v > hi[t];
+    }
+    keys[i] = far ? far_key : sort_key(x, kp);
+    ids[i] = (uint32_t)i;
+  }
+  const uint64_t fm = ballot(far);
+  if (lane_id() == 0 && fm) atomicAdd(n_far, (unsigned long long)__builtin_popcountll(fm));
 }
 
 // ---------------------------------------------------------------------------
@@ -226,8 +261,11 @@ __device__ __forceinline__ int64_t find_cell(uint64_t key, const uint64_t *__res
   return (a < ncell && cell_key[a] == key) ? (int64_t)a : -1;
 }
 
+// Query cells are qkey[0 .. nq) (the table itself in a self-join); the
+// table is cell_key[0 .. ncell) with its cell_start.
 __global__ __launch_bounds__(kBlock) void k_neighbors(
-    int pass, const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ cell_start,
+    int pass, const uint64_t *__restrict__ qkey, uint64_t nq,
+    const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ cell_start,
     uint64_t ncell, NbrParams np, uint32_t *__restrict__ nbr_count,
     uint64_t *__restrict__ cand_sum, const uint32_t *__restrict__ nbr_off,
     uint32_t *__restrict__ nbr_cell) {
@@ -238,8 +276,8 @@ __global__ __launch_bounds__(kBlock) void k_neighbors(
   const uint32_t l = lane_id();
   const uint64_t wid = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   const uint64_t nw = (uint64_t)gridDim.x * kWavesPerBlock;
-  for (uint64_t A = wid; A < ncell; A += nw) {
-    const uint64_t keyA = cell_key[A];
+  for (uint64_t A = wid; A < nq; A += nw) {
+    const uint64_t keyA = qkey[A];
     int64_t cA[kKeyMaxDims];
     for (uint32_t r = 0; r < np.k; ++r) cA[r] = (int64_t)((keyA / np.mult[r]) % np.m[r]);
     uint32_t count = 0, wpos = (pass == 1) ? nbr_off[A] : 0u;
@@ -450,17 +488,25 @@ __global__ void k_cell_products(uint64_t ncell, const uint32_t *__restrict__ cel
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
 
-// Row starts of the sorted result: offsets[i] = index of the first pair
-// (i, .) for every i that occurs in keys [g0, g0 + count) of the whole
-// sorted key list; prev is the key before g0 (~0 when g0 == 0).
-__global__ __launch_bounds__(kBlock) void k_row_offsets(const uint64_t *__restrict__ keys,
-                                                        uint64_t count, uint64_t g0, uint64_t prev,
-                                                        uint64_t *__restrict__ offsets) {
+// Pairs per row of sorted keys (row = key >> 32): counts[i] += the number
+// of keys of row i.  Each wave adds one count per row it holds: the lane
+// that starts a run of equal rows inside the wave adds the run's length.
+__global__ __launch_bounds__(kBlock) void k_row_counts(const uint64_t *__restrict__ keys,
+                                                       uint64_t count,
+                                                       unsigned long long *__restrict__ counts) {
   const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= count) return;
-  const uint64_t i = keys[e] >> 32;
-  const uint64_t before = e ? keys[e - 1] : prev;
-  if (before == ~0ull || (before >> 32) != i) offsets[i] = g0 + e;
+  const uint32_t l = lane_id();
+  const bool live = e < count;
+  const uint64_t row = live ? keys[e] >> 32 : 0;
+  const bool head = live && (l == 0 || (keys[e - 1] >> 32) != row);
+  const uint64_t heads = ballot(head);
+  const uint64_t lives = ballot(live);
+  if (!head) return;
+  // the run ends at the next head above this lane, or at the last live lane
+  const uint64_t above = heads & ~((2ull << l) - 1ull);
+  const uint32_t end = above ? (uint32_t)__builtin_ctzll(above)
+                             : (uint32_t)(64 - __builtin_clzll(lives));
+  atomicAdd(&counts[row], (unsigned long long)(end - l));
 }
 
 }  // namespace
@@ -492,6 +538,15 @@ void launch_cellkey(const float *P, uint64_t n, uint32_t d, const KeyParams &kp,
   SJ_HIP(hipGetLastError());
 }
 
+void launch_query_keys(const float *Q, uint64_t m, uint32_t d, const KeyParams &kp,
+                       const double *lo, const double *hi, uint64_t far_key, uint64_t *keys,
+                       uint32_t *ids, unsigned long long *n_far, hipStream_t s) {
+  if (!m) return;
+  hipLaunchKernelGGL(k_query_keys, dim3(blocks_for(m)), dim3(kBlock), 0, s, Q, m, d, kp, lo, hi,
+                     far_key, keys, ids, n_far);
+  SJ_HIP(hipGetLastError());
+}
+
 void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const uint32_t *perm,
                    const uint32_t *sorted_ids, float *X, uint32_t *orig_id, uint32_t *pos_of,
                    hipStream_t s) {
@@ -514,14 +569,15 @@ void launch_compact(const uint64_t *keys, uint64_t n, uint32_t fine_shift, uint3
   SJ_HIP(hipGetLastError());
 }
 
-void launch_neighbors(int pass, const uint64_t *cell_key, const uint32_t *cell_start,
-                      uint64_t ncell, const NbrParams &np, uint32_t *nbr_count, uint64_t *cand_sum,
-                      const uint32_t *nbr_off, uint32_t *nbr_cell, hipStream_t s) {
-  if (!ncell) return;
-  const uint64_t waves = ncell;
+void launch_neighbors(int pass, const uint64_t *qkey, uint64_t nq, const uint64_t *cell_key,
+                      const uint32_t *cell_start, uint64_t ncell, const NbrParams &np,
+                      uint32_t *nbr_count, uint64_t *cand_sum, const uint32_t *nbr_off,
+                      uint32_t *nbr_cell, hipStream_t s) {
+  if (!nq || !ncell) return;
+  const uint64_t waves = nq;
   uint32_t grid = (uint32_t)std::min<uint64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 4096);
-  hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(kBlock), 0, s, pass, cell_key, cell_start,
-                     ncell, np, nbr_count, cand_sum, nbr_off, nbr_cell);
+  hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(kBlock), 0, s, pass, qkey, nq, cell_key,
+                     cell_start, ncell, np, nbr_count, cand_sum, nbr_off, nbr_cell);
   SJ_HIP(hipGetLastError());
 }
 
@@ -581,12 +637,11 @@ void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint
   SJ_HIP(hipGetLastError());
 }
 
-void launch_row_offsets(const uint64_t *keys, uint64_t count, uint64_t g0, uint64_t prev,
-                        uint64_t *offsets, hipStream_t s) {
+void launch_row_counts(const uint64_t *keys, uint64_t count, unsigned long long *counts,
+                       hipStream_t s) {
   if (!count) return;
-  const uint32_t grid = (uint32_t)((count + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_row_offsets, dim3(grid), dim3(kBlock), 0, s, keys, count, g0, prev,
-                     offsets);
+  hipLaunchKernelGGL(k_row_counts, dim3(blocks_for(count)), dim3(kBlock), 0, s, keys, count,
+                     counts);
   SJ_HIP(hipGetLastError());
 }
 

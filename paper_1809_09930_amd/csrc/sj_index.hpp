@@ -44,6 +44,12 @@ void launch_variance(const float *P, uint32_t d, uint64_t stride, uint64_t m, do
                      hipStream_t s);
 void launch_cellkey(const float *P, uint64_t n, uint32_t d, const KeyParams &kp, uint64_t *keys,
                     uint32_t *ids, hipStream_t s);
+// Sort keys of query points Q [m][d] in an indexed set's grid kp; queries
+// outside [lo_t, hi_t] in some dimension t get far_key (see k_query_keys),
+// and *n_far (device, zeroed by the caller) counts them.
+void launch_query_keys(const float *Q, uint64_t m, uint32_t d, const KeyParams &kp,
+                       const double *lo, const double *hi, uint64_t far_key, uint64_t *keys,
+                       uint32_t *ids, unsigned long long *n_far, hipStream_t s);
 void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const uint32_t *perm,
                    const uint32_t *sorted_ids, float *X, uint32_t *orig_id, uint32_t *pos_of,
                    hipStream_t s);
@@ -51,9 +57,12 @@ void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const ui
 void launch_compact(const uint64_t *keys, uint64_t n, uint32_t fine_shift, uint32_t *flag_tmp,
                     uint32_t *d_ncell, uint64_t *cell_key, uint32_t *cell_start, void *scan_tmp,
                     hipStream_t s);
-void launch_neighbors(int pass, const uint64_t *cell_key, const uint32_t *cell_start,
-                      uint64_t ncell, const NbrParams &np, uint32_t *nbr_count, uint64_t *cand_sum,
-                      const uint32_t *nbr_off, uint32_t *nbr_cell, hipStream_t s);
+// Adjacent non-empty cells of the query cells qkey[0 .. nq) in the table
+// cell_key[0 .. ncell) (qkey = cell_key, nq = ncell in a self-join).
+void launch_neighbors(int pass, const uint64_t *qkey, uint64_t nq, const uint64_t *cell_key,
+                      const uint32_t *cell_start, uint64_t ncell, const NbrParams &np,
+                      uint32_t *nbr_count, uint64_t *cand_sum, const uint32_t *nbr_off,
+                      uint32_t *nbr_cell, hipStream_t s);
 void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
                  const uint32_t *nbr_off, const uint32_t *nbr_cell, uint32_t *run_count,
                  const uint32_t *run_off, uint2 *runs, hipStream_t s);
@@ -78,9 +87,9 @@ void launch_gather_wu(const WorkUnit *src, const uint64_t *keys, uint64_t n, Wor
 void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
                           uint64_t *out, hipStream_t s);
 
-// offsets[i] = global index of the first key (i << 32 | .) among the sorted
-// keys [g0, g0 + count); prev = the key before g0, or ~0 for g0 == 0.
-void launch_row_offsets(const uint64_t *keys, uint64_t count, uint64_t g0, uint64_t prev,
-                        uint64_t *offsets, hipStream_t s);
+// counts[i] += number of keys (i << 32 | .) among the sorted keys
+// [0, count) (counts zeroed by the caller; chunks may be added one by one).
+void launch_row_counts(const uint64_t *keys, uint64_t count, unsigned long long *counts,
+                       hipStream_t s);
 
 }  // namespace sj

@@ -116,6 +116,8 @@ struct DeviceIndex;  // defined in sj_index.hip
 struct JoinLaunch {
   const float *X;           // [n][dp] points in cell order, reordered dims, zero padded
   const uint32_t *orig_id;  // [n] position -> caller index
+  const float *Xq;          // query rows (X itself in a self-join), same layout
+  const uint32_t *qid;      // query position -> caller query index
   const uint16_t *inv_perm; // [d] caller dim t -> reordered position
   const WorkUnit *wu;
   uint64_t n_wu;
@@ -133,7 +135,7 @@ struct JoinLaunch {
   unsigned long long *rechecks;  // FP64 rechecks performed
   int rq;                   // queries per lane (1, 2 or 4); units hold 64*rq queries
   int norm;                 // 1: norm form with the tables QA / CR
-  const float *QA, *CR;     // [n][norm_table_row(dp)] query / candidate tables
+  const float *QA, *CR;     // [.][norm_table_row(dp)] query (of Xq) / candidate (of X) tables
 };
 
 // Queries per lane the FP32 kernel uses for padded dimension dp.
@@ -150,10 +152,12 @@ void launch_join_fp32(const JoinLaunch &a, hipStream_t s);
 
 // Unpack sorted keys [first, first+count) to (i, j) columns and optionally
 // recompute FP32 distances.
-// Keys are (i << ishift) | j with both fields `ishift` bits wide.
+// Keys are (i << ishift) | j with both fields `ishift` bits wide; i is a
+// row of the query points (Xq, qpos_of), j of the indexed points (X, pos_of).
 void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i,
-                   uint32_t *out_j, float *out_dist, const float *X,
-                   const uint32_t *pos_of, const uint16_t *inv_perm,
-                   uint32_t d, uint32_t dp, hipStream_t s, uint32_t ishift = 32);
+                   uint32_t *out_j, float *out_dist, const float *Xq,
+                   const uint32_t *qpos_of, const float *X, const uint32_t *pos_of,
+                   const uint16_t *inv_perm, uint32_t d, uint32_t dp, hipStream_t s,
+                   uint32_t ishift = 32);
 
 }  // namespace sj

@@ -93,12 +93,13 @@ static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 flo
 #endif
 
 // Canonical predicate on positions a, b of the cell-ordered rows.
-__device__ __noinline__ bool canonical_within(const float *__restrict__ X, uint32_t a, uint32_t b,
+__device__ __noinline__ bool canonical_within(const float *__restrict__ XA, uint32_t a,
+                                              const float *__restrict__ XB, uint32_t b,
                                               const uint16_t *__restrict__ inv_perm, uint32_t d,
                                               uint32_t dp, double eps2) {
 #pragma clang fp contract(off)
-  const float *pa = X + (uint64_t)a * dp;
-  const float *pb = X + (uint64_t)b * dp;
+  const float *pa = XA + (uint64_t)a * dp;
+  const float *pb = XB + (uint64_t)b * dp;
   double acc = 0.0;
   for (uint32_t t = 0; t < d; ++t) {
     const uint32_t r = inv_perm[t];
@@ -172,7 +173,7 @@ __device__ __forceinline__ Head<DP, kNorm> load_head(const float *__restrict__ c
 template <int DP, int RQ, bool kCount>
 __device__ __forceinline__ void classify_emit(
     const Lanes<DP, RQ> &L, int r, uint32_t c, uint64_t m, uint64_t lo_m,
-    const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
+    const float *__restrict__ Xq, const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
     const uint16_t *__restrict__ inv_perm, uint32_t d, double eps2, bool symmetric,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
@@ -185,7 +186,8 @@ __device__ __forceinline__ void classify_emit(
   const uint64_t band = m & ~acc;
   if (band) {
     bool ok = false;
-    if ((band >> lane_id()) & 1ull) ok = canonical_within(X, L.pos[r], c, inv_perm, d, DP, eps2);
+    if ((band >> lane_id()) & 1ull)
+      ok = canonical_within(Xq, L.pos[r], X, c, inv_perm, d, DP, eps2);
     acc |= ballot(ok);
     n_recheck += (uint64_t)__builtin_popcountll(band);
   }
@@ -208,7 +210,7 @@ __device__ __forceinline__ void classify_emit(
 template <int DP, int RQ, bool kFilter, bool kCount, bool kSC>
 __device__ __forceinline__ void eval_candidate(
     const Lanes<DP, RQ> &L, const Head<DP, false> &hd, uint32_t c,
-    const float *__restrict__ crow, const float *__restrict__ X,
+    const float *__restrict__ crow, const float *__restrict__ Xq, const float *__restrict__ X,
     const uint32_t *__restrict__ orig_id, const uint16_t *__restrict__ inv_perm, uint32_t d,
     float lo, float hi, double eps2, bool symmetric, WaveStage &st, uint64_t *__restrict__ out,
     uint64_t capacity, unsigned long long *__restrict__ cursor, uint64_t &n_recheck,
@@ -269,8 +271,8 @@ __device__ __forceinline__ void eval_candidate(
   for (int r = 0; r < RQ; ++r) {
     const uint64_t m = ballot(s[r] <= hi);
     if (m == 0) continue;
-    classify_emit<DP, RQ, kCount>(L, r, c, m, ballot(s[r] <= lo), X, orig_id, inv_perm, d, eps2,
-                                  symmetric, st, out, capacity, cursor, n_recheck, n_count);
+    classify_emit<DP, RQ, kCount>(L, r, c, m, ballot(s[r] <= lo), Xq, X, orig_id, inv_perm, d,
+                                  eps2, symmetric, st, out, capacity, cursor, n_recheck, n_count);
   }
 }
 
@@ -287,7 +289,7 @@ template <int DP, int RQ, bool kFilter, bool kCount, bool kSC>
 __device__ __forceinline__ void eval_candidate_norm(
     const Lanes<DP, RQ> &L, const NormLanes<DP, RQ, true> &N, const Head<DP, true> &hd,
     uint32_t c, const float *__restrict__ crow, const float *__restrict__ cr,
-    const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
+    const float *__restrict__ Xq, const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
     const uint16_t *__restrict__ inv_perm, uint32_t d, double eps2, bool symmetric,
     WaveStage &st, uint64_t *__restrict__ out, uint64_t capacity,
     unsigned long long *__restrict__ cursor, uint64_t &n_recheck, uint64_t &n_count) {
@@ -333,7 +335,7 @@ __device__ __forceinline__ void eval_candidate_norm(
   for (int r = 0; r < RQ; ++r) {
     const uint64_t m = ballot(a[r] <= rej);
     if (m == 0) continue;
-    classify_emit<DP, RQ, kCount>(L, r, c, m, ballot(a[r] + N.qa[r][K] <= acc_t), X, orig_id,
+    classify_emit<DP, RQ, kCount>(L, r, c, m, ballot(a[r] + N.qa[r][K] <= acc_t), Xq, X, orig_id,
                                   inv_perm, d, eps2, symmetric, st, out, capacity, cursor,
                                   n_recheck, n_count);
   }
@@ -344,6 +346,7 @@ __device__ __forceinline__ void eval_candidate_norm(
 template <int DP, int RQ, bool kCount, bool kNorm, bool kSC>
 __device__ __forceinline__ void join_body(
     const float *__restrict__ X, const uint32_t *__restrict__ orig_id,
+    const float *__restrict__ Xq, const uint32_t *__restrict__ qid,
     const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,
     const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, float lo,
     float hi, double eps2, int symmetric, uint64_t *__restrict__ out,
@@ -364,9 +367,9 @@ __device__ __forceinline__ void join_body(
     const bool live = slot < wu.q1;
     const uint32_t p = live ? (qlist ? qlist[slot] : slot) : 0u;
     L.pos[r] = live ? p : 0xffffffffu;
-    L.id[r] = live ? orig_id[p] : 0u;
+    L.id[r] = live ? qid[p] : 0u;
     L.init[r] = live ? 0.0f : __builtin_inff();
-    const float4 *row = reinterpret_cast<const float4 *>(X + (uint64_t)p * DP);
+    const float4 *row = reinterpret_cast<const float4 *>(Xq + (uint64_t)p * DP);
     const float sc = kNorm ? -2.0f : 1.0f;  // exact scaling
 #pragma unroll
     for (int t = 0; t < DP / 4; ++t) {
@@ -406,13 +409,13 @@ __device__ __forceinline__ void join_body(
       const float *ccr = kNorm ? CR + (uint64_t)from * NR : nullptr;
       auto eval = [&](const Head<DP, kNorm> &h, uint32_t c) __attribute__((always_inline)) {
         if constexpr (kNorm)
-          eval_candidate_norm<DP, RQ, kF, kCount, kSC>(L, NL, h, c, crow, ccr, X, orig_id,
+          eval_candidate_norm<DP, RQ, kF, kCount, kSC>(L, NL, h, c, crow, ccr, Xq, X, orig_id,
                                                        inv_perm, d, eps2, sym, st, out, capacity,
                                                        cursor, n_recheck, n_count);
         else
-          eval_candidate<DP, RQ, kF, kCount, kSC>(L, h, c, crow, X, orig_id, inv_perm, d, lo, hi,
-                                                  eps2, sym, st, out, capacity, cursor, n_recheck,
-                                                  n_count);
+          eval_candidate<DP, RQ, kF, kCount, kSC>(L, h, c, crow, Xq, X, orig_id, inv_perm, d, lo,
+                                                  hi, eps2, sym, st, out, capacity, cursor,
+                                                  n_recheck, n_count);
       };
       auto next = [&]() __attribute__((always_inline)) {
         crow += DP;
@@ -460,6 +463,7 @@ __device__ __forceinline__ void join_body(
 
 #define SJ_JOIN_PARAMS                                                                          \
   const float *__restrict__ X, const uint32_t *__restrict__ orig_id,                            \
+      const float *__restrict__ Xq, const uint32_t *__restrict__ qid,                           \
       const uint16_t *__restrict__ inv_perm, const WorkUnit *__restrict__ wus, uint64_t n_wu,   \
       const uint2 *__restrict__ runs, const uint32_t *__restrict__ qlist, uint32_t d, float lo, \
       float hi, double eps2, int symmetric, uint64_t *__restrict__ out,                         \
@@ -467,11 +471,12 @@ __device__ __forceinline__ void join_body(
       unsigned long long *__restrict__ rechecks, const float *__restrict__ QA,                  \
       const float *__restrict__ CR
 
-// The self-join distance kernel: emits result pairs.
+// The distance kernel (queries Xq against candidates X; Xq = X in a
+// self-join): emits result pairs.
 template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_join_fp32(SJ_JOIN_PARAMS) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  join_body<DP, RQ, false, kNorm, kSC>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
+  join_body<DP, RQ, false, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
                                        eps2, symmetric, out, capacity, cursor, rechecks,
                                        stage_mem, QA, CR);
 }
@@ -479,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fp32(SJ_JOIN_PARAMS) {
 // The estimation kernel (count only) used to size result buffers.
 template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_count_fp32(SJ_JOIN_PARAMS) {
-  join_body<DP, RQ, true, kNorm, kSC>(X, orig_id, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
+  join_body<DP, RQ, true, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
                                       eps2, symmetric, out, capacity, cursor, rechecks, nullptr,
                                       QA, CR);
 }
@@ -563,6 +568,8 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ 
                                                    uint64_t count, uint32_t *__restrict__ out_i,
                                                    uint32_t *__restrict__ out_j,
                                                    float *__restrict__ out_dist,
+                                                   const float *__restrict__ Xq,
+                                                   const uint32_t *__restrict__ qpos_of,
                                                    const float *__restrict__ X,
                                                    const uint32_t *__restrict__ pos_of,
                                                    const uint16_t *__restrict__ inv_perm,
@@ -575,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ 
   if (out_i) out_i[e] = i;
   if (out_j) out_j[e] = j;
   if (out_dist) {
-    const float *a = X + (uint64_t)pos_of[i] * dp;
+    const float *a = Xq + (uint64_t)qpos_of[i] * dp;
     const float *b = X + (uint64_t)pos_of[j] * dp;
     float s = 0.0f;
     for (uint32_t t = 0; t < d; ++t) {
@@ -595,11 +602,11 @@ void launch_form(const JoinLaunch &a, hipStream_t s) {
                             : (DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1));
   if (a.count_only)
     hipLaunchKernelGGL((k_count_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
-                       a.orig_id, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
+                       a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
                        a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks, a.QA, a.CR);
   else
     hipLaunchKernelGGL((k_join_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
-                       a.orig_id, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
+                       a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
                        a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks, a.QA, a.CR);
   SJ_HIP(hipGetLastError());
 }
@@ -688,13 +695,13 @@ void launch_join_fp32(const JoinLaunch &a, hipStream_t s) {
 }
 
 void launch_unpack(const uint64_t *keys, uint64_t count, uint32_t *out_i, uint32_t *out_j,
-                   float *out_dist, const float *X, const uint32_t *pos_of,
-                   const uint16_t *inv_perm, uint32_t d, uint32_t dp, hipStream_t s,
-                   uint32_t ishift) {
+                   float *out_dist, const float *Xq, const uint32_t *qpos_of, const float *X,
+                   const uint32_t *pos_of, const uint16_t *inv_perm, uint32_t d, uint32_t dp,
+                   hipStream_t s, uint32_t ishift) {
   if (!count) return;
   const uint32_t grid = (uint32_t)((count + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_unpack, dim3(grid), dim3(kBlock), 0, s, keys, count, out_i, out_j,
-                     out_dist, X, pos_of, inv_perm, d, dp, ishift);
+                     out_dist, Xq, qpos_of, X, pos_of, inv_perm, d, dp, ishift);
   SJ_HIP(hipGetLastError());
 }
 

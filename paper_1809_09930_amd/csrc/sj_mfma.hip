@@ -223,14 +223,15 @@ __global__ __launch_bounds__(kBlock) void k_mfma_thresholds(
 #define SJ_RECHECK_INLINE __noinline__
 #endif
 // Canonical predicate on positions (caller's dimension order, FP64, no
-// contraction).
+// contraction): row a of XA (queries) against row b of XB (candidates).
 // ---------------------------------------------------------------------------
-__device__ SJ_RECHECK_INLINE bool canonical_within_m(const float *__restrict__ X, uint32_t a, uint32_t b,
-                                                const uint16_t *__restrict__ inv_perm, uint32_t d,
-                                                uint32_t dp, double eps2) {
+__device__ SJ_RECHECK_INLINE bool canonical_within_m(const float *__restrict__ XA, uint32_t a,
+                                                     const float *__restrict__ XB, uint32_t b,
+                                                     const uint16_t *__restrict__ inv_perm,
+                                                     uint32_t d, uint32_t dp, double eps2) {
 #pragma clang fp contract(off)
-  const float *pa = X + (uint64_t)a * dp;
-  const float *pb = X + (uint64_t)b * dp;
+  const float *pa = XA + (uint64_t)a * dp;
+  const float *pb = XB + (uint64_t)b * dp;
   double acc = 0.0;
   for (uint32_t t = 0; t < d; ++t) {
     const uint32_t r = inv_perm[t];
@@ -363,7 +364,7 @@ __device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const floa
           bs.st.cnt += nb;
         } else {
           if (band)
-            acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+            acc_ok = canonical_within_m(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
           n_recheck += (uint64_t)__builtin_popcountll(bm);
         }
       }
@@ -420,7 +421,7 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
           bs.st.cnt += nb;
         } else {
           if (band)
-            acc_ok = canonical_within_m(v.X, qpos[j], cp, v.inv_perm, v.d, v.dp, v.eps2);
+            acc_ok = canonical_within_m(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
           n_recheck += (uint64_t)__builtin_popcountll(bm);
         }
       }
@@ -789,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck(
       const uint64_t key = v.band[i];
       q = (uint32_t)(key >> 32);
       c = (uint32_t)key;
-      ok = canonical_within_m(v.X, q, c, v.inv_perm, v.d, v.dp, v.eps2);
+      ok = canonical_within_m(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
     }
     const uint64_t am = ballot(ok);
     if (am == 0) continue;
@@ -897,7 +898,7 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck_batched(
       const uint32_t job = (uint32_t)(key >> 40);
       const uint32_t q = (uint32_t)((key >> 20) & kMask), c = (uint32_t)(key & kMask);
       const MfmaView &v = jobs[job].view;
-      ok = canonical_within_m(v.X, q, c, v.inv_perm, v.d, v.dp, v.eps2);
+      ok = canonical_within_m(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
       two = ok && v.symmetric && q != c;
       rkey = ((uint64_t)job << 40) | ((uint64_t)c << 20) | q;
     }
@@ -949,13 +950,15 @@ __global__ __launch_bounds__(kBlock) void k_job_bounds(
   }
 }
 
-// Keys of cell-order positions (p << 32 | q) -> keys of caller indices.
+// Keys of cell-order positions (q << 32 | c) -> keys of caller indices
+// (query positions through qid, candidate positions through orig_id).
 __global__ __launch_bounds__(kBlock) void k_pos_to_id(uint64_t *__restrict__ keys, uint64_t count,
+                                                      const uint32_t *__restrict__ qid,
                                                       const uint32_t *__restrict__ orig_id) {
   const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= count) return;
   const uint64_t k = keys[e];
-  keys[e] = ((uint64_t)orig_id[(uint32_t)(k >> 32)] << 32) | orig_id[(uint32_t)k];
+  keys[e] = ((uint64_t)qid[(uint32_t)(k >> 32)] << 32) | orig_id[(uint32_t)k];
 }
 
 template <int KP, int FMT>
@@ -1035,10 +1038,11 @@ void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, co
   SJ_HIP(hipGetLastError());
 }
 
-void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, hipStream_t s) {
+void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *qid,
+                      const uint32_t *orig_id, hipStream_t s) {
   if (!count) return;
   hipLaunchKernelGGL(k_pos_to_id, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, keys, count, orig_id);
+                     s, keys, count, qid, orig_id);
   SJ_HIP(hipGetLastError());
 }
 

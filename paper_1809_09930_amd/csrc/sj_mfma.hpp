@@ -21,7 +21,8 @@ struct MfmaView {
   const void *XA, *XB;      // [n_pad][kp] 16-bit operands (candidate rows / query columns)
   const float *cn;          // [n_pad] candidate norms, the MFMA's initial accumulator
   const float *thi, *tlo;   // per-point thresholds
-  const float *X;           // FP32 rows (recheck)
+  const float *X;           // FP32 candidate rows (recheck)
+  const float *Xq;          // FP32 query rows (X itself in a self-join)
   const uint16_t *inv_perm;
   const uint2 *runs;
   const uint32_t *qlist;    // query positions, or null for contiguous slots
@@ -79,7 +80,8 @@ void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, co
 void launch_band_recheck(const MfmaView &v, uint64_t *out, uint64_t capacity,
                          unsigned long long *cursor, unsigned long long *rechecks, hipStream_t s);
 void launch_join_mfma(const MfmaLaunch &a, hipStream_t s);
-void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *orig_id, hipStream_t s);
+void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *qid,
+                      const uint32_t *orig_id, hipStream_t s);
 
 // Batched path: variant index of (kp, fmt), or -1 when kp is not supported
 // (kp <= 80); workgroups per CU the persistent kernel fits.

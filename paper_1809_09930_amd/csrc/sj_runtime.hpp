@@ -198,6 +198,18 @@ struct sj_index {
   std::vector<double> dmin, dmax;
   float lo32 = 0.0f, hi32 = 0.0f;
 
+  // General join Q join_eps E (Section 3.1): a query handle holds the query
+  // points Q (n = |Q|) in the grid of the indexed set `entries` (E, which
+  // must outlive it); its X / orig_id / pos_of / cells / norm tables / 16-bit
+  // query operands describe Q, and the candidates are E's.  Null in a
+  // self-join (the handle is its own entries).
+  const sj_index *entries = nullptr;
+  uint64_t n_near = 0;    // points in cells (a query handle drops far queries)
+  sj::Geometry geom{};    // grid of the build (k, key and neighbour parameters)
+  std::vector<float> mfma_centre;  // matrix-core centring of the indexed set
+  sj::MfmaBand mfma_band{};        // and its error-band constants
+  DevBuf mfma_max;                 // its maxima (k_mfma_maxima) on the device
+
   // index
   DevBuf X, orig_id, pos_of, perm_d, inv_perm_d;
   DevBuf cell_key, cell_start;
@@ -249,6 +261,11 @@ void fill_defaults(sj_options *o);
 sj_options checked_options(const float *points, uint64_t n, uint32_t d, double epsilon,
                            const sj_options *opts);
 void build(sj_index &ix, const float *points, hipStream_t s);
+// Builds the query handle q (opt, n set) of the points `queries` against
+// the indexed set E (see sj_index::entries).
+void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream_t s);
+// The indexed (candidate) side of a handle: its entries, or itself.
+inline const sj_index &entries_of(const sj_index &ix) { return ix.entries ? *ix.entries : ix; }
 uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms);
 uint64_t default_budget();
 MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist, int sym);

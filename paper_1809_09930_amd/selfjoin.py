@@ -31,7 +31,8 @@ SJ_FP32_DIFFERENCE = 1
 SJ_FP32_NORM = 2
 FP32_FORMS = {"auto": SJ_FP32_AUTO, "difference": SJ_FP32_DIFFERENCE, "norm": SJ_FP32_NORM}
 
-EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_run",
+EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_build_query",
+            "selfjoin_run",
             "selfjoin_fetch_pairs", "selfjoin_fetch_offsets", "selfjoin_get_info",
             "selfjoin_get_perm",
             "selfjoin_free", "selfjoin_last_error", "selfjoin_run_batched",
@@ -131,6 +132,8 @@ def load_library(path: str = LIB_PATH):
     lib.selfjoin_build_index.argtypes = [vp, u64, u32, dbl, ctypes.POINTER(SjOptions), vp,
                                          ctypes.POINTER(vp)]
     lib.selfjoin_build_index.restype = ctypes.c_int
+    lib.selfjoin_build_query.argtypes = [vp, vp, u64, vp, ctypes.POINTER(vp)]
+    lib.selfjoin_build_query.restype = ctypes.c_int
     lib.selfjoin_run.argtypes = [vp, vp, ctypes.POINTER(u64)]
     lib.selfjoin_run.restype = ctypes.c_int
     lib.selfjoin_fetch_pairs.argtypes = [vp, u64, u64, vp, vp, vp, ctypes.POINTER(u64), vp]
@@ -207,6 +210,23 @@ def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = Tru
     ptr = points.data_ptr() if points.numel() else None
     _check(lib.selfjoin_build_index(ptr, n, d, float(epsilon), ctypes.byref(o),
                                     _stream_handle(stream), ctypes.byref(h)))
+    return h.value
+
+
+def selfjoin_build_query(entries, queries, stream=None):
+    """Query handle of the general join Q join_eps E: the float32 [m, d]
+    tensor `queries` (CUDA or CPU) against the index `entries` (a handle of
+    selfjoin_build_index, which must outlive the query handle).  Run, fetch
+    and free it like any handle; its pairs are (query row, row of E)."""
+    import torch
+    lib = load_library()
+    if queries.dtype != torch.float32 or queries.dim() != 2:
+        raise ValueError("queries must be a float32 [m, d] tensor")
+    queries = queries.contiguous()
+    h = ctypes.c_void_p()
+    ptr = queries.data_ptr() if queries.numel() else None
+    _check(lib.selfjoin_build_query(entries, ptr, queries.shape[0], _stream_handle(stream),
+                                    ctypes.byref(h)))
     return h.value
 
 
