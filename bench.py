@@ -55,6 +55,10 @@ def parse():
                     help="distance filter of the headline line")
     ap.add_argument("--compare", default="fp16",
                     help="comma list of other precisions timed on the same workload ('' = none)")
+    ap.add_argument("--query-sets", type=int, default=0,
+                    help="instead of the self-join: the general join of N_b entity-partitioned "
+                         "query sets Q_l (every N_b-th point from offset l) against the whole "
+                         "workload, one query handle per set")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a buffer of this many MiB device-to-device 3 times (scales "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -201,6 +205,95 @@ def bench_batched(a, table):
     print(json.dumps(out), flush=True)
 
 
+def bench_query_sets(a, table, P, Pd, targets, eps_list):
+    """The general join Q_l join_eps D for the N_b entity-partitioned query
+    sets of the paper's distributed scheme: one index of D, then one query
+    handle per set (build, join, sort).  Reports the aggregate rate and the
+    spread of the per-set join times (the load balance across sets)."""
+    import torch
+    from paper_1809_09930_amd import selfjoin as sj
+    nb = a.query_sets
+    n, d = P.shape
+    sets = [Pd[l::nb].contiguous() for l in range(nb)]
+    torch.cuda.synchronize()
+
+    def step(record, precision):
+        for t, eps in zip(targets, eps_list):
+            he = sj.selfjoin_build_index(Pd, eps, precision=precision)
+            e_info = sj.selfjoin_get_info(he)
+            e_info["perm"] = sj.selfjoin_get_perm(he, d)
+            rows = []
+            for q in sets:
+                hq = sj.selfjoin_build_query(he, q)
+                total = sj.selfjoin_run(hq)
+                rows.append((total, sj.selfjoin_get_info(hq)))
+                sj.selfjoin_free(hq)
+            sj.selfjoin_free(he)
+            if record is not None:
+                record.append((t, eps, e_info, rows))
+
+    prec = a.precision
+    for _ in range(a.warmup):
+        step(None, prec)
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        step(recs, prec)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cand = sum(i["candidates"] for r in recs for _, i in r[3])
+    pairs = sum(tot for r in recs for tot, _ in r[3])
+    per_eps = {}
+    flops_total = time_total = 0.0
+    join_all = []
+    for t, eps, e_info, rows in recs[:len(targets)]:
+        join = np.array([i["ms_join"] / max(i["join_launches"], 1) for _, i in rows])
+        c_sets = float(sum(i["candidates"] for _, i in rows))
+        if prec == "fp32":  # operations the short-circuit leaves, per candidate (one direction)
+            flops_total += 3.0 * shortc_prefix_mean(P, e_info["perm"], eps * eps) * c_sets
+        else:               # one d-long dot product per candidate
+            flops_total += 2.0 * d * c_sets
+        time_total += float(join.sum()) / 1e3
+        join_all.extend(join.tolist())
+        run = np.array([i["ms_run"] for _, i in rows])
+        build = np.array([i["ms_build"] for _, i in rows])
+        tot = sum(x for x, _ in rows)
+        per_eps[t] = {"eps": eps, "pairs": tot, "sd": (tot - n) / n, "k": e_info["k"],
+                      "candidates": sum(i["candidates"] for _, i in rows),
+                      "ms_index_build": round(e_info["ms_build"], 3),
+                      "ms_query_build_sum": round(float(build.sum()), 3),
+                      "ms_join_per_set": {"min": round(float(join.min()), 3),
+                                          "max": round(float(join.max()), 3),
+                                          "mean": round(float(join.mean()), 3)},
+                      "ms_run_per_set": {"min": round(float(run.min()), 3),
+                                         "max": round(float(run.max()), 3),
+                                         "mean": round(float(run.mean()), 3)},
+                      "max_over_min_join": round(float(join.max() / max(join.min(), 1e-9)), 4)}
+    out = {
+        "metric": "candidate distance evals/s (exact pair set)",
+        "value": cand / elapsed,
+        "unit": "candidate distance evals/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": elapsed * 1e3 / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else prec, "data": "synthetic",
+        "config": {"workload": a.workload, "n": n, "d": d, "query_sets": nb,
+                   "target_mean_neighbours": [int(t) for t in targets],
+                   "path": "general join Q_l join_eps D per query set (one direction, "
+                           "%s filter), index of D built once per epsilon" % prec},
+        "result_pairs_per_s": pairs / elapsed,
+        "per_epsilon": per_eps,
+    }
+    achieved = flops_total / time_total / 1e12 if time_total > 0 else 0.0
+    peak = PEAK_FP32_VALU_TFLOPS if prec == "fp32" else PEAK_MFMA_16BIT_TFLOPS
+    out["roofline"] = {"bound": "alu" if prec == "fp32" else "mfma", "achieved": achieved,
+                       "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                       "kernel": "k_join_fp32" if prec == "fp32" else "k_join_mfma",
+                       "mean_launch_ms": float(np.mean(join_all)) if join_all else 0.0}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -231,6 +324,9 @@ def main():
     n, d = P.shape
     Pd = torch.from_numpy(P).cuda()
     torch.cuda.synchronize()
+    if a.query_sets:
+        bench_query_sets(a, table, P, Pd, targets, eps_list)
+        return
 
     def step(record, precision):
         for t, eps in zip(targets, eps_list):
