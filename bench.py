@@ -279,7 +279,7 @@ def bench_query_sets(a, table, P, Pd, targets, eps_list):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if prec == "fp32" else prec, "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "d": d, "query_sets": nb,
-                   "target_mean_neighbours": [int(t) for t in targets],
+                   "epsilons": eps_list,
                    "path": "general join Q_l join_eps D per query set (one direction, "
                            "%s filter), index of D built once per epsilon" % prec},
         "result_pairs_per_s": pairs / elapsed,
@@ -317,9 +317,14 @@ def main():
         bench_batched(a, table)
         return
     w = datagen.WORKLOADS[a.workload]
-    targets = [t.strip() for t in a.targets.split(",") if t.strip()] or \
-        [str(t) for t in w["targets"]]
-    eps_list = [float.fromhex(table[a.workload]["eps"][t]["hex"]) for t in targets]
+    if "eps_fixed" in w:  # the paper's own epsilons (its synthetic family)
+        targets = [t.strip() for t in a.targets.split(",") if t.strip()] or \
+            [repr(e) for e in w["eps_fixed"]]
+        eps_list = [float(t) for t in targets]
+    else:
+        targets = [t.strip() for t in a.targets.split(",") if t.strip()] or \
+            [str(t) for t in w["targets"]]
+        eps_list = [float.fromhex(table[a.workload]["eps"][t]["hex"]) for t in targets]
     P = datagen.make_workload(a.workload)
     n, d = P.shape
     Pd = torch.from_numpy(P).cuda()
@@ -393,7 +398,9 @@ def main():
         "dtype": "f32" if fp32 else a.precision,
         "data": "synthetic",
         "config": {"workload": a.workload, "n": n, "d": d, "distribution": w["kind"],
-                   "target_mean_neighbours": [int(t) for t in targets],
+                   "target_mean_neighbours": ([int(t) for t in targets]
+                                              if "eps_fixed" not in w else None),
+                   "epsilons": eps_list,
                    "path": ("plain FP32 grid join" if fp32 else
                             "%s matrix-core join with FP64 band recheck" % a.precision)
                    + ", k auto in 4..8, symmetric tiles"},

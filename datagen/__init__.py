@@ -112,6 +112,15 @@ WORKLOADS = {
     "mixture20_515k_d90": dict(kind="mixture_uniform_std", n=515_000, d=90,
                                seed=4, n_centers=20, std_lo=0.01, std_hi=0.3,
                                targets=[50]),
+    # The paper's synthetic family (Section 5.1, Table 1: Syn16D2M, Syn32D2M,
+    # Syn64D2M) at the smallest and largest epsilon of its sweep (Table 3);
+    # these use the paper's epsilons as given instead of calibrated ones.
+    "syn_2m_d16": dict(kind="exponential", n=2_000_000, d=16, seed=21, lam=40.0,
+                       eps_fixed=[0.03, 0.05]),
+    "syn_2m_d32": dict(kind="exponential", n=2_000_000, d=32, seed=37, lam=40.0,
+                       eps_fixed=[0.08, 0.10]),
+    "syn_2m_d64": dict(kind="exponential", n=2_000_000, d=64, seed=69, lam=40.0,
+                       eps_fixed=[0.16, 0.18]),
 }
 
 
@@ -128,6 +137,8 @@ def make_workload(name: str, n: int | None = None) -> np.ndarray:
     if w["kind"] == "mixture_uniform_std":
         std = uniform_std(w["d"], w["std_lo"], w["std_hi"], w["seed"] + 500)
         return gaussian_mixture(nn, w["d"], w["n_centers"], std, w["seed"])
+    if w["kind"] == "exponential":
+        return exponential_syn(nn, w["d"], w["lam"], w["seed"])
     raise KeyError(name)
 
 

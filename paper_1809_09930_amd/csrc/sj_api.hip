@@ -377,12 +377,16 @@ void compute_thresholds(sj_index &ix) {
 // Operands and thresholds of the matrix-core filter (see sj_mfma.hip).
 void mfma_prepare(sj_index &ix, hipStream_t s) {
   const uint32_t d = ix.d;
-  // centre: per-dimension midrange (reordered order, like the rows of X)
+  // centre: the per-dimension sample mean (reordered order, like the rows
+  // of X), clamped into the range.  Any centre gives a valid band; the
+  // band's width grows with the distances of the points from the centre
+  // (typical ones for the query, the largest for the candidates), so on
+  // skewed data the mean beats the midrange
   std::vector<float> centre(d);
   double max_abs = 0.0, n_bound = 0.0;
   for (uint32_t r = 0; r < d; ++r) {
     const uint32_t t = ix.perm[r];
-    centre[r] = (float)((ix.dmin[t] + ix.dmax[t]) * 0.5);
+    centre[r] = (float)std::min(std::max(ix.dmean[t], ix.dmin[t]), ix.dmax[t]);
     const double h = std::max(std::fabs(ix.dmax[t] - (double)centre[r]),
                               std::fabs(ix.dmin[t] - (double)centre[r]));
     max_abs = std::max(max_abs, h);
@@ -529,7 +533,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   }
   // a1/a2: min/max, finiteness, sample variance
   TmpBuf stats;
-  stats.alloc(d * 16 + 256);
+  stats.alloc(d * 32 + 256);
   uint32_t *gmin = stats.as<uint32_t>();
   uint32_t *gmax = gmin + d;
   uint32_t *bad = gmax + d;
@@ -540,13 +544,14 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   launch_variance(P, d, stride, m, var, s);
   std::vector<uint32_t> hmin(d), hmax(d);
   uint32_t hbad = 0;
-  std::vector<double> hvar(d);
+  std::vector<double> hvar(2 * (size_t)d);  // variances, then means
   SJ_HIP(hipMemcpyAsync(hmin.data(), gmin, d * 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipMemcpyAsync(hmax.data(), gmax, d * 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s));
-  SJ_HIP(hipMemcpyAsync(hvar.data(), var, d * 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipMemcpyAsync(hvar.data(), var, d * 16, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
   if (hbad) fail(SJ_ERR_INVALID_ARG, "points contain NaN or Inf coordinates");
+  ix.dmean.assign(hvar.begin() + d, hvar.end());
   for (uint32_t t = 0; t < d; ++t) {
     ix.dmin[t] = (double)ordered_to_float(hmin[t]);
     ix.dmax[t] = (double)ordered_to_float(hmax[t]);
@@ -1164,7 +1169,7 @@ void run(sj_index &ix, hipStream_t s) {
     const uint64_t fit = budget / 20;
     uint64_t per_batch = ix.opt.batch_pairs ? ix.opt.batch_pairs : fit;
     per_batch = std::min(per_batch, fit);
-    per_batch = std::min<uint64_t>(per_batch, 0xF0000000ull);
+    per_batch = std::min<uint64_t>(per_batch, 1ull << 36);  // 512 GiB of keys: beyond HBM
     const uint32_t min_b = ix.opt.min_batches;
     if (est + est / 8 <= per_batch && min_b <= 1)
       run_single(ix, est, s);

@@ -107,7 +107,10 @@ __global__ __launch_bounds__(kBlock) void k_variance(const float *__restrict__ P
     q += x * x;
   }
   const double ss = block_sum_f64(q);
-  if (threadIdx.x == 0) var[t] = m > 1 ? ss / (double)(m - 1) : 0.0;
+  if (threadIdx.x == 0) {
+    var[t] = m > 1 ? ss / (double)(m - 1) : 0.0;
+    var[d + t] = mean;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -190,15 +193,18 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float *__restrict__ P, 
                                                    float *__restrict__ X,
                                                    uint32_t *__restrict__ orig_id,
                                                    uint32_t *__restrict__ pos_of) {
-  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= n * dp) return;
-  const uint64_t p = e / dp;
-  const uint32_t r = (uint32_t)(e - p * dp);
-  const uint32_t id = sorted_ids[p];
-  X[e] = r < d ? P[(uint64_t)id * d + perm[r]] : 0.0f;
-  if (r == 0) {
-    orig_id[p] = id;
-    pos_of[id] = (uint32_t)p;
+  // grid-stride: n * dp elements may exceed the 2^32 work-items of a dispatch
+  const uint64_t total = n * dp;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t p = e / dp;
+    const uint32_t r = (uint32_t)(e - p * dp);
+    const uint32_t id = sorted_ids[p];
+    X[e] = r < d ? P[(uint64_t)id * d + perm[r]] : 0.0f;
+    if (r == 0) {
+      orig_id[p] = id;
+      pos_of[id] = (uint32_t)p;
+    }
   }
 }
 
@@ -487,26 +493,38 @@ __global__ void k_cell_products(uint64_t ncell, const uint32_t *__restrict__ cel
 }
 
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+// Workgroups of a grid-stride launch over n elements: one element per
+// thread up to 2^20 workgroups (a dispatch holds at most 2^32 work-items).
+inline uint32_t stride_blocks(uint64_t n) {
+  return (uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1u << 20);
+}
 
 // Pairs per row of sorted keys (row = key >> 32): counts[i] += the number
 // of keys of row i.  Each wave adds one count per row it holds: the lane
 // that starts a run of equal rows inside the wave adds the run's length.
+// Grid-stride over 64-key segments, one per wave and step (count may exceed
+// the 2^32 work-items of one dispatch).
 __global__ __launch_bounds__(kBlock) void k_row_counts(const uint64_t *__restrict__ keys,
                                                        uint64_t count,
                                                        unsigned long long *__restrict__ counts) {
-  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const uint32_t l = lane_id();
-  const bool live = e < count;
-  const uint64_t row = live ? keys[e] >> 32 : 0;
-  const bool head = live && (l == 0 || (keys[e - 1] >> 32) != row);
-  const uint64_t heads = ballot(head);
-  const uint64_t lives = ballot(live);
-  if (!head) return;
-  // the run ends at the next head above this lane, or at the last live lane
-  const uint64_t above = heads & ~((2ull << l) - 1ull);
-  const uint32_t end = above ? (uint32_t)__builtin_ctzll(above)
-                             : (uint32_t)(64 - __builtin_clzll(lives));
-  atomicAdd(&counts[row], (unsigned long long)(end - l));
+  const uint64_t step = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t e0 = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~(uint32_t)(kWave - 1));
+       e0 < count; e0 += step) {
+    const uint64_t e = e0 + l;
+    const bool live = e < count;
+    const uint64_t row = live ? keys[e] >> 32 : 0;
+    const bool head = live && (l == 0 || (keys[e - 1] >> 32) != row);
+    const uint64_t heads = ballot(head);
+    const uint64_t lives = ballot(live);
+    if (head) {
+      // the run ends at the next head above this lane, or at the last live lane
+      const uint64_t above = heads & ~((2ull << l) - 1ull);
+      const uint32_t end = above ? (uint32_t)__builtin_ctzll(above)
+                                 : (uint32_t)(64 - __builtin_clzll(lives));
+      atomicAdd(&counts[row], (unsigned long long)(end - l));
+    }
+  }
 }
 
 }  // namespace
@@ -551,7 +569,7 @@ void launch_gather(const float *P, uint64_t n, uint32_t d, uint32_t dp, const ui
                    const uint32_t *sorted_ids, float *X, uint32_t *orig_id, uint32_t *pos_of,
                    hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n * dp)), dim3(kBlock), 0, s, P, n, d, dp, perm,
+  hipLaunchKernelGGL(k_gather, dim3(stride_blocks(n * dp)), dim3(kBlock), 0, s, P, n, d, dp, perm,
                      sorted_ids, X, orig_id, pos_of);
   SJ_HIP(hipGetLastError());
 }
@@ -640,7 +658,7 @@ void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint
 void launch_row_counts(const uint64_t *keys, uint64_t count, unsigned long long *counts,
                        hipStream_t s) {
   if (!count) return;
-  hipLaunchKernelGGL(k_row_counts, dim3(blocks_for(count)), dim3(kBlock), 0, s, keys, count,
+  hipLaunchKernelGGL(k_row_counts, dim3(stride_blocks(count)), dim3(kBlock), 0, s, keys, count,
                      counts);
   SJ_HIP(hipGetLastError());
 }

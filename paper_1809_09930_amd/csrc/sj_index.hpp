@@ -40,6 +40,8 @@ struct NbrParams {
 
 void launch_minmax(const float *P, uint64_t n, uint32_t d, uint32_t *gmin, uint32_t *gmax,
                    uint32_t *bad, hipStream_t s);
+// var[t] = sample variance, var[d + t] = sample mean of dimension t over the
+// rows 0, stride, 2 stride, ... (m rows).
 void launch_variance(const float *P, uint32_t d, uint64_t stride, uint64_t m, double *var,
                      hipStream_t s);
 void launch_cellkey(const float *P, uint64_t n, uint32_t d, const KeyParams &kp, uint64_t *keys,

@@ -955,10 +955,12 @@ __global__ __launch_bounds__(kBlock) void k_job_bounds(
 __global__ __launch_bounds__(kBlock) void k_pos_to_id(uint64_t *__restrict__ keys, uint64_t count,
                                                       const uint32_t *__restrict__ qid,
                                                       const uint32_t *__restrict__ orig_id) {
-  const uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= count) return;
-  const uint64_t k = keys[e];
-  keys[e] = ((uint64_t)qid[(uint32_t)(k >> 32)] << 32) | orig_id[(uint32_t)k];
+  // grid-stride: count may exceed the 2^32 work-items of one dispatch
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < count;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t k = keys[e];
+    keys[e] = ((uint64_t)qid[(uint32_t)(k >> 32)] << 32) | orig_id[(uint32_t)k];
+  }
 }
 
 template <int KP, int FMT>
@@ -1041,8 +1043,8 @@ void launch_mfma_thresholds(uint64_t n, uint64_t n_pad, const MfmaBand &band, co
 void launch_pos_to_id(uint64_t *keys, uint64_t count, const uint32_t *qid,
                       const uint32_t *orig_id, hipStream_t s) {
   if (!count) return;
-  hipLaunchKernelGGL(k_pos_to_id, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, keys, count, qid, orig_id);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((count + kBlock - 1) / kBlock, 1u << 20);
+  hipLaunchKernelGGL(k_pos_to_id, dim3(grid), dim3(kBlock), 0, s, keys, count, qid, orig_id);
   SJ_HIP(hipGetLastError());
 }
 

@@ -148,7 +148,7 @@ __device__ __forceinline__ uint64_t live_count(uint64_t n, const unsigned long l
 
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys,
                                                     uint64_t n_cap, int shift,
-                                                    uint32_t *__restrict__ hist,
+                                                    uint64_t *__restrict__ hist,
                                                     uint32_t nblocks,
                                                     const unsigned long long *__restrict__ d_count) {
   __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
     uint32_t t = 0;
 #pragma unroll
     for (int i = 0; i < kWavesPerBlock; ++i) t += cnt[i][dg];
-    hist[(uint64_t)dg * nblocks + blockIdx.x] = t;
+    hist[(uint64_t)dg * nblocks + blockIdx.x] = t;  // 64-bit: offsets may pass 2^32
   }
 }
 
@@ -179,12 +179,12 @@ template <bool kVals>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n_cap, int shift,
-    const uint32_t *__restrict__ offs, uint32_t nblocks,
+    const uint64_t *__restrict__ offs, uint32_t nblocks,
     const unsigned long long *__restrict__ d_count) {
   __shared__ uint32_t cnt[kWavesPerBlock][kRadixBins];
   __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];
   __shared__ uint32_t dbase[kRadixBins];   // first slot of each digit in the tile
-  __shared__ uint32_t gbase[kRadixBins];   // first global slot of each digit
+  __shared__ uint64_t gbase[kRadixBins];   // first global slot of each digit
   __shared__ uint64_t tkey[kRsTile];
   __shared__ uint32_t tval[kVals ? kRsTile : 1];
   const int w = threadIdx.x / kWave;
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   for (uint32_t i = threadIdx.x; i < valid_keys; i += kBlock) {
     const uint64_t k = tkey[i];
     const uint32_t dg = (uint32_t)(k >> shift) & (kRadixBins - 1);
-    const uint64_t pos = (uint64_t)gbase[dg] + (i - dbase[dg]);
+    const uint64_t pos = gbase[dg] + (i - dbase[dg]);
     kout[pos] = k;
     if (kVals) vout[pos] = tval[i];
   }
@@ -328,7 +328,7 @@ void exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, uint64_t 
 size_t radix_tmp_bytes(uint64_t n) {
   const uint64_t nb = (n + kRsTile - 1) / kRsTile;
   const uint64_t hist = (uint64_t)kRadixBins * (nb ? nb : 1);
-  return ((hist * 4 + 255) / 256) * 256 + scan_levels_bytes<uint32_t>(hist);
+  return ((hist * 8 + 255) / 256) * 256 + scan_levels_bytes<uint64_t>(hist);
 }
 
 void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v, hipStream_t s) {
@@ -341,18 +341,18 @@ void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v
 void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int *shifts,
                     int n_passes, void *tmp, hipStream_t s, const unsigned long long *d_count) {
   if (n == 0 || (n == 1 && !d_count) || n_passes == 0) return;
-  if (n > 0xffffffffull) fail(SJ_ERR_INVALID_ARG, "radix sort of more than 2^32-1 keys");
+  if ((n + kRsTile - 1) / kRsTile > 0x7fffffffull) fail(SJ_ERR_INVALID_ARG, "radix sort too large");
   const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
   const uint64_t nhist = (uint64_t)kRadixBins * nb;
-  uint32_t *hist = static_cast<uint32_t *>(tmp);
-  char *scan_tmp = static_cast<char *>(tmp) + ((nhist * 4 + 255) / 256) * 256;
+  uint64_t *hist = static_cast<uint64_t *>(tmp);
+  char *scan_tmp = static_cast<char *>(tmp) + ((nhist * 8 + 255) / 256) * 256;
   int cur = 0;
   for (int p = 0; p < n_passes; ++p) {
     const int sh = shifts[p];
     hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kBlock), 0, s, keys[cur], n, sh, hist, nb,
                        d_count);
     SJ_HIP(hipGetLastError());
-    exclusive_scan_u32(hist, hist, nhist, nullptr, scan_tmp, s);
+    exclusive_scan_u64(hist, hist, nhist, nullptr, scan_tmp, s);
     if (vals) {
       hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
                          vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, sh, hist, nb, d_count);

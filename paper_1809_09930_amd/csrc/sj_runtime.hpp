@@ -195,7 +195,7 @@ struct sj_index {
   sj_options opt{};
   std::vector<uint32_t> perm;
   std::vector<uint16_t> inv_perm;
-  std::vector<double> dmin, dmax;
+  std::vector<double> dmin, dmax, dmean;  // per caller dimension; dmean from the variance sample
   float lo32 = 0.0f, hi32 = 0.0f;
 
   // General join Q join_eps E (Section 3.1): a query handle holds the query

@@ -431,3 +431,49 @@ def test_csr_neighbour_table(opts):
     assert np.array_equal(off_d.cpu().numpy(), want)
     assert np.array_equal(off_h.numpy(), want)
     assert np.array_equal(nb.cpu().numpy().view(np.uint32), oj)
+
+
+# --------------------------------------------------------------------------
+# The paper's synthetic family (exponential, rate 40, in [0, 1); Section 5.1)
+# at the paper's own epsilons.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("n,d,eps", [(20000, 16, 0.05), (12000, 32, 0.10), (6000, 64, 0.18)])
+def test_exponential_family_full_result(prec, n, d, eps):
+    P = datagen.exponential_syn(n, d, 40.0, 100 + d)
+    print("case syn", n, d, eps, prec, flush=True)
+    assert_same_as_oracle(P, eps, precision=prec)
+
+
+@pytest.mark.parametrize("workload,eps,prec", [
+    ("syn_2m_d16", 0.05, "fp32"), ("syn_2m_d16", 0.05, "fp16"),
+    ("syn_2m_d32", 0.08, "bf16"), ("syn_2m_d64", 0.16, "fp16"),
+    ("syn_2m_d64", 0.18, "fp16")])  # 4.7e9 pairs: more than 2^32 keys in one sorted batch
+def test_exponential_family_full_size_sampled_rows(workload, eps, prec):
+    """Syn16/32/64D2M-shaped inputs at the paper's epsilons: sampled full
+    rows against the oracle, sorted order and the self pairs."""
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.make_workload(workload)
+    n = len(P)
+    print("case", workload, eps, prec, flush=True)
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps, precision=prec)
+    try:
+        total = sj.selfjoin_run(h)
+        oi = torch.empty(total, dtype=torch.int32, device="cuda")
+        oj = torch.empty(total, dtype=torch.int32, device="cuda")
+        sj.selfjoin_fetch_pairs(h, 0, oi, oj, None, max_pairs=total)
+    finally:
+        sj.selfjoin_free(h)
+    assert bool((oi[1:] >= oi[:-1]).all())
+    assert int((oi == oj).sum()) == n
+    rng = np.random.default_rng(13)
+    rows = np.sort(rng.choice(n, size=24, replace=False))
+    cnt, js = oracle.rows(P, eps, rows)
+    starts = torch.searchsorted(oi, torch.from_numpy(rows.astype(np.int32)).cuda()).tolist()
+    off = 0
+    for r, c, st in zip(rows, cnt, starts):
+        got = oj[st:st + int(c)].cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, js[off:off + c]), r
+        if st + int(c) < total:
+            assert int(oi[st + int(c)]) != r
+        off += int(c)
