@@ -59,6 +59,9 @@ def parse():
                     help="instead of the self-join: the general join of N_b entity-partitioned "
                          "query sets Q_l (every N_b-th point from offset l) against the whole "
                          "workload, one query handle per set")
+    ap.add_argument("--k-sweep", default="",
+                    help="comma list of explicit k: index and join the largest epsilon of the "
+                         "workload at each k and report the index-search and distance work")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only copy a buffer of this many MiB device-to-device 3 times (scales "
                          "the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -294,6 +297,39 @@ def bench_query_sets(a, table, P, Pd, targets, eps_list):
     print(json.dumps(out), flush=True)
 
 
+def bench_k_sweep(a, P, Pd, eps):
+    """Section 5.5 (Figure 8): index-search work against distance work as k
+    grows, at one epsilon.  Per k: non-empty cells #G, adjacent-cell lookups
+    (#G * 3^k here, one search per cell; |D| * 3^k in the paper's
+    one-thread-per-point kernel), ordered candidates C and the coordinates a
+    join without short-circuit would load (C * d), with the build and join
+    times of the library."""
+    import torch
+    from paper_1809_09930_amd import selfjoin as sj
+    n, d = P.shape
+    rows = {}
+    for k in [int(x) for x in a.k_sweep.split(",") if x.strip()]:
+        for rep_ in range(a.warmup + 1):
+            h = sj.selfjoin_build_index(Pd, eps, k=k, precision=a.precision)
+            total = sj.selfjoin_run(h)
+            info = sj.selfjoin_get_info(h)
+            sj.selfjoin_free(h)
+        torch.cuda.synchronize()
+        rows[str(k)] = {"k": info["k"], "cells": info["n_cells"],
+                        "lookups_per_cell_search": info["n_cells"] * 3 ** info["k"],
+                        "lookups_per_point_search": n * 3 ** info["k"],
+                        "candidates": info["candidates"],
+                        "distance_coordinate_loads": info["candidates"] * d,
+                        "pairs": total, "rechecks": info["rechecks"],
+                        "batches": info["batches"], "join_launches": info["join_launches"],
+                        "ms_build": round(info["ms_build"], 3),
+                        "ms_join": round(info["ms_join"] / max(info["join_launches"], 1), 3),
+                        "ms_sort": round(info["ms_sort"], 3), "ms_run": round(info["ms_run"], 3)}
+    out = {"metric": "index-search vs distance work per k", "workload": a.workload,
+           "eps": eps, "precision": a.precision, "n": n, "d": d, "per_k": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -332,6 +368,9 @@ def main():
     if a.query_sets:
         bench_query_sets(a, table, P, Pd, targets, eps_list)
         return
+    if a.k_sweep:
+        bench_k_sweep(a, P, Pd, eps_list[-1])
+        return
 
     def step(record, precision):
         for t, eps in zip(targets, eps_list):
@@ -362,7 +401,8 @@ def main():
                    "cells": info["n_cells"], "candidates": info["candidates"],
                    "evaluated": info["evaluated"], "rechecks": info["rechecks"],
                    "ms_build": round(info["ms_build"], 3), "ms_join": round(ms, 3),
-                   "ms_sort": round(info["ms_sort"], 3), "ms_run": round(info["ms_run"], 3)}
+                   "ms_sort": round(info["ms_sort"], 3), "ms_run": round(info["ms_run"], 3),
+                   "batches": info["batches"], "join_launches": info["join_launches"]}
             if with_prefix:
                 pbar = shortc_prefix_mean(P, perm, eps * eps)
                 row["shortc_prefix_mean"] = round(pbar, 3)

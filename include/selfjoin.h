@@ -165,7 +165,7 @@ typedef struct sj_info {
     float    ms_join;         /* device time of the distance kernels of the last run */
     float    ms_sort;         /* device time of result sorting of the last run */
     float    ms_run;          /* device time of the whole last run */
-    uint32_t join_launches;   /* launches of the distance kernel in the last run */
+    uint32_t join_launches;   /* launches of the distance kernel in the last run (reruns after an undersized buffer included) */
     uint32_t fp32_form;       /* form of the FP32 filter (enum sj_fp32_form; 0 on the matrix-core path) */
 } sj_info;
 

@@ -932,6 +932,7 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
         m.view.band_cap = ix.band_cap;
         m.view.band_cursor = band_cursor;
         launch_join_mfma(m, s);
+        ix.info.join_launches++;
         launch_band_recheck(m.view, out, cap, a.cursor, a.rechecks, s);
         const uint64_t nb = read_counter(ix, 2, s);
         if (nb <= ix.band_cap) break;
@@ -943,6 +944,7 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     }
   } else {
     launch_join_fp32(a, s);
+    if (!count_only) ix.info.join_launches++;
   }
   SJ_HIP(hipEventRecord(e1.e, s));
   SJ_HIP(hipEventSynchronize(e1.e));
@@ -1021,7 +1023,6 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
     const bool self = !ix.entries;  // a self-join's units are symmetric
     join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, self ? ix.runs_sym : ix.runs_full,
                 nullptr, self ? 1 : 0, 0, ix.pairs.as<uint64_t>(), cap, s, &ms_join);
-    ix.info.join_launches++;
     const uint64_t got = read_counter(ix, 0, s);
     if (got <= cap) {
       ix.total = got;
@@ -1111,7 +1112,6 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
         SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
         join_launch(ix, wu, nwu, ix.runs_full, p32.as<uint32_t>(), 0, 0, sl.keys.as<uint64_t>(),
                     cap, s, &ms_join);
-        ix.info.join_launches++;
         got = read_counter(ix, 0, s);
         if (got <= cap) break;
         cap = got;
