@@ -12,6 +12,7 @@ Accelerated Similarity Self-Join for Multi-Dimensional Data", it follows):
 * ``grid_join``       O2: grid-index join over k indexed dimensions (C).
 * ``cell_coords``     grid cell coordinates (C; Figure 1/2 pins).
 * ``grid_candidates`` the points one query's grid search visits (C).
+* ``sortidu_candidates`` the same with SORTIDU's search along u (C).
 * ``rows_smallest``   K smallest distances per row (C; eps calibration).
 * ``bruteforce_np``   O1': numpy twin of O1 (same rounding sequence).
 * ``exact_int_join``  O0: exact integer join for data on a 2^-g grid.
@@ -73,6 +74,9 @@ def _load():
     lib.oracle_grid_candidates.argtypes = [P, u64, u32, f64, u32, P,
                                            ctypes.c_int, f64, u64, P, u64]
     lib.oracle_grid_candidates.restype = i64
+    lib.oracle_sortidu_candidates.argtypes = [P, u64, u32, f64, u32, P, ctypes.c_int, f64,
+                                              u32, u64, P, u64]
+    lib.oracle_sortidu_candidates.restype = i64
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -225,6 +229,28 @@ def grid_candidates(P, eps: float, dims, query: int,
     lib.oracle_grid_candidates(_ptr(P), n, d, float(eps), len(dims),
                                _ptr(dims), int(origin_zero), float(width_factor),
                                int(query), _ptr(out), len(out))
+    return out
+
+
+def sortidu_candidates(P, eps: float, dims, u: int, query: int,
+                       origin_zero: bool = False,
+                       width_factor: float = 1.0 + 2.0 ** -20):
+    """SORTIDU (Section 4.3): candidate ids one query visits when every cell
+    is sorted by the un-indexed dimension u -- a binary search to the first
+    point within eps along u, then a scan until one is farther.  Cells in the
+    order of the 3^k offsets, points in increasing u inside each."""
+    P = _points(P)
+    n, d = P.shape
+    dims = np.ascontiguousarray(dims, dtype=np.uint32)
+    lib = _load()
+    args = (_ptr(P), n, d, float(eps), len(dims), _ptr(dims), int(origin_zero),
+            float(width_factor), int(u), int(query))
+    cnt = lib.oracle_sortidu_candidates(*args, None, 0)
+    if cnt < 0:
+        raise ValueError("oracle_sortidu_candidates failed (%d)" % cnt)
+    out = np.empty(cnt, dtype=np.uint32)
+    got = lib.oracle_sortidu_candidates(*args, _ptr(out), len(out))
+    assert got == cnt
     return out
 
 

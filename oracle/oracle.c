@@ -442,3 +442,78 @@ int64_t oracle_grid_candidates(const float *P, uint64_t n, uint32_t d,
     free(coord);
     return (int64_t)w;
 }
+
+/* ---------------------------------------------------------------------------
+ * SORTIDU (Section 4.3): the candidates one query visits when the points of
+ * every cell are sorted by an un-indexed dimension u.  For each adjacent
+ * cell (Algorithm 1's 3^k box, as in oracle_grid_candidates): the cell's
+ * points are sorted by increasing u (ties by id); a binary search finds the
+ * first point r whose u is within eps of the query's, |p(u) - r(u)| <= eps,
+ * and the scan runs from r until the first point s with |p(u) - s(u)| > eps.
+ * Differences are taken in binary64.  Output: cells in offset order, points
+ * in increasing u inside each cell.  Returns the count (-1 when cap is too
+ * small, counts still exact; -2 no memory; -3 bad arguments).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const float *P;
+    uint32_t d, u;
+} u_ctx;
+static u_ctx g_uctx; /* qsort comparator context, single-threaded use */
+
+static int cmp_by_u(const void *pa, const void *pb)
+{
+    const uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    const float ua = g_uctx.P[(uint64_t)a * g_uctx.d + g_uctx.u];
+    const float ub = g_uctx.P[(uint64_t)b * g_uctx.d + g_uctx.u];
+    if (ua < ub) return -1;
+    if (ua > ub) return 1;
+    return (a > b) - (a < b);
+}
+
+int64_t oracle_sortidu_candidates(const float *P, uint64_t n, uint32_t d,
+                                  double eps, uint32_t k, const uint32_t *dims,
+                                  int origin_zero, double width_factor,
+                                  uint32_t u, uint64_t query, uint32_t *out_j,
+                                  uint64_t cap)
+{
+    if (k == 0 || k > 20 || query >= n || u >= d) return -3;
+    int64_t *coord = (int64_t *)malloc(n * k * sizeof(int64_t));
+    uint32_t *cell = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!coord || !cell) { free(coord); free(cell); return -2; }
+    oracle_cell_coords(P, n, d, eps, k, dims, origin_zero, width_factor, coord);
+    const int64_t *cq = coord + query * k;
+    const double pu = (double)P[query * d + u];
+    uint64_t n_off = 1, w = 0;
+    for (uint32_t r = 0; r < k; ++r) n_off *= 3;
+    g_uctx.P = P;
+    g_uctx.d = d;
+    g_uctx.u = u;
+    for (uint64_t o = 0; o < n_off; ++o) {
+        int64_t nb[20];
+        uint64_t rem = o;
+        for (uint32_t r = 0; r < k; ++r) { nb[r] = cq[r] + (int64_t)(rem % 3) - 1; rem /= 3; }
+        /* the cell's points, sorted by u */
+        uint64_t m = 0;
+        for (uint64_t j = 0; j < n; ++j)
+            if (cmp_coord(coord + j * k, nb, k) == 0) cell[m++] = (uint32_t)j;
+        qsort(cell, m, sizeof(uint32_t), cmp_by_u);
+        /* r: first point with u >= p(u) - eps, i.e. the smallest u within eps */
+        uint64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            const double cu = (double)P[(uint64_t)cell[mid] * d + u];
+            if (pu - cu > eps) lo = mid + 1; else hi = mid;
+        }
+        /* scan from r until s, the first point farther than eps along u */
+        for (uint64_t i = lo; i < m; ++i) {
+            const double cu = (double)P[(uint64_t)cell[i] * d + u];
+            if (fabs(pu - cu) > eps) break;
+            if (w < cap) out_j[w] = cell[i];
+            ++w;
+        }
+    }
+    free(coord);
+    free(cell);
+    if (out_j && w > cap) return -1;
+    return (int64_t)w;
+}

@@ -419,3 +419,51 @@ def test_join_empty_sides():
     for Q, EE in ((z, E), (E, z), (z, z)):
         qi, ej = oracle.join(Q, EE, 0.3)
         assert len(qi) == 0 and len(ej) == 0
+
+
+# --------------------------------------------------------------------------
+# SORTIDU (Section 4.3): search along one un-indexed dimension u
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d,k,u,seed", [(600, 6, 2, 3, 61), (800, 4, 1, 2, 62),
+                                          (500, 8, 3, 0, 63)])
+def test_sortidu_candidates_are_the_cells_points_within_eps_along_u(n, d, k, u, seed):
+    """The binary search plus scan visits exactly the points of the adjacent
+    cells whose u-coordinate is within eps of the query's (the definition,
+    written here as a plain filter), each cell's in increasing u; and that
+    set holds every neighbour of the query."""
+    P = datagen.uniform_grid(n, d, seed)
+    eps = oracle.calibrate_eps(P, 12, np.arange(0, n, 4))[0]
+    dims = [r for r in range(d) if r != u][:k] if u < k else list(range(k))
+    coords = oracle.cell_coords(P, eps, dims)
+    for q in range(0, n, 37):
+        grid = oracle.grid_candidates(P, eps, dims, q)
+        want = {int(j) for j in grid
+                if abs(float(P[j, u]) - float(P[q, u])) <= eps}
+        got = oracle.sortidu_candidates(P, eps, dims, u, q)
+        assert len(got) == len(set(got.tolist())) and set(got.tolist()) == want
+        # grouped by cell, increasing u inside each cell
+        keys = [tuple(coords[j]) for j in got]
+        for a in range(1, len(got)):
+            if keys[a] == keys[a - 1]:
+                assert P[got[a], u] >= P[got[a - 1], u]
+        _, js = oracle.rows(P, eps, [q])
+        assert set(js.tolist()) <= want
+
+
+def test_sortidu_prunes_when_u_spans_many_eps():
+    """Points spread far along the un-indexed dimension: the search along u
+    visits a small fraction of the cells' points (the case Section 4.3 is
+    for), and nothing when the query is isolated along u."""
+    rng = np.random.default_rng(64)
+    P = np.empty((2000, 3), np.float32)
+    P[:, 0] = rng.random(2000) * 0.2        # indexed: one or two cells
+    P[:, 1] = rng.random(2000) * 0.2
+    P[:, 2] = rng.random(2000) * 50.0       # u: 500 eps long
+    eps = 0.1
+    tot_grid = tot_u = 0
+    for q in range(0, 2000, 50):
+        tot_grid += len(oracle.grid_candidates(P, eps, [0, 1], q))
+        tot_u += len(oracle.sortidu_candidates(P, eps, [0, 1], 2, q))
+    assert tot_u * 50 < tot_grid
+    P[0, 2] = 1000.0
+    assert len(oracle.sortidu_candidates(P, eps, [0, 1], 2, 0)) == 1  # itself
