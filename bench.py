@@ -59,6 +59,8 @@ def parse():
                     help="instead of the self-join: the general join of N_b entity-partitioned "
                          "query sets Q_l (every N_b-th point from offset l) against the whole "
                          "workload, one query handle per set")
+    ap.add_argument("--sortidu", action="store_true",
+                    help="build every index with SORTIDU (search along one un-indexed dimension)")
     ap.add_argument("--k-sweep", default="",
                     help="comma list of explicit k: index and join the largest epsilon of the "
                          "workload at each k and report the index-search and distance work")
@@ -222,7 +224,7 @@ def bench_query_sets(a, table, P, Pd, targets, eps_list):
 
     def step(record, precision):
         for t, eps in zip(targets, eps_list):
-            he = sj.selfjoin_build_index(Pd, eps, precision=precision)
+            he = sj.selfjoin_build_index(Pd, eps, precision=precision, sortidu=a.sortidu)
             e_info = sj.selfjoin_get_info(he)
             e_info["perm"] = sj.selfjoin_get_perm(he, d)
             rows = []
@@ -310,7 +312,7 @@ def bench_k_sweep(a, P, Pd, eps):
     rows = {}
     for k in [int(x) for x in a.k_sweep.split(",") if x.strip()]:
         for rep_ in range(a.warmup + 1):
-            h = sj.selfjoin_build_index(Pd, eps, k=k, precision=a.precision)
+            h = sj.selfjoin_build_index(Pd, eps, k=k, precision=a.precision, sortidu=a.sortidu)
             total = sj.selfjoin_run(h)
             info = sj.selfjoin_get_info(h)
             sj.selfjoin_free(h)
@@ -374,7 +376,7 @@ def main():
 
     def step(record, precision):
         for t, eps in zip(targets, eps_list):
-            h = sj.selfjoin_build_index(Pd, eps, precision=precision)
+            h = sj.selfjoin_build_index(Pd, eps, precision=precision, sortidu=a.sortidu)
             total = sj.selfjoin_run(h)
             info = sj.selfjoin_get_info(h)
             perm = sj.selfjoin_get_perm(h, d)
@@ -443,7 +445,7 @@ def main():
                    "epsilons": eps_list,
                    "path": ("plain FP32 grid join" if fp32 else
                             "%s matrix-core join with FP64 band recheck" % a.precision)
-                   + ", k auto in 4..8, symmetric tiles"},
+                   + ", k auto in 4..8, symmetric tiles" + (", SORTIDU" if a.sortidu else "")},
         "result_pairs_per_s": pairs / elapsed,
         "per_epsilon": per_eps,
         "roofline": {"bound": "alu" if fp32 else "mfma", "achieved": achieved, "peak": peak,

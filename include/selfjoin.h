@@ -86,7 +86,9 @@ typedef struct sj_options {
     uint32_t autotune;      /* selfjoin_run_batched only: 1 = time candidate tile lengths and queue granularities on the batch and keep the fastest */
     uint64_t mem_budget;    /* device bytes the result buffers may use; 0 = a default share of free device memory */
     uint32_t fp32_form;     /* SJ_PREC_FP32 arithmetic: enum sj_fp32_form */
-    uint32_t reserved0;     /* must be 0 */
+    uint32_t sortidu;       /* 1 = SORTIDU (Section 4.3): points of each cell sorted by one un-indexed
+                               dimension u, and each block of queries searches every adjacent cell only
+                               for points within epsilon of the block's u-range; 0 = off */
 } sj_options;
 
 /* How the FP32 filter evaluates squared distances.  Both are exact filters
@@ -101,7 +103,7 @@ enum sj_fp32_form { SJ_FP32_AUTO = 0, SJ_FP32_DIFFERENCE = 1, SJ_FP32_NORM = 2 }
 
 /* Fills *opts with the defaults: k = 0 (auto, 4..8), reorder = 1,
  * shortc = 1, precision = SJ_PREC_FP32, batch_pairs = 0, min_batches = 0,
- * mem_budget = 0, fp32_form = SJ_FP32_AUTO.  Callers built against an
+ * mem_budget = 0, fp32_form = SJ_FP32_AUTO, sortidu = 0.  Callers built against an
  * older header may pass a shorter struct (struct_size); missing fields take
  * their defaults. */
 void selfjoin_default_options(sj_options *opts);

@@ -153,14 +153,23 @@ bool make_geometry(const sj_index &ix, uint32_t k, Geometry &g) {
   }
   const uint32_t cell_bits = bits_for(mult - 1);
   // fine key: Morton code of up to SJ_FINE_DIMS reordered dimensions,
-  // SJ_FINE_BITS bits each, as far as the 64-bit sort key allows
-  const uint32_t fm = std::min<uint32_t>(ix.d, SJ_FINE_DIMS);
+  // SJ_FINE_BITS bits each, as far as the 64-bit sort key allows; with
+  // SORTIDU the quantised coordinate u of one un-indexed dimension instead
+  // (the first one after the k indexed; reordered dimension 0 when k = d),
+  // up to 24 bits, so every cell is sorted by u (Section 4.3)
+  uint32_t fm = std::min<uint32_t>(ix.d, SJ_FINE_DIMS);
   uint32_t fb = SJ_FINE_BITS;
+  uint32_t u_rank = 0;
+  if (ix.opt.sortidu) {
+    u_rank = k < ix.d ? k : 0;
+    fm = 1;
+    fb = std::min<uint32_t>(24, 63 - std::min<uint32_t>(cell_bits, 63));
+  }
   while (fb > 0 && cell_bits + fm * fb > 63) --fb;
   g.kp.fm = fb ? fm : 0;
   g.kp.fb = fb;
   for (uint32_t r = 0; r < g.kp.fm; ++r) {
-    const uint32_t t = ix.perm[r];
+    const uint32_t t = ix.perm[ix.opt.sortidu ? u_rank : r];
     g.kp.fdim[r] = t;
     g.kp.forg[r] = ix.dmin[t];
     const double span = ix.dmax[t] - ix.dmin[t];
@@ -168,6 +177,7 @@ bool make_geometry(const sj_index &ix, uint32_t k, Geometry &g) {
   }
   g.fine_bits = g.kp.fm * g.kp.fb;
   g.key_bits = cell_bits + g.fine_bits;
+  g.u_rank = u_rank;
   uint64_t noff = 1;
   for (uint32_t r = 0; r < k; ++r) noff *= 3;
   g.np.n_off = noff;
@@ -197,6 +207,10 @@ uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t
   if (keep) {
     launch_gather(P, n, ix.d, ix.dp, ix.perm_d.as<uint32_t>(), vb[0], ix.X.as<float>(),
                   ix.orig_id.as<uint32_t>(), ix.pos_of.as<uint32_t>(), s);
+    if (ix.opt.sortidu) {  // the sorted keys: SORTIDU searches their u part
+      ix.skey.alloc(n * 8);
+      SJ_HIP(hipMemcpyAsync(ix.skey.p, kb[0], n * 8, hipMemcpyDeviceToDevice, s));
+    }
   }
   uint32_t *d_ncell = t.small.as<uint32_t>();
   launch_compact(kb[0], n, g.fine_bits, t.flag.as<uint32_t>(), d_ncell,
@@ -278,9 +292,27 @@ uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &
 // their query block, then by block: units that run at the same time then
 // read overlapping candidate rows (shared in the caches) instead of every
 // stretch of one block.
+// SORTIDU search parameters of a handle (its sort keys' u part).
+USearch usearch_of(const sj_index &ix) {
+  const Geometry &g = ix.geom;
+  USearch us{};
+  us.ur = g.u_rank;
+  us.dp = ix.dp;
+  us.fmask = g.fine_bits ? ((1ull << g.fine_bits) - 1ull) : 0ull;
+  us.org = g.kp.fm ? g.kp.forg[0] : 0.0;
+  us.scale = g.kp.fm ? g.kp.fscale[0] : 0.0;
+  us.fmax = g.kp.fb ? (1u << g.kp.fb) - 1u : 0u;
+  us.eps = ix.eps;
+  return us;
+}
+
+// With u_ranges (SORTIDU; contiguous queries only), every query block gets
+// its own candidate ranges (launch_qb_ranges, into *u_ranges) and the units
+// are cut from those instead of from the cells' runs.
 uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
                          const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
-                         DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch = false) {
+                         DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch,
+                         DevBuf *u_ranges) {
   const uint64_t nc = ix.ncell;
   ScratchScope scope;  // every temporary below is dead at the final synchronisation
   TmpBuf qb_off, run_total, scan, tot;
@@ -297,14 +329,47 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
   SJ_HIP(hipMemcpyAsync(&h_nqb, tot.p, 4, hipMemcpyDeviceToHost, s));
   SJ_HIP(hipStreamSynchronize(s));
   const uint64_t nqb = h_nqb;
+  // the runs the units are cut from: the cells' (indexed by cell), or with
+  // SORTIDU each block's own ranges (indexed by block)
+  const uint32_t *r_off = run_off.as<uint32_t>();
+  const uint2 *r_runs = runs.as<uint2>();
+  const uint64_t *r_total = run_total.as<uint64_t>();
+  int per_block = 0;
+  TmpBuf rcount, rlen;
+  if (u_ranges && !qlist && nqb) {
+    const sj_index &E = entries_of(ix);
+    const USearch us = usearch_of(E);
+    rcount.alloc((nqb + 1) * 4);
+    rlen.alloc(nqb * 8);
+    SJ_HIP(hipMemsetAsync(rcount.p, 0, (nqb + 1) * 4, s));
+    launch_qb_ranges(0, sym, nqb, nc, tq, ix.cell_start.as<uint32_t>(), qb_off.as<uint32_t>(),
+                     ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(),
+                     E.cell_start.as<uint32_t>(), E.skey.as<uint64_t>(), ix.X.as<float>(), us,
+                     rcount.as<uint32_t>(), rlen.as<uint64_t>(), nullptr, nullptr, s);
+    scan.alloc(scan_tmp_bytes(nqb + 1) + 64);
+    exclusive_scan_u32(rcount.as<uint32_t>(), rcount.as<uint32_t>(), nqb + 1, tot.as<uint32_t>(),
+                       scan.p, s);
+    uint32_t h_nr = 0;
+    SJ_HIP(hipMemcpyAsync(&h_nr, tot.p, 4, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    u_ranges->alloc(std::max<uint64_t>(h_nr, 1) * sizeof(uint2));
+    launch_qb_ranges(1, sym, nqb, nc, tq, ix.cell_start.as<uint32_t>(), qb_off.as<uint32_t>(),
+                     ix.nbr_off.as<uint32_t>(), ix.nbr_cell.as<uint32_t>(),
+                     E.cell_start.as<uint32_t>(), E.skey.as<uint64_t>(), ix.X.as<float>(), us,
+                     nullptr, nullptr, rcount.as<uint32_t>(), u_ranges->as<uint2>(), s);
+    r_off = rcount.as<uint32_t>();
+    r_runs = u_ranges->as<uint2>();
+    r_total = rlen.as<uint64_t>();
+    per_block = 1;
+  }
   TmpBuf units, ev;
   units.alloc((nqb + 1) * 4);
   ev.alloc((nqb + 1) * 8);
   SJ_HIP(hipMemsetAsync(units.p, 0, (nqb + 1) * 4, s));
   SJ_HIP(hipMemsetAsync(ev.p, 0, (nqb + 1) * 8, s));
   launch_wu_count(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
-                  qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
-                  run_total.as<uint64_t>(), units.as<uint32_t>(), ev.as<uint64_t>(), s);
+                  qb_off.as<uint32_t>(), r_off, r_runs, r_total, units.as<uint32_t>(),
+                  ev.as<uint64_t>(), s, per_block);
   scan.alloc(scan_tmp_bytes(nqb + 1) + 64);
   exclusive_scan_u32(units.as<uint32_t>(), units.as<uint32_t>(), nqb + 1, tot.as<uint32_t>(),
                      scan.p, s);
@@ -322,9 +387,8 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
     keys[0].alloc(n_wu * 8);
     keys[1].alloc(n_wu * 8);
     launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
-                   qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
-                   run_total.as<uint64_t>(), units.as<uint32_t>(), unordered.as<WorkUnit>(),
-                   keys[0].as<uint64_t>(), s);
+                   qb_off.as<uint32_t>(), r_off, r_runs, r_total, units.as<uint32_t>(),
+                   unordered.as<WorkUnit>(), keys[0].as<uint64_t>(), s, per_block);
     // stable LSD sort on the stretch index (high word) keeps block order
     std::vector<int> sh;
     for (uint32_t b = 0; b < bits_for(n_wu - 1); b += 8) sh.push_back(32 + (int)b);
@@ -334,9 +398,8 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
     launch_gather_wu(unordered.as<WorkUnit>(), kb[0], n_wu, out.as<WorkUnit>(), s);
   } else {
     launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
-                   qb_off.as<uint32_t>(), run_off.as<uint32_t>(), runs.as<uint2>(),
-                   run_total.as<uint64_t>(), units.as<uint32_t>(), out.as<WorkUnit>(), nullptr,
-                   s);
+                   qb_off.as<uint32_t>(), r_off, r_runs, r_total, units.as<uint32_t>(),
+                   out.as<WorkUnit>(), nullptr, s, per_block);
   }
   SJ_HIP(hipStreamSynchronize(s));
   return n_wu;
@@ -635,11 +698,13 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   if (ix.opt.precision == SJ_PREC_FP32) choose_fp32_form(ix, s);
   ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form);
   uint64_t ev = 0;
-  DevBuf probe;
-  build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s);
+  DevBuf probe, probe_r;
+  const bool su = ix.opt.sortidu != 0;  // units from per-block SORTIDU ranges
+  build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s,
+                  false, su ? &probe_r : nullptr);
   ix.tc = choose_tc(ev, ix.tq);
   ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc, ix.wu,
-                            &ix.evaluated_sym, s, kWuByStretch);
+                            &ix.evaluated_sym, s, kWuByStretch, su ? &ix.uruns : nullptr);
   if (ix.opt.precision != SJ_PREC_FP32) {
     mfma_prepare(ix, s);
     ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);         // per wave (batched kernel)
@@ -652,7 +717,8 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     ix.tc_single = ix.mfma_per_wave ? choose_tc(ev, ix.tq_single)
                                     : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
     ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_single,
-                                ix.tc_single, ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch);
+                                ix.tc_single, ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch,
+                                su ? &ix.uruns_m : nullptr);
   }
 
   SJ_HIP(hipEventRecord(ev1.e, s));
@@ -804,12 +870,14 @@ void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream
                        q.norm_qa.as<float>(), cr.as<float>(), nsum.as<double>(), s);
   }
   uint64_t ev = 0;
-  DevBuf probe;
-  build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq, 16384, probe, &ev, s);
+  DevBuf probe, probe_r;
+  const bool su = q.opt.sortidu != 0;  // units from per-block SORTIDU ranges
+  build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq, 16384, probe, &ev, s,
+                  false, su ? &probe_r : nullptr);
   q.tc = choose_tc(ev, q.tq);
   if (q.prec == SJ_PREC_FP32) {
     q.n_wu = build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq, q.tc, q.wu,
-                             &q.evaluated_sym, s, kWuByStretch);
+                             &q.evaluated_sym, s, kWuByStretch, su ? &q.uruns : nullptr);
   } else {
     // the queries' operands and thresholds against E's centring and maxima
     q.n_pad = (q.n_near + 31) / 32 * 32 + 64;
@@ -838,7 +906,8 @@ void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream
     q.tc_single = q.mfma_per_wave ? choose_tc(ev, q.tq_single)
                                   : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
     q.n_wu_m = build_workunits(q, 0, nullptr, 0, q.run_off_full, q.runs_full, q.tq_single,
-                               q.tc_single, q.wu_m, &q.evaluated_sym_m, s, kWuByStretch);
+                               q.tc_single, q.wu_m, &q.evaluated_sym_m, s, kWuByStretch,
+                               su ? &q.uruns_m : nullptr);
     q.evaluated_sym = q.evaluated_sym_m;
   }
   finish();
@@ -1021,8 +1090,10 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
     SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
     const bool m = ix.prec != SJ_PREC_FP32;
     const bool self = !ix.entries;  // a self-join's units are symmetric
-    join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, self ? ix.runs_sym : ix.runs_full,
-                nullptr, self ? 1 : 0, 0, ix.pairs.as<uint64_t>(), cap, s, &ms_join);
+    const DevBuf &runs = ix.opt.sortidu ? (m ? ix.uruns_m : ix.uruns)
+                                        : (self ? ix.runs_sym : ix.runs_full);
+    join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, runs, nullptr, self ? 1 : 0, 0,
+                ix.pairs.as<uint64_t>(), cap, s, &ms_join);
     const uint64_t got = read_counter(ix, 0, s);
     if (got <= cap) {
       ix.total = got;
@@ -1307,7 +1378,7 @@ sj_options checked_options(const float *points, uint64_t n, uint32_t d, double e
   }
   if (o.precision > SJ_PREC_BF16) fail(SJ_ERR_INVALID_ARG, "unknown precision");
   if (o.fp32_form > SJ_FP32_NORM) fail(SJ_ERR_INVALID_ARG, "unknown fp32_form");
-  if (o.reserved0 != 0) fail(SJ_ERR_INVALID_ARG, "sj_options.reserved0 must be 0");
+  if (o.sortidu > 1) fail(SJ_ERR_INVALID_ARG, "sj_options.sortidu must be 0 or 1");
   if (o.k < 0) fail(SJ_ERR_INVALID_ARG, "k must be >= 0");
   return o;
 }

@@ -34,11 +34,7 @@
 
 #include "sj_runtime.hpp"
 
-namespace sj {
-uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
-                         const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
-                         DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch = false);
-}
+
 
 using namespace sj;
 

@@ -389,8 +389,9 @@ __global__ __launch_bounds__(kBlock) void k_wu_cells(
 // slot range and candidate count.
 struct QBlock {
   uint32_t A, q0, q1;
-  uint64_t L;   // candidates of the block
+  uint64_t L;       // candidates of the block
   uint32_t skip;
+  uint32_t r0, r1;  // its runs [r0, r1)
 };
 
 __device__ __forceinline__ QBlock query_block(uint64_t t, int sym, uint64_t ncell, uint32_t tq,
@@ -399,7 +400,8 @@ __device__ __forceinline__ QBlock query_block(uint64_t t, int sym, uint64_t ncel
                                               const uint32_t *__restrict__ qb_off,
                                               const uint32_t *__restrict__ run_off,
                                               const uint2 *__restrict__ runs,
-                                              const uint64_t *__restrict__ run_total) {
+                                              const uint64_t *__restrict__ run_total,
+                                              int per_block) {
   uint64_t lo = 0, hi = ncell;  // last cell with qb_off[A] <= t
   while (hi - lo > 1) {
     const uint64_t m = (lo + hi) >> 1;
@@ -413,8 +415,16 @@ __device__ __forceinline__ QBlock query_block(uint64_t t, int sym, uint64_t ncel
   cell_query_slots(lo, cell_start, qlist, nq, &qa, &qe);
   b.q0 = qa + (uint32_t)(t - qb_off[lo]) * tq;
   b.q1 = min(b.q0 + tq, qe);
-  const uint32_t r0 = run_off[lo];
-  b.skip = sym ? (b.q0 - runs[r0].x) : 0u;
+  if (per_block) {  // the block's own runs (SORTIDU ranges), already cut at q0
+    b.r0 = run_off[t];
+    b.r1 = run_off[t + 1];
+    b.skip = 0u;
+    b.L = run_total[t];
+    return b;
+  }
+  b.r0 = run_off[lo];
+  b.r1 = run_off[lo + 1];
+  b.skip = sym ? (b.q0 - runs[b.r0].x) : 0u;
   b.L = run_total[lo] - b.skip;
   return b;
 }
@@ -424,11 +434,11 @@ __global__ __launch_bounds__(kBlock) void k_wu_count(
     const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qlist, uint64_t nq,
     const uint32_t *__restrict__ qb_off, const uint32_t *__restrict__ run_off,
     const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_total,
-    uint32_t *__restrict__ units, uint64_t *__restrict__ eval) {
+    uint32_t *__restrict__ units, uint64_t *__restrict__ eval, int per_block) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= nqb_total) return;
   const QBlock b = query_block(t, sym, ncell, tq, cell_start, qlist, nq, qb_off, run_off, runs,
-                               run_total);
+                               run_total, per_block);
   units[t] = (uint32_t)((b.L + tc - 1) / tc);
   eval[t] = (uint64_t)(b.q1 - b.q0) * b.L;
 }
@@ -439,15 +449,15 @@ __global__ __launch_bounds__(kBlock) void k_wu_fill(
     const uint32_t *__restrict__ qb_off, const uint32_t *__restrict__ run_off,
     const uint2 *__restrict__ runs, const uint64_t *__restrict__ run_total,
     const uint32_t *__restrict__ unit_off, WorkUnit *__restrict__ wu,
-    uint64_t *__restrict__ order_key) {
+    uint64_t *__restrict__ order_key, int per_block) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= nqb_total) return;
   const QBlock b = query_block(t, sym, ncell, tq, cell_start, qlist, nq, qb_off, run_off, runs,
-                               run_total);
+                               run_total, per_block);
   if (b.L == 0) return;
   const uint32_t nu = (uint32_t)((b.L + tc - 1) / tc);
-  const uint32_t r1 = run_off[b.A + 1];
-  uint32_t r = run_off[b.A];
+  const uint32_t r1 = b.r1;
+  uint32_t r = b.r0;
   uint32_t c = runs[r].x + b.skip;
   uint32_t w = unit_off[t];
   for (uint32_t u = 0; u < nu; ++u) {
@@ -473,6 +483,114 @@ __global__ __launch_bounds__(kBlock) void k_wu_fill(
     if (order_key) order_key[w] = ((uint64_t)u << 32) | w;
     wu[w++] = x;
     if (c == runs[r].y && r + 1 < r1) { ++r; c = runs[r].x; }
+  }
+}
+
+// SORTIDU for blocks of queries (see launch_qb_ranges).  The window around
+// the block's u-range [umin, umax] is widened by eps (1 + 2^-16) plus a
+// relative 2^-40: a candidate outside it is farther than eps (1 + 2^-16)
+// from every query of the block along u alone, so its canonical FP64 sum
+// exceeds eps^2 and no pair is lost.  The window is quantised like the sort
+// key, so the search runs over the sorted keys of each adjacent cell.
+__device__ __forceinline__ uint32_t quantise_u(double v, const USearch &us) {
+  double q = (v - us.org) * us.scale;
+  q = q < 0.0 ? 0.0 : q;
+  q = q > (double)us.fmax ? (double)us.fmax : q;
+  return (uint32_t)q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qb_ranges(
+    int pass, int sym, uint64_t nqb_total, uint64_t ncell, uint32_t tq,
+    const uint32_t *__restrict__ cell_start, const uint32_t *__restrict__ qb_off,
+    const uint32_t *__restrict__ nbr_off, const uint32_t *__restrict__ nbr_cell,
+    const uint32_t *__restrict__ ecell_start, const uint64_t *__restrict__ ekey,
+    const float *__restrict__ Xq, USearch us, uint32_t *__restrict__ rcount,
+    uint64_t *__restrict__ rlen, const uint32_t *__restrict__ roff, uint2 *__restrict__ ranges) {
+  const uint32_t l = lane_id();
+  const uint64_t nw = (uint64_t)gridDim.x * kWavesPerBlock;
+  for (uint64_t t = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; t < nqb_total;
+       t += nw) {
+    // the block: its cell A (last cell with qb_off[A] <= t) and slots
+    uint64_t lo = 0, hi = ncell;
+    while (hi - lo > 1) {
+      const uint64_t m = (lo + hi) >> 1;
+      if (qb_off[m] <= t) lo = m; else hi = m;
+    }
+    const uint32_t A = (uint32_t)lo;
+    const uint32_t q0 = cell_start[A] + (uint32_t)(t - qb_off[A]) * tq;
+    const uint32_t q1 = min(q0 + tq, cell_start[A + 1]);
+    // the queries' u-range
+    float umin = __builtin_inff(), umax = -__builtin_inff();
+    for (uint32_t q = q0 + l; q < q1; q += kWave) {
+      const float u = Xq[(uint64_t)q * us.dp + us.ur];
+      umin = fminf(umin, u);
+      umax = fmaxf(umax, u);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      umin = fminf(umin, __shfl_xor(umin, off));
+      umax = fmaxf(umax, __shfl_xor(umax, off));
+    }
+    const double dl = (double)umin, dh = (double)umax;
+    const double wl = us.eps * (1.0 + 0x1p-16) + (__builtin_fabs(dl) + us.eps) * 0x1p-40;
+    const double wh = us.eps * (1.0 + 0x1p-16) + (__builtin_fabs(dh) + us.eps) * 0x1p-40;
+    const uint64_t flo = quantise_u(dl - wl, us), fhi = quantise_u(dh + wh, us);
+    // adjacent cells, 64 at a time: each lane searches one cell, then the
+    // wave merges the lanes' ranges in cell order
+    const uint32_t b0 = nbr_off[A], b1 = nbr_off[A + 1];
+    uint32_t cnt = 0, oc0 = 0, oc1 = 0;
+    uint64_t len = 0;
+    bool open = false;
+    const uint32_t wbase = pass ? roff[t] : 0u;
+    for (uint32_t base = b0; base < b1; base += kWave) {
+      const uint32_t i = base + l;
+      uint32_t c0 = 0, c1 = 0;
+      if (i < b1) {
+        const uint32_t B = nbr_cell[i];
+        if (!(sym && B < A)) {
+          const uint32_t cs = ecell_start[B], ce = ecell_start[B + 1];
+          uint32_t a = cs, b = ce;  // first position with u-part >= flo
+          while (a < b) {
+            const uint32_t m = (a + b) >> 1;
+            if ((ekey[m] & us.fmask) < flo) a = m + 1; else b = m;
+          }
+          c0 = a;
+          b = ce;  // first position with u-part > fhi
+          while (a < b) {
+            const uint32_t m = (a + b) >> 1;
+            if ((ekey[m] & us.fmask) <= fhi) a = m + 1; else b = m;
+          }
+          c1 = a;
+          if (sym && B == A && c0 < q0) c0 = q0;
+        }
+      }
+      const uint32_t nl = min((uint32_t)kWave, b1 - base);
+      for (uint32_t j = 0; j < nl; ++j) {
+        const uint32_t x0 = (uint32_t)__builtin_amdgcn_readlane((int)c0, (int)j);
+        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)c1, (int)j);
+        if (x1 <= x0) continue;
+        if (open && x0 == oc1) {
+          oc1 = x1;
+          continue;
+        }
+        if (open) {
+          if (pass && l == 0) ranges[wbase + cnt] = make_uint2(oc0, oc1);
+          len += oc1 - oc0;
+          ++cnt;
+        }
+        open = true;
+        oc0 = x0;
+        oc1 = x1;
+      }
+    }
+    if (open) {
+      if (pass && l == 0) ranges[wbase + cnt] = make_uint2(oc0, oc1);
+      len += oc1 - oc0;
+      ++cnt;
+    }
+    if (!pass && l == 0) {
+      rcount[t] = cnt;
+      rlen[t] = len;
+    }
   }
 }
 
@@ -620,11 +738,12 @@ void launch_wu_cells(uint64_t ncell, uint32_t tq, const uint32_t *cell_start,
 void launch_wu_count(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
                      const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
                      const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
-                     const uint64_t *run_total, uint32_t *units, uint64_t *eval, hipStream_t s) {
+                     const uint64_t *run_total, uint32_t *units, uint64_t *eval, hipStream_t s,
+                     int per_block) {
   if (!nqb_total) return;
   hipLaunchKernelGGL(k_wu_count, dim3(blocks_for(nqb_total)), dim3(kBlock), 0, s, nqb_total, sym,
                      ncell, tq, tc, cell_start, qlist, nq, qb_off, run_off, runs, run_total, units,
-                     eval);
+                     eval, per_block);
   SJ_HIP(hipGetLastError());
 }
 
@@ -632,11 +751,26 @@ void launch_wu_fill(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, ui
                     const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
                     const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
                     const uint64_t *run_total, const uint32_t *unit_off, WorkUnit *wu,
-                    uint64_t *order_key, hipStream_t s) {
+                    uint64_t *order_key, hipStream_t s, int per_block) {
   if (!nqb_total) return;
   hipLaunchKernelGGL(k_wu_fill, dim3(blocks_for(nqb_total)), dim3(kBlock), 0, s, nqb_total, sym,
                      ncell, tq, tc, cell_start, qlist, nq, qb_off, run_off, runs, run_total,
-                     unit_off, wu, order_key);
+                     unit_off, wu, order_key, per_block);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_qb_ranges(int pass, int sym, uint64_t nqb_total, uint64_t ncell, uint32_t tq,
+                      const uint32_t *cell_start, const uint32_t *qb_off,
+                      const uint32_t *nbr_off, const uint32_t *nbr_cell,
+                      const uint32_t *ecell_start, const uint64_t *ekey, const float *Xq,
+                      const USearch &us, uint32_t *rcount, uint64_t *rlen,
+                      const uint32_t *roff, uint2 *ranges, hipStream_t s) {
+  if (!nqb_total) return;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((nqb_total + kWavesPerBlock - 1) /
+                                                     kWavesPerBlock, 1u << 16);
+  hipLaunchKernelGGL(k_qb_ranges, dim3(grid), dim3(kBlock), 0, s, pass, sym, nqb_total, ncell,
+                     tq, cell_start, qb_off, nbr_off, nbr_cell, ecell_start, ekey, Xq, us,
+                     rcount, rlen, roff, ranges);
   SJ_HIP(hipGetLastError());
 }
 

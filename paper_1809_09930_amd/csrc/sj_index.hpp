@@ -69,20 +69,43 @@ void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
                  const uint32_t *nbr_off, const uint32_t *nbr_cell, uint32_t *run_count,
                  const uint32_t *run_off, uint2 *runs, hipStream_t s);
 // Work units in three steps: per cell (query blocks, run total), per query
-// block (units, evaluated pairs), per query block (fill).
+// block (units, evaluated pairs), per query block (fill).  With per_block,
+// run_off / run_total are indexed by query block (each block has runs of
+// its own, the SORTIDU ranges) instead of by cell.
 void launch_wu_cells(uint64_t ncell, uint32_t tq, const uint32_t *cell_start,
                      const uint32_t *qlist, uint64_t nq, const uint32_t *run_off,
                      const uint2 *runs, uint32_t *nqb, uint64_t *run_total, hipStream_t s);
 void launch_wu_count(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
                      const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
                      const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
-                     const uint64_t *run_total, uint32_t *units, uint64_t *eval, hipStream_t s);
+                     const uint64_t *run_total, uint32_t *units, uint64_t *eval, hipStream_t s,
+                     int per_block = 0);
 void launch_wu_fill(uint64_t nqb_total, int sym, uint64_t ncell, uint32_t tq, uint32_t tc,
                     const uint32_t *cell_start, const uint32_t *qlist, uint64_t nq,
                     const uint32_t *qb_off, const uint32_t *run_off, const uint2 *runs,
                     const uint64_t *run_total, const uint32_t *unit_off, WorkUnit *wu,
-                    uint64_t *order_key,
-                    hipStream_t s);
+                    uint64_t *order_key, hipStream_t s, int per_block = 0);
+// SORTIDU search along u (Section 4.3) for blocks of queries.
+struct USearch {
+  uint32_t ur, dp;   // reordered column of u in the query rows, row stride
+  uint64_t fmask;    // fine (quantised u) part of a sort key
+  double org, scale; // quantisation of u, as in the sort key
+  uint32_t fmax;
+  double eps;
+};
+// Per query block t of contiguous query slots (blocks as in the work units:
+// qb_off over the query cells, tq slots each): its candidate ranges in the
+// adjacent cells of the indexed side (nbr_off / nbr_cell into ecell_start,
+// sorted keys ekey), restricted to the points within eps of the block's
+// u-range, ranges that touch merged; sym keeps cells B >= A and starts A's
+// own range at the block's first query.  pass 0: rcount[t] ranges of
+// rlen[t] candidates; pass 1: the ranges from roff[t].
+void launch_qb_ranges(int pass, int sym, uint64_t nqb_total, uint64_t ncell, uint32_t tq,
+                      const uint32_t *cell_start, const uint32_t *qb_off,
+                      const uint32_t *nbr_off, const uint32_t *nbr_cell,
+                      const uint32_t *ecell_start, const uint64_t *ekey, const float *Xq,
+                      const USearch &us, uint32_t *rcount, uint64_t *rlen,
+                      const uint32_t *roff, uint2 *ranges, hipStream_t s);
 // dst[i] = src[(uint32_t)keys[i]] (work units in the order of sorted keys)
 void launch_gather_wu(const WorkUnit *src, const uint64_t *keys, uint64_t n, WorkUnit *dst,
                       hipStream_t s);

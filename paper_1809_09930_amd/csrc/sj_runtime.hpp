@@ -177,6 +177,7 @@ struct Geometry {
   NbrParams np{};
   uint32_t key_bits = 0;   // bits of the sort key
   uint32_t fine_bits = 0;  // low bits of the sort key below the cell key
+  uint32_t u_rank = 0;     // SORTIDU: reordered position of the dimension u
 };
 
 inline double gamma_n(double m, double u) { return m * u / (1.0 - m * u); }
@@ -212,6 +213,7 @@ struct sj_index {
 
   // index
   DevBuf X, orig_id, pos_of, perm_d, inv_perm_d;
+  DevBuf skey;  // SORTIDU: sorted keys (cell key << fine bits | quantised u), position order
   DevBuf cell_key, cell_start;
   uint64_t ncell = 0;
   DevBuf nbr_off, nbr_cell;
@@ -220,6 +222,7 @@ struct sj_index {
   uint64_t n_runs_sym = 0, n_runs_full = 0;
   DevBuf wu;
   uint64_t n_wu = 0;
+  DevBuf uruns, uruns_m;  // SORTIDU: per-query-block candidate ranges of wu / wu_m
   uint32_t tq = 256, tc = 16384;
   uint64_t candidates = 0, evaluated_sym = 0;
   DevBuf counters;  // [0] cursor, [1] rechecks
@@ -261,6 +264,14 @@ void fill_defaults(sj_options *o);
 sj_options checked_options(const float *points, uint64_t n, uint32_t d, double epsilon,
                            const sj_options *opts);
 void build(sj_index &ix, const float *points, hipStream_t s);
+// Work units of the distance kernels over the runs (run_off, runs) of ix's
+// cells, queries contiguous or from qlist; *eval receives the pairs they
+// cover.  by_stretch orders them by stretch index; u_ranges (SORTIDU,
+// contiguous queries) cuts them from per-block ranges stored there.
+uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
+                         const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
+                         DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch = false,
+                         DevBuf *u_ranges = nullptr);
 // Builds the query handle q (opt, n set) of the points `queries` against
 // the indexed set E (see sj_index::entries).
 void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream_t s);

@@ -53,7 +53,7 @@ class SjOptions(ctypes.Structure):
                 ("autotune", ctypes.c_uint32),
                 ("mem_budget", ctypes.c_uint64),
                 ("fp32_form", ctypes.c_uint32),
-                ("reserved0", ctypes.c_uint32)]
+                ("sortidu", ctypes.c_uint32)]
 
 
 class SjInfo(ctypes.Structure):
@@ -187,7 +187,8 @@ def _stream_handle(stream):
 def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = True,
                          shortc: bool = True, batch_pairs: int = 0, min_batches: int = 0,
                          mem_budget: int = 0, k_min: int = 4, k_max: int = 8,
-                         precision="fp32", fp32_form="auto", stream=None):
+                         precision="fp32", fp32_form="auto", sortidu: bool = False,
+                         stream=None):
     """Build the grid index over a float32 [n, d] tensor (CUDA or CPU).
     Returns an opaque handle (int)."""
     import torch
@@ -205,6 +206,7 @@ def selfjoin_build_index(points, epsilon: float, k: int = 0, reorder: bool = Tru
     o.mem_budget = int(mem_budget)
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.fp32_form = FP32_FORMS[fp32_form] if isinstance(fp32_form, str) else int(fp32_form)
+    o.sortidu = 1 if sortidu else 0
     h = ctypes.c_void_p()
     n, d = points.shape
     ptr = points.data_ptr() if points.numel() else None

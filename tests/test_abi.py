@@ -95,7 +95,7 @@ def test_bad_option_struct_size(lib):
 
 
 @pytest.mark.parametrize("field,value,msg", [("fp32_form", 3, "fp32_form"),
-                                             ("reserved0", 1, "reserved0"),
+                                             ("sortidu", 2, "sortidu"),
                                              ("precision", 7, "precision")])
 def test_bad_option_values(lib, field, value, msg):
     from paper_1809_09930_amd import selfjoin

@@ -477,3 +477,73 @@ def test_exponential_family_full_size_sampled_rows(workload, eps, prec):
         if st + int(c) < total:
             assert int(oi[st + int(c)]) != r
         off += int(c)
+
+
+# --------------------------------------------------------------------------
+# SORTIDU (Section 4.3): cells sorted by an un-indexed dimension u, each
+# block of queries searching only the points within eps of its u-range.
+# The result is unchanged; the evaluated pairs can only shrink.
+# --------------------------------------------------------------------------
+def _spread_along_u(n, seed):
+    """Three dimensions of ranges 8, 4 and 0.1: indexed on the first alone
+    (k = 1, about 70 cells of side 0.12, so every cell holds several blocks
+    of queries), the second (u) spans about 33 eps, so a block of queries,
+    a slab of its cell along u, finds only part of each adjacent cell."""
+    rng = np.random.default_rng(seed)
+    P = rng.random((n, 3)) * np.array([8.0, 4.0, 0.1])
+    return (np.round(P * 2 ** 20) / 2 ** 20).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("case", ["uniform", "clustered", "spread"])
+def test_sortidu_matches_oracle_and_prunes(prec, case):
+    if case == "uniform":
+        P = datagen.uniform_grid(3000, 16, 81)
+        eps, k = calibrated(P, 30), 0
+    elif case == "clustered":
+        std = datagen.decaying_std(18, 0.2, 0.002, 82)
+        P = datagen.gaussian_mixture(5000, 18, 12, std, 82)
+        eps, k = calibrated(P, 25), 4
+    else:
+        P = _spread_along_u(60000, 83)
+        eps, k = 0.12, 1
+    print("case sortidu", case, prec, flush=True)
+    info_u = assert_same_as_oracle(P, eps, precision=prec, k=k, sortidu=True)
+    info_p = assert_same_as_oracle(P, eps, precision=prec, k=k)
+    assert info_u["evaluated"] <= info_p["evaluated"]
+    if case == "spread":  # blocks are slabs of about a quarter of u's range
+        assert info_u["evaluated"] * 2 < info_p["evaluated"]
+
+
+def test_sortidu_with_every_dimension_indexed_and_in_batches():
+    """k = d (u is then an indexed dimension), and the multi-batch path."""
+    P = datagen.uniform_grid(2500, 5, 84)
+    eps = calibrated(P, 20)
+    assert_same_as_oracle(P, eps, k=5, sortidu=True)
+    assert_same_as_oracle(P, eps, sortidu=True, min_batches=3)
+    assert_same_as_oracle(P, eps, sortidu=True, batch_pairs=4000, precision="fp16")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_sortidu_general_join(prec):
+    from paper_1809_09930_amd import selfjoin as sj
+    E = _spread_along_u(30000, 85)
+    Q = _spread_along_u(8000, 86)
+    Q[:1000, 1] += 3.9  # partly beyond E's range along u
+    eps = 0.12
+    oi, oj = oracle.join(Q, E, eps)
+    he = sj.selfjoin_build_index(torch.from_numpy(E).cuda(), eps, k=1, precision=prec,
+                                 sortidu=True)
+    try:
+        hq = sj.selfjoin_build_query(he, torch.from_numpy(Q).cuda())
+        try:
+            total = sj.selfjoin_run(hq)
+            gi = torch.empty(total, dtype=torch.int32, device="cuda")
+            gj = torch.empty(total, dtype=torch.int32, device="cuda")
+            sj.selfjoin_fetch_pairs(hq, 0, gi, gj, None, max_pairs=total)
+        finally:
+            sj.selfjoin_free(hq)
+    finally:
+        sj.selfjoin_free(he)
+    assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
