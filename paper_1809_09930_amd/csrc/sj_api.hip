@@ -1029,10 +1029,12 @@ uint64_t read_counter(sj_index &ix, int which, hipStream_t s) {
 
 // Estimate |R| from a strided sample of query positions (Section 3.2.2:
 // a count-only pass over a fraction of the points).  Counts pairs the FP32
-// filter cannot reject, so it is an upper-bound estimate.
+// filter cannot reject, so it is an upper-bound estimate.  The sample is
+// 1/64 of the queries, at least 1024 and at most 8192 of them, so it stays
+// a small part of the join's work for small and mid-sized inputs too.
 uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   const uint64_t n = ix.n_near;  // query positions in cells
-  const uint64_t target = 8192;
+  const uint64_t target = std::min<uint64_t>(8192, std::max<uint64_t>(1024, n / 64));
   const uint64_t stride = n <= target ? 1 : n / target;
   const uint64_t nq = (n + stride - 1) / stride;
   ScratchScope scope;  // the read-back of the count below synchronises the stream
