@@ -681,6 +681,11 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
         best = cost;
         g = gk;
         have = true;
+      } else if (cost > best * 1.02) {
+        // C(k) never grows with k (one more indexed dimension only removes
+        // candidates) while the lookups grow as 3^k: once the cost is past
+        // the minimum, larger k are not built
+        break;
       }
     }
     if (!have) {
