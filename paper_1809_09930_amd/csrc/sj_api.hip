@@ -705,11 +705,18 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   uint64_t ev = 0;
   DevBuf probe, probe_r;
   const bool su = ix.opt.sortidu != 0;  // units from per-block SORTIDU ranges
-  build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s,
-                  false, su ? &probe_r : nullptr);
-  ix.tc = choose_tc(ev, ix.tq);
-  ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc, ix.wu,
-                            &ix.evaluated_sym, s, kWuByStretch, su ? &ix.uruns : nullptr);
+  if (ix.batch_job) {
+    // a job of the batched path cuts its own units from runs_sym later; its
+    // symmetric pair count is (C + n) / 2 up to the tiles' rounding
+    ev = (ix.candidates + n) / 2;
+  } else {
+    build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s,
+                    false, su ? &probe_r : nullptr);
+    ix.tc = choose_tc(ev, ix.tq);
+    ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc,
+                              ix.wu, &ix.evaluated_sym, s, kWuByStretch,
+                              su ? &ix.uruns : nullptr);
+  }
   if (ix.opt.precision != SJ_PREC_FP32) {
     mfma_prepare(ix, s);
     ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);         // per wave (batched kernel)
@@ -721,9 +728,10 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     ix.tq_single = ix.mfma_per_wave ? mfma_wave_queries() : tq_wg;
     ix.tc_single = ix.mfma_per_wave ? choose_tc(ev, ix.tq_single)
                                     : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
-    ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_single,
-                                ix.tc_single, ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch,
-                                su ? &ix.uruns_m : nullptr);
+    if (!ix.batch_job)
+      ix.n_wu_m = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_single,
+                                  ix.tc_single, ix.wu_m, &ix.evaluated_sym_m, s, kWuByStretch,
+                                  su ? &ix.uruns_m : nullptr);
   }
 
   SJ_HIP(hipEventRecord(ev1.e, s));

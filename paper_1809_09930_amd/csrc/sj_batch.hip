@@ -331,6 +331,7 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
         ix->eps2 = jb.epsilon * jb.epsilon;
         ix->opt = jopt[j];
         ix->info.struct_size = sizeof(sj_info);
+        ix->batch_job = true;
         build(*ix, jb.points, ws);
         if (ix->n && batched_variant(ix->kp, ix->fmt) < 0)
           fail(SJ_ERR_INVALID_ARG,

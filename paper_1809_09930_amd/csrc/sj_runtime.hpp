@@ -205,6 +205,7 @@ struct sj_index {
   // query operands describe Q, and the candidates are E's.  Null in a
   // self-join (the handle is its own entries).
   const sj_index *entries = nullptr;
+  bool batch_job = false;  // built for the batched path: no single-join work units
   uint64_t n_near = 0;    // points in cells (a query handle drops far queries)
   sj::Geometry geom{};    // grid of the build (k, key and neighbour parameters)
   std::vector<float> mfma_centre;  // matrix-core centring of the indexed set
