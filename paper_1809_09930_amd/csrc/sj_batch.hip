@@ -71,7 +71,10 @@ namespace sj {
 namespace {
 
 constexpr uint32_t kMaxBatchN = (1u << 20) - 1;  // positions fit 20 bits
-constexpr uint32_t kBuildThreads = 8;             // host threads building job indexes
+#ifndef SJ_BUILD_THREADS
+#define SJ_BUILD_THREADS 12
+#endif
+constexpr uint32_t kBuildThreads = SJ_BUILD_THREADS;  // host threads building job indexes
 constexpr size_t kBuildScratchKeep = (size_t)256 << 20;  // scratch a build thread keeps
 
 __global__ void k_tag_wus(WorkUnit *__restrict__ wu, uint64_t count, uint32_t job) {
