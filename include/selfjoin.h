@@ -193,8 +193,9 @@ int selfjoin_fetch_offsets(sj_index *idx, uint64_t *offsets, void *stream);
  * and options the join uses; Q is binned into E's grid and searched against
  * E's cells (Algorithm 1's kernel with the query points taken from Q).
  *   entries  the index of E.  It is only read: it may still be run and
- *            fetched itself, and several query handles may share it, but it
- *            must not be freed before every query handle built on it.
+ *            fetched itself, and several query handles may share it.  If the
+ *            caller frees it first, its memory is released with the last
+ *            query handle built on it.
  *   queries  host or device, row-major float32 [m][d] (d = E's d),
  *            caller-owned; read during the call only.
  *   m        query count (0 allowed: an empty result), m <= 2^32 - 1.
@@ -220,7 +221,8 @@ int selfjoin_get_info(const sj_index *idx, sj_info *info);
  * writes min(cap, d) entries. */
 int selfjoin_get_perm(const sj_index *idx, uint32_t *perm, uint32_t cap);
 
-/* Releases the handle and all its memory.  NULL is ignored. */
+/* Releases the handle and all its memory (an index that query handles
+ * still use: when the last of them is freed).  NULL is ignored. */
 void selfjoin_free(sj_index *idx);
 
 /* ------------------------------------------------------------------------

@@ -1441,6 +1441,7 @@ int selfjoin_build_query(const sj_index *entries, const float *queries, uint64_t
     q->n = m;
     q->info.struct_size = sizeof(sj_info);
     sj::build_query(*q, *entries, queries, static_cast<hipStream_t>(stream));
+    const_cast<sj_index *>(entries)->refs.fetch_add(1);  // kept until the query handle goes
     *out = q.release();
   });
 }
@@ -1495,7 +1496,15 @@ int selfjoin_get_perm(const sj_index *idx, uint32_t *perm, uint32_t cap) {
   });
 }
 
-void selfjoin_free(sj_index *idx) { delete idx; }
+void selfjoin_free(sj_index *idx) {
+  // a handle goes when the caller has freed it and no query handle still
+  // reads it; freeing a query handle releases its entries' reference
+  while (idx && idx->refs.fetch_sub(1) == 1) {
+    sj_index *e = const_cast<sj_index *>(idx->entries);
+    delete idx;
+    idx = e;
+  }
+}
 
 const char *selfjoin_last_error(void) { return sj::g_last_error.c_str(); }
 

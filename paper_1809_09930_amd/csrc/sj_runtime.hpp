@@ -3,6 +3,7 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -205,6 +206,7 @@ struct sj_index {
   // query operands describe Q, and the candidates are E's.  Null in a
   // self-join (the handle is its own entries).
   const sj_index *entries = nullptr;
+  std::atomic<uint32_t> refs{1};  // the caller's handle plus the query handles built on it
   bool batch_job = false;  // built for the batched path: no single-join work units
   uint64_t n_near = 0;    // points in cells (a query handle drops far queries)
   sj::Geometry geom{};    // grid of the build (k, key and neighbour parameters)

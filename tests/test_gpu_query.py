@@ -287,3 +287,26 @@ def test_uniform_2m_d16_query_set_sampled_rows(prec):
         off += int(c)
     sd = total / len(Q) - 1.0
     assert 40 < sd < 90
+
+
+def test_entries_freed_before_the_query_handle():
+    """Freeing the index first keeps it alive for its query handles: the
+    query handle still runs and fetches, and the last free releases both."""
+    sj = _sj()
+    E = datagen.uniform_grid(3000, 8, 91)
+    Q = datagen.uniform_grid(900, 8, 92)
+    eps = calibrated(E, 20)
+    oi, oj = oracle.join(Q, E, eps)
+    he = sj.selfjoin_build_index(torch.from_numpy(E).cuda(), eps)
+    hq1 = sj.selfjoin_build_query(he, torch.from_numpy(Q).cuda())
+    hq2 = sj.selfjoin_build_query(he, torch.from_numpy(Q[:100]).cuda())
+    sj.selfjoin_free(he)
+    for hq, m in ((hq1, len(Q)), (hq2, 100)):
+        total = sj.selfjoin_run(hq)
+        gi = torch.empty(total, dtype=torch.int32, device="cuda")
+        gj = torch.empty(total, dtype=torch.int32, device="cuda")
+        sj.selfjoin_fetch_pairs(hq, 0, gi, gj, None, max_pairs=total)
+        keep = oi < m
+        assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi[keep])
+        assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj[keep])
+        sj.selfjoin_free(hq)
