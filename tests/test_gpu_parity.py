@@ -547,3 +547,40 @@ def test_sortidu_general_join(prec):
         sj.selfjoin_free(he)
     assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
     assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
+
+
+@pytest.mark.parametrize("workload,target,k", [("uniform_2m_d16", "64", 0),
+                                               ("mixture50_5m_d18", "50", 0)])
+def test_full_size_results_identical_across_filters(workload, target, k):
+    """At full size, every exact filter must give the same whole result: the
+    FP32 difference and norm forms, FP16 and BF16 matrix cores, SORTIDU,
+    and another k.  The CSR row starts and the neighbour column of each run
+    are compared element by element with the first run's."""
+    import json
+    import os
+    from conftest import GOLDEN
+    from paper_1809_09930_amd import selfjoin as sj
+    with open(os.path.join(GOLDEN, "eps.json")) as f:
+        eps = float.fromhex(json.load(f)[workload]["eps"][target]["hex"])
+    P = datagen.make_workload(workload)
+    Pd = torch.from_numpy(P).cuda()
+    runs = [dict(fp32_form="norm"), dict(fp32_form="difference"), dict(precision="fp16"),
+            dict(precision="bf16"), dict(sortidu=True), dict(k=5, precision="fp16")]
+    ref = None
+    for opts in runs:
+        print("case", workload, opts, flush=True)
+        h = sj.selfjoin_build_index(Pd, eps, **opts)
+        try:
+            total = sj.selfjoin_run(h)
+            nb = torch.empty(total, dtype=torch.int32, device="cuda")
+            sj.selfjoin_fetch_pairs(h, 0, None, nb, None, max_pairs=total)
+            off = torch.empty(len(P) + 1, dtype=torch.int64, device="cuda")
+            sj.selfjoin_fetch_offsets(h, off)
+        finally:
+            sj.selfjoin_free(h)
+        if ref is None:
+            ref = (off, nb)
+            assert int(off[-1]) == total and bool((off[1:] > off[:-1]).all())
+        else:
+            assert torch.equal(off, ref[0]), opts
+            assert torch.equal(nb, ref[1]), opts
