@@ -122,3 +122,24 @@ def test_short_option_struct_takes_defaults(lib):
                                   None, None)
     assert rc == selfjoin.SJ_ERR_INVALID_ARG
     assert "struct_size" not in lib.selfjoin_last_error().decode()
+
+
+def test_build_query_rejects_null_arguments(lib):
+    """Argument checks of the general join entry point run before any device
+    call, so they hold without a GPU."""
+    from paper_1809_09930_amd import selfjoin
+    h = ctypes.c_void_p()
+    buf = (ctypes.c_float * 8)()
+    rc = lib.selfjoin_build_query(None, ctypes.cast(buf, ctypes.c_void_p), 2, None,
+                                  ctypes.byref(h))
+    assert rc == selfjoin.SJ_ERR_INVALID_ARG and h.value is None
+    assert "NULL" in lib.selfjoin_last_error().decode()
+    rc = lib.selfjoin_build_query(ctypes.cast(buf, ctypes.c_void_p),
+                                  ctypes.cast(buf, ctypes.c_void_p), 2, None, None)
+    assert rc == selfjoin.SJ_ERR_INVALID_ARG
+
+
+def test_default_options_leave_sortidu_off(lib):
+    from paper_1809_09930_amd import selfjoin
+    o = selfjoin.default_options()
+    assert (o.sortidu, o.fp32_form) == (0, selfjoin.SJ_FP32_AUTO)
