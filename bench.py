@@ -116,11 +116,13 @@ def cpu_baseline(P, eps, rows_req):
     n = len(P)
     rng = np.random.default_rng(2024)
     if rows_req <= 0:
-        probe = np.sort(rng.choice(n, size=8, replace=False))
+        # size the sample to about 15 s from a probe that fills every thread
+        m = max(64, 4 * oracle.num_threads())
+        probe = np.sort(rng.choice(n, size=m, replace=False))
         t0 = time.perf_counter()
         oracle.rows(P, eps, probe)
         dt = max(time.perf_counter() - t0, 1e-3)
-        rows_req = int(min(4096, max(16, 8 * 15.0 / dt)))
+        rows_req = int(min(8192, max(16, m * 15.0 / dt)))
     rows = np.sort(rng.choice(n, size=min(rows_req, n), replace=False))
     t0 = time.perf_counter()
     oracle.rows(P, eps, rows)

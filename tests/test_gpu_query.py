@@ -310,3 +310,16 @@ def test_entries_freed_before_the_query_handle():
         assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi[keep])
         assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj[keep])
         sj.selfjoin_free(hq)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(precision="fp16")])
+def test_every_query_far_and_one_dimension(opts):
+    """All queries beyond E's range (no query cell at all), and d = 1."""
+    E = datagen.uniform_grid(2000, 4, 93)
+    eps = calibrated(E, 15)
+    far = datagen.uniform_grid(500, 4, 94) + np.float32(10.0)
+    info, oi = assert_query_join_matches(far, E, eps, **opts)
+    assert len(oi) == 0 and info["n_cells"] == 0
+    E1 = datagen.uniform_grid(4000, 1, 95)
+    Q1 = np.concatenate([datagen.uniform_grid(700, 1, 96), np.float32([[1.0], [-0.001]])])
+    assert_query_join_matches(Q1, E1, 0.002, **opts)
