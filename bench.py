@@ -61,6 +61,10 @@ def parse():
                          "workload, one query handle per set")
     ap.add_argument("--sortidu", action="store_true",
                     help="build every index with SORTIDU (search along one un-indexed dimension)")
+    ap.add_argument("--host-io", action="store_true",
+                    help="instead of the device-resident step: points handed over from host "
+                         "memory and the whole result (i, j) fetched into pinned host memory, "
+                         "timed per epsilon (PCIe-inclusive rate)")
     ap.add_argument("--k-sweep", default="",
                     help="comma list of explicit k: index and join the largest epsilon of the "
                          "workload at each k and report the index-search and distance work")
@@ -301,6 +305,40 @@ def bench_query_sets(a, table, P, Pd, targets, eps_list):
     print(json.dumps(out), flush=True)
 
 
+def bench_host_io(a, P, targets, eps_list):
+    """The whole call sequence with host buffers at both ends: build from a
+    host array (the library copies it to the device), run, and fetch the i
+    and j columns of the result into pinned host memory."""
+    import torch
+    from paper_1809_09930_amd import selfjoin as sj
+    n, d = P.shape
+    Ph = torch.from_numpy(P)
+    rows = {}
+    for t, eps in zip(targets, eps_list):
+        for rep_ in range(a.warmup + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = sj.selfjoin_build_index(Ph, eps, precision=a.precision)
+            t1 = time.perf_counter()
+            total = sj.selfjoin_run(h)
+            t2 = time.perf_counter()
+            oi = torch.empty(total, dtype=torch.int32, pin_memory=True)
+            oj = torch.empty(total, dtype=torch.int32, pin_memory=True)
+            t3 = time.perf_counter()
+            sj.selfjoin_fetch_pairs(h, 0, oi, oj, None, max_pairs=total)
+            t4 = time.perf_counter()
+            info = sj.selfjoin_get_info(h)
+            sj.selfjoin_free(h)
+        rows[t] = {"eps": eps, "pairs": total, "s_build_from_host": round(t1 - t0, 4),
+                   "s_run": round(t2 - t1, 4), "s_fetch_to_pinned_host": round(t4 - t3, 4),
+                   "s_total_excl_host_alloc": round((t4 - t0) - (t3 - t2), 4),
+                   "candidates_per_s": info["candidates"] / ((t4 - t0) - (t3 - t2)),
+                   "fetch_GB_per_s": total * 8 / max(t4 - t3, 1e-9) / 1e9}
+    print(json.dumps({"metric": "PCIe-inclusive self-join (host input, host output)",
+                      "workload": a.workload, "precision": a.precision, "n": n, "d": d,
+                      "per_epsilon": rows}), flush=True)
+
+
 def bench_k_sweep(a, P, Pd, eps):
     """Section 5.5 (Figure 8): index-search work against distance work as k
     grows, at one epsilon.  Per k: non-empty cells #G, adjacent-cell lookups
@@ -374,6 +412,9 @@ def main():
         return
     if a.k_sweep:
         bench_k_sweep(a, P, Pd, eps_list[-1])
+        return
+    if a.host_io:
+        bench_host_io(a, P, targets, eps_list)
         return
 
     def step(record, precision):
