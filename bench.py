@@ -34,13 +34,6 @@ PEAK_FP32_VALU_TFLOPS = 78.6
 PEAK_MFMA_16BIT_TFLOPS = 2500.0
 
 
-def mfma_k(d, precision):
-    """K (padded reduction length) of the matrix-core tiles: d coordinates
-    plus 2 (FP16) or 3 (BF16) norm pieces, rounded up to 16."""
-    pieces = 2 if precision == 1 else 3
-    return (d + pieces + 15) // 16 * 16
-
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

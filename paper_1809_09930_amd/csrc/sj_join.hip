@@ -68,7 +68,10 @@ constexpr int checkpoint_dim(int dp, int k) {
 }
 // floats per point in the norm form's two tables (checkpoints + 1, padded)
 constexpr int norm_row(int dp) {
-  return n_checkpoints(dp) + 1 <= 2 ? 2 : (n_checkpoints(dp) + 1 <= 4 ? 4 : (n_checkpoints(dp) + 1 <= 8 ? 8 : 16));
+  return n_checkpoints(dp) + 1 <= 2   ? 2
+         : n_checkpoints(dp) + 1 <= 4 ? 4
+         : n_checkpoints(dp) + 1 <= 8 ? 8
+                                      : 16;
 }
 static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 floats");
 
@@ -476,17 +479,17 @@ __device__ __forceinline__ void join_body(
 template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_join_fp32(SJ_JOIN_PARAMS) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  join_body<DP, RQ, false, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
-                                       eps2, symmetric, out, capacity, cursor, rechecks,
+  join_body<DP, RQ, false, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d,
+                                       lo, hi, eps2, symmetric, out, capacity, cursor, rechecks,
                                        stage_mem, QA, CR);
 }
 
 // The estimation kernel (count only) used to size result buffers.
 template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_count_fp32(SJ_JOIN_PARAMS) {
-  join_body<DP, RQ, true, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d, lo, hi,
-                                      eps2, symmetric, out, capacity, cursor, rechecks, nullptr,
-                                      QA, CR);
+  join_body<DP, RQ, true, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d,
+                                      lo, hi, eps2, symmetric, out, capacity, cursor, rechecks,
+                                      nullptr, QA, CR);
 }
 
 // Tables of the norm form, one row of norm_row(DP) floats per point p (the
@@ -509,9 +512,10 @@ __global__ __launch_bounds__(kBlock) void k_count_fp32(SJ_JOIN_PARAMS) {
 // the sum over points of N_K-1 (the caller's choice of form uses the mean).
 __device__ __forceinline__ float rd_f32(double v) {
   float f = (float)v;
-  if ((double)f > v) f = __builtin_bit_cast(float, f > 0.0f ? __builtin_bit_cast(uint32_t, f) - 1u
-                                                   : (f == 0.0f ? 0x80000001u
-                                                               : __builtin_bit_cast(uint32_t, f) + 1u));
+  if ((double)f > v) {
+    const uint32_t b = __builtin_bit_cast(uint32_t, f);  // one step towards -inf
+    f = __builtin_bit_cast(float, f > 0.0f ? b - 1u : (f == 0.0f ? 0x80000001u : b + 1u));
+  }
   return f;
 }
 __device__ __forceinline__ float ru_f32(double v) { return -rd_f32(-v); }
@@ -602,12 +606,14 @@ void launch_form(const JoinLaunch &a, hipStream_t s) {
                             : (DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1));
   if (a.count_only)
     hipLaunchKernelGGL((k_count_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
-                       a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
-                       a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks, a.QA, a.CR);
+                       a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d,
+                       a.lo, a.hi, a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks,
+                       a.QA, a.CR);
   else
     hipLaunchKernelGGL((k_join_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
-                       a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d, a.lo, a.hi,
-                       a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks, a.QA, a.CR);
+                       a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d,
+                       a.lo, a.hi, a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks,
+                       a.QA, a.CR);
   SJ_HIP(hipGetLastError());
 }
 
