@@ -137,3 +137,65 @@ def test_batched_error_in_one_job_of_many():
         sj.selfjoin_run_batched(good[:5] + [wide] + good[5:], [0.3] * 13)
     assert e.value.code == sj.SJ_ERR_INVALID_ARG
     check_batch([(g.cpu().numpy(), 0.3) for g in good[:4]])
+
+
+def test_batched_256_workload_sampled_jobs_and_replays():
+    """The benchmark's 256-job batch (its job shapes and epsilons, autotuned
+    as bench.py runs it): sampled jobs against the oracle (whole result for
+    jobs up to 30,000 points, sampled full rows above), every job's pairs
+    sorted and symmetric, and three replays of the captured graph, with
+    eager device work and synchronisations between them, each giving the
+    same pairs again."""
+    import json
+    from conftest import GOLDEN
+    from paper_1809_09930_amd import selfjoin as sj
+    with open(os.path.join(GOLDEN, "eps.json")) as f:
+        entry = json.load(f)["batched_256"]
+    specs = datagen.batched_job_specs(entry["n_jobs"], entry["seed"])
+    pts_h = [datagen.make_job(sp) for sp in specs]
+    eps = [float.fromhex(j["hex"]) for j in entry["jobs"]]
+    pts = [torch.from_numpy(P).cuda() for P in pts_h]
+    rng = np.random.default_rng(17)
+    sizes = np.array([len(P) for P in pts_h])
+    pick = sorted({int(sizes.argmax()), int(sizes.argmin())} |
+                  set(rng.choice(len(pts), 4, replace=False).tolist()))
+    h = sj.selfjoin_run_batched(pts, eps, precision="fp16", autotune=True)
+    try:
+        info = sj.selfjoin_batch_get_info(h)
+        total = 0
+        for j in range(len(pts)):
+            first, count = sj.selfjoin_batch_range(h, j)
+            total += count
+        assert total == info["pairs"]
+        first_fetch = {}
+        for j in pick:
+            P, e = pts_h[j], eps[j]
+            gi, gj, _ = fetch_job(sj, h, j)
+            first_fetch[j] = (gi, gj)
+            key = gi.astype(np.uint64) << np.uint64(32) | gj.astype(np.uint64)
+            assert (np.diff(key.astype(np.int64)) > 0).all(), j
+            rkey = np.sort(gj.astype(np.uint64) << np.uint64(32) | gi.astype(np.uint64))
+            assert np.array_equal(rkey, key), j
+            if len(P) <= 30000:
+                ri, rj = oracle.bruteforce(P, e)
+                assert np.array_equal(gi, ri) and np.array_equal(gj, rj), j
+            else:
+                rows = np.sort(rng.choice(len(P), 16, replace=False))
+                cnt, js = oracle.rows(P, e, rows)
+                starts = np.searchsorted(gi, rows)
+                off = 0
+                for r, c, st in zip(rows, cnt, starts):
+                    assert np.array_equal(gj[st:st + int(c)], js[off:off + c]), (j, r)
+                    off += int(c)
+        for rep in range(3):
+            x = torch.randn(1 << 20, device="cuda")
+            torch.cuda.synchronize()
+            assert float((x * x).sum()) > 0
+            sj.selfjoin_batch_replay(h)
+            torch.cuda.synchronize()
+            for j in pick:
+                gi, gj, _ = fetch_job(sj, h, j)
+                assert np.array_equal(gi, first_fetch[j][0]), (rep, j)
+                assert np.array_equal(gj, first_fetch[j][1]), (rep, j)
+    finally:
+        sj.selfjoin_batch_free(h)
