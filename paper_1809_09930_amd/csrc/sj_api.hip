@@ -1087,11 +1087,12 @@ uint64_t default_budget() {
 void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s) {
   const uint64_t ne = entries_of(ix).n;
   const uint32_t ibits = bits_for(ix.n ? ix.n - 1 : 0), jbits = bits_for(ne ? ne - 1 : 0);
-  std::vector<int> sh = digit_shifts(jbits, ibits);
+  std::vector<int> sh, wd;
+  digit_plan(jbits, ibits, sh, wd);
   DevBuf tmp;
   tmp.alloc(radix_tmp_bytes(cnt));
   uint64_t *kb[2] = {a.as<uint64_t>(), b.as<uint64_t>()};
-  radix_sort_u64(kb, nullptr, cnt, sh.data(), (int)sh.size(), tmp.p, s);
+  radix_sort_u64(kb, nullptr, cnt, sh.data(), (int)sh.size(), tmp.p, s, nullptr, wd.data());
 }
 
 // Single batch: symmetric join of all work units into device memory.

@@ -89,15 +89,17 @@ void exclusive_scan_u64(const uint64_t *in, uint64_t *out, uint64_t n,
                         uint64_t *d_total, void *tmp, hipStream_t s);
 
 // Stable LSD radix sort of 64-bit keys (optionally with 32-bit values) over
-// the bit ranges listed in `shifts` (8-bit digits at each shift).  Sorted
-// output ends in keys[0]/vals[0]; keys[1]/vals[1] are the ping-pong buffers.
+// the bit ranges listed in `shifts`: digits of widths[p] bits (1..8; 8 when
+// widths is null) at each shift.  Sorted output ends in keys[0]/vals[0];
+// keys[1]/vals[1] are the ping-pong buffers.
 // With d_count non-null, n is the capacity that sizes the launches and only
 // the first min(*d_count, n) keys are sorted (for captured graphs, where
 // the count is known on the device only).
 size_t radix_tmp_bytes(uint64_t n);
 void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n,
                     const int *shifts, int n_passes, void *tmp, hipStream_t s,
-                    const unsigned long long *d_count = nullptr);
+                    const unsigned long long *d_count = nullptr,
+                    const int *widths = nullptr);
 void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v, hipStream_t s);
 
 // out[i] = i * stride; widen u32 -> u64; narrow u64 -> u32 (low half).

@@ -133,8 +133,11 @@ void scan_impl(const T *in, T *out, uint64_t n, T *d_total, char *tmp, hipStream
 // ---------------------------------------------------------------------------
 // Radix sort: 8-bit digits, 4096 keys per workgroup (4 waves x 16 rounds of
 // 64 consecutive keys).  Ranks inside a workgroup are found with the wave
-// "multisplit": eight ballots give each lane the mask of lanes holding the
-// same digit, so equal digits keep their input order (stable).
+// "multisplit": one ballot per digit bit gives each lane the mask of lanes
+// holding the same digit, so equal digits keep their input order (stable).
+// Digits are BITS <= 8 wide; narrower digits with the same number of passes
+// give longer runs of equal digits per tile (better coalesced writes) and
+// fewer ballots.
 // ---------------------------------------------------------------------------
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
@@ -146,6 +149,7 @@ __device__ __forceinline__ uint64_t live_count(uint64_t n, const unsigned long l
   return d_count ? (*d_count < n ? (uint64_t)*d_count : n) : n;
 }
 
+template <int BITS>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys,
                                                     uint64_t n_cap, int shift,
                                                     uint64_t *__restrict__ hist,
@@ -162,12 +166,12 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
   for (int r = 0; r < kRsRounds; ++r) {
     uint64_t idx = base + (uint64_t)r * kBlock + threadIdx.x;
     if (idx < n) {
-      uint32_t dg = (uint32_t)(keys[idx] >> shift) & (kRadixBins - 1);
+      uint32_t dg = (uint32_t)(keys[idx] >> shift) & ((1u << BITS) - 1u);
       atomicAdd(&cnt[w][dg], 1u);
     }
   }
   __syncthreads();
-  for (int dg = threadIdx.x; dg < kRadixBins; dg += kBlock) {
+  for (int dg = threadIdx.x; dg < (1 << BITS); dg += kBlock) {
     uint32_t t = 0;
 #pragma unroll
     for (int i = 0; i < kWavesPerBlock; ++i) t += cnt[i][dg];
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
   }
 }
 
-template <bool kVals>
+template <bool kVals, int BITS>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n_cap, int shift,
@@ -206,10 +210,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     const bool valid = idx < n;
     key[r] = valid ? kin[idx] : 0ull;
     if (kVals) val[r] = valid ? vin[idx] : 0u;
-    const uint32_t dg = (uint32_t)(key[r] >> shift) & (kRadixBins - 1);
+    const uint32_t dg = (uint32_t)(key[r] >> shift) & ((1u << BITS) - 1u);
     uint64_t peers = ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (dg >> b) & 1u;
       const uint64_t m = ballot(bit);
       peers &= bit ? m : ~m;
@@ -238,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     uint32_t total;
     const uint32_t ex = block_exclusive_scan<uint32_t>(sum, &total);
     dbase[dg] = ex;
-    gbase[dg] = offs[(uint64_t)dg * nblocks + blockIdx.x];
+    if (dg < (1u << BITS)) gbase[dg] = offs[(uint64_t)dg * nblocks + blockIdx.x];
   }
   __syncthreads();
   // 3. place the keys digit-major in LDS
@@ -246,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   for (int r = 0; r < kRsRounds; ++r) {
     const uint64_t idx = base + (uint64_t)r * kWave + l;
     if (idx < n) {
-      const uint32_t dg = (uint32_t)(key[r] >> shift) & (kRadixBins - 1);
+      const uint32_t dg = (uint32_t)(key[r] >> shift) & ((1u << BITS) - 1u);
       const uint32_t lp = dbase[dg] + woff[w][dg] + rank[r];
       tkey[lp] = key[r];
       if (kVals) tval[lp] = val[r];
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
                  : (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
   for (uint32_t i = threadIdx.x; i < valid_keys; i += kBlock) {
     const uint64_t k = tkey[i];
-    const uint32_t dg = (uint32_t)(k >> shift) & (kRadixBins - 1);
+    const uint32_t dg = (uint32_t)(k >> shift) & ((1u << BITS) - 1u);
     const uint64_t pos = gbase[dg] + (i - dbase[dg]);
     kout[pos] = k;
     if (kVals) vout[pos] = tval[i];
@@ -338,8 +342,29 @@ void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v
   SJ_HIP(hipGetLastError());
 }
 
+// One pass over the digit of BITS bits at shift sh.
+template <int BITS>
+void rs_pass(uint64_t *kin, uint32_t *vin, uint64_t *kout, uint32_t *vout, uint64_t n, int sh,
+             uint64_t *hist, uint32_t nb, char *scan_tmp, hipStream_t s,
+             const unsigned long long *d_count) {
+  hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(nb), dim3(kBlock), 0, s, kin, n, sh, hist, nb,
+                     d_count);
+  SJ_HIP(hipGetLastError());
+  exclusive_scan_u64(hist, hist, (uint64_t)(1u << BITS) * nb, nullptr, scan_tmp, s);
+  if (vin) {
+    hipLaunchKernelGGL((k_rs_scatter<true, BITS>), dim3(nb), dim3(kBlock), 0, s, kin, vin, kout,
+                       vout, n, sh, hist, nb, d_count);
+  } else {
+    hipLaunchKernelGGL((k_rs_scatter<false, BITS>), dim3(nb), dim3(kBlock), 0, s, kin,
+                       (const uint32_t *)nullptr, kout, (uint32_t *)nullptr, n, sh, hist, nb,
+                       d_count);
+  }
+  SJ_HIP(hipGetLastError());
+}
+
 void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int *shifts,
-                    int n_passes, void *tmp, hipStream_t s, const unsigned long long *d_count) {
+                    int n_passes, void *tmp, hipStream_t s, const unsigned long long *d_count,
+                    const int *widths) {
   if (n == 0 || (n == 1 && !d_count) || n_passes == 0) return;
   if ((n + kRsTile - 1) / kRsTile > 0x7fffffffull) fail(SJ_ERR_INVALID_ARG, "radix sort too large");
   const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
@@ -349,19 +374,20 @@ void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int 
   int cur = 0;
   for (int p = 0; p < n_passes; ++p) {
     const int sh = shifts[p];
-    hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(kBlock), 0, s, keys[cur], n, sh, hist, nb,
-                       d_count);
-    SJ_HIP(hipGetLastError());
-    exclusive_scan_u64(hist, hist, nhist, nullptr, scan_tmp, s);
-    if (vals) {
-      hipLaunchKernelGGL(k_rs_scatter<true>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
-                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, sh, hist, nb, d_count);
-    } else {
-      hipLaunchKernelGGL(k_rs_scatter<false>, dim3(nb), dim3(kBlock), 0, s, keys[cur],
-                         (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n,
-                         sh, hist, nb, d_count);
+    const int w = widths ? widths[p] : kRadixBits;
+    uint64_t *ki = keys[cur], *ko = keys[cur ^ 1];
+    uint32_t *vi = vals ? vals[cur] : nullptr, *vo = vals ? vals[cur ^ 1] : nullptr;
+    switch (w) {
+      case 1: rs_pass<1>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 2: rs_pass<2>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 3: rs_pass<3>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 4: rs_pass<4>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 5: rs_pass<5>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 6: rs_pass<6>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 7: rs_pass<7>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 8: rs_pass<8>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      default: fail(SJ_ERR_INVALID_ARG, "radix digit width must be 1..8");
     }
-    SJ_HIP(hipGetLastError());
     cur ^= 1;
   }
   if (cur == 1) {

@@ -148,12 +148,26 @@ inline uint32_t bits_for(uint64_t v) {  // bits needed to represent v
   return b;
 }
 
-inline std::vector<int> digit_shifts(uint32_t lo_bits, uint32_t hi_bits) {
-  // 8-bit digits over bits [0, lo_bits) and [32, 32 + hi_bits)
-  std::vector<int> s;
-  for (uint32_t b = 0; b < lo_bits; b += 8) s.push_back((int)b);
-  for (uint32_t b = 0; b < hi_bits; b += 8) s.push_back(32 + (int)b);
-  return s;
+// Radix digits over bits [0, lo_bits) and [32, 32 + hi_bits): each field in
+// as few passes as 8-bit digits need, its bits spread evenly over them
+// (21 bits: 7 + 7 + 7), so runs of equal digits are as long as possible.
+inline void digit_plan(uint32_t lo_bits, uint32_t hi_bits, std::vector<int> &shifts,
+                       std::vector<int> &widths) {
+  shifts.clear();
+  widths.clear();
+  const uint32_t field[2] = {lo_bits, hi_bits}, base[2] = {0, 32};
+  for (int f = 0; f < 2; ++f) {
+    const uint32_t b = field[f];
+    if (!b) continue;
+    const uint32_t p = (b + 7) / 8;
+    uint32_t at = base[f];
+    for (uint32_t i = 0; i < p; ++i) {
+      const uint32_t w = b / p + (i < b % p ? 1u : 0u);
+      shifts.push_back((int)at);
+      widths.push_back((int)w);
+      at += w;
+    }
+  }
 }
 
 inline bool is_device_pointer(const void *ptr) {
