@@ -142,14 +142,19 @@ void scan_impl(const T *in, T *out, uint64_t n, T *d_total, char *tmp, hipStream
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kRsRounds = 16;
-constexpr int kRsTile = kBlock * kRsRounds;  // 4096
+constexpr int kRsTile = kBlock * kRsRounds;  // 4096 keys per workgroup with values
+// rounds of a keys-only sort (no value array in LDS leaves room for a larger tile)
+#ifndef SJ_RS_ROUNDS_KEYS
+#define SJ_RS_ROUNDS_KEYS 16
+#endif
+constexpr int kRsRoundsKeys = SJ_RS_ROUNDS_KEYS;
 
 // When d_count is non-null only the first min(*d_count, n) keys take part.
 __device__ __forceinline__ uint64_t live_count(uint64_t n, const unsigned long long *d_count) {
   return d_count ? (*d_count < n ? (uint64_t)*d_count : n) : n;
 }
 
-template <int BITS>
+template <int BITS, int R>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__ keys,
                                                     uint64_t n_cap, int shift,
                                                     uint64_t *__restrict__ hist,
@@ -161,9 +166,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
   for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock)
     (&cnt[0][0])[i] = 0;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+  const uint64_t base = (uint64_t)blockIdx.x * (kBlock * R);
 #pragma unroll 4
-  for (int r = 0; r < kRsRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     uint64_t idx = base + (uint64_t)r * kBlock + threadIdx.x;
     if (idx < n) {
       uint32_t dg = (uint32_t)(keys[idx] >> shift) & ((1u << BITS) - 1u);
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint64_t *__restrict__
   }
 }
 
-template <bool kVals, int BITS>
+template <bool kVals, int BITS, int R>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t n_cap, int shift,
@@ -189,8 +194,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   __shared__ uint32_t woff[kWavesPerBlock][kRadixBins];
   __shared__ uint32_t dbase[kRadixBins];   // first slot of each digit in the tile
   __shared__ uint64_t gbase[kRadixBins];   // first global slot of each digit
-  __shared__ uint64_t tkey[kRsTile];
-  __shared__ uint32_t tval[kVals ? kRsTile : 1];
+  constexpr int kTile = kBlock * R;
+  __shared__ uint64_t tkey[kTile];
+  __shared__ uint32_t tval[kVals ? kTile : 1];
   const int w = threadIdx.x / kWave;
   const uint32_t l = lane_id();
   for (int i = threadIdx.x; i < kWavesPerBlock * kRadixBins; i += kBlock)
@@ -199,13 +205,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
 
   // 1. rank every key among equal digits of its wave, in input order
   const uint64_t n = live_count(n_cap, d_count);
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
-  const uint64_t base = tile0 + (uint64_t)w * (kRsTile / kWavesPerBlock);
-  uint64_t key[kRsRounds];
-  uint32_t val[kRsRounds];
-  uint32_t rank[kRsRounds];
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kTile;
+  const uint64_t base = tile0 + (uint64_t)w * (kTile / kWavesPerBlock);
+  uint64_t key[R];
+  uint32_t val[R];
+  uint32_t rank[R];
 #pragma unroll
-  for (int r = 0; r < kRsRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const uint64_t idx = base + (uint64_t)r * kWave + l;
     const bool valid = idx < n;
     key[r] = valid ? kin[idx] : 0ull;
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   __syncthreads();
   // 3. place the keys digit-major in LDS
 #pragma unroll
-  for (int r = 0; r < kRsRounds; ++r) {
+  for (int r = 0; r < R; ++r) {
     const uint64_t idx = base + (uint64_t)r * kWave + l;
     if (idx < n) {
       const uint32_t dg = (uint32_t)(key[r] >> shift) & ((1u << BITS) - 1u);
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(
   //    consecutive slots of each digit's run
   const uint32_t valid_keys =
       tile0 >= n ? 0u
-                 : (uint32_t)((n - tile0) < (uint64_t)kRsTile ? (n - tile0) : (uint64_t)kRsTile);
+                 : (uint32_t)((n - tile0) < (uint64_t)kTile ? (n - tile0) : (uint64_t)kTile);
   for (uint32_t i = threadIdx.x; i < valid_keys; i += kBlock) {
     const uint64_t k = tkey[i];
     const uint32_t dg = (uint32_t)(k >> shift) & ((1u << BITS) - 1u);
@@ -342,22 +348,29 @@ void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v
   SJ_HIP(hipGetLastError());
 }
 
-// One pass over the digit of BITS bits at shift sh.
+// One pass over the digit of BITS bits at shift sh: tiles of 16 rounds of
+// 256 keys with values, kRsRoundsKeys rounds without.
 template <int BITS>
 void rs_pass(uint64_t *kin, uint32_t *vin, uint64_t *kout, uint32_t *vout, uint64_t n, int sh,
-             uint64_t *hist, uint32_t nb, char *scan_tmp, hipStream_t s,
-             const unsigned long long *d_count) {
-  hipLaunchKernelGGL(k_rs_hist<BITS>, dim3(nb), dim3(kBlock), 0, s, kin, n, sh, hist, nb,
-                     d_count);
-  SJ_HIP(hipGetLastError());
-  exclusive_scan_u64(hist, hist, (uint64_t)(1u << BITS) * nb, nullptr, scan_tmp, s);
+             uint64_t *hist, char *scan_tmp, hipStream_t s, const unsigned long long *d_count) {
   if (vin) {
-    hipLaunchKernelGGL((k_rs_scatter<true, BITS>), dim3(nb), dim3(kBlock), 0, s, kin, vin, kout,
-                       vout, n, sh, hist, nb, d_count);
+    const uint32_t nb = (uint32_t)((n + kRsTile - 1) / kRsTile);
+    hipLaunchKernelGGL((k_rs_hist<BITS, kRsRounds>), dim3(nb), dim3(kBlock), 0, s, kin, n, sh,
+                       hist, nb, d_count);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan_u64(hist, hist, (uint64_t)(1u << BITS) * nb, nullptr, scan_tmp, s);
+    hipLaunchKernelGGL((k_rs_scatter<true, BITS, kRsRounds>), dim3(nb), dim3(kBlock), 0, s, kin,
+                       vin, kout, vout, n, sh, hist, nb, d_count);
   } else {
-    hipLaunchKernelGGL((k_rs_scatter<false, BITS>), dim3(nb), dim3(kBlock), 0, s, kin,
-                       (const uint32_t *)nullptr, kout, (uint32_t *)nullptr, n, sh, hist, nb,
-                       d_count);
+    constexpr uint64_t kT = (uint64_t)kBlock * kRsRoundsKeys;
+    const uint32_t nb = (uint32_t)((n + kT - 1) / kT);
+    hipLaunchKernelGGL((k_rs_hist<BITS, kRsRoundsKeys>), dim3(nb), dim3(kBlock), 0, s, kin, n,
+                       sh, hist, nb, d_count);
+    SJ_HIP(hipGetLastError());
+    exclusive_scan_u64(hist, hist, (uint64_t)(1u << BITS) * nb, nullptr, scan_tmp, s);
+    hipLaunchKernelGGL((k_rs_scatter<false, BITS, kRsRoundsKeys>), dim3(nb), dim3(kBlock), 0, s,
+                       kin, (const uint32_t *)nullptr, kout, (uint32_t *)nullptr, n, sh, hist,
+                       nb, d_count);
   }
   SJ_HIP(hipGetLastError());
 }
@@ -378,14 +391,14 @@ void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n, const int 
     uint64_t *ki = keys[cur], *ko = keys[cur ^ 1];
     uint32_t *vi = vals ? vals[cur] : nullptr, *vo = vals ? vals[cur ^ 1] : nullptr;
     switch (w) {
-      case 1: rs_pass<1>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 2: rs_pass<2>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 3: rs_pass<3>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 4: rs_pass<4>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 5: rs_pass<5>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 6: rs_pass<6>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 7: rs_pass<7>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
-      case 8: rs_pass<8>(ki, vi, ko, vo, n, sh, hist, nb, scan_tmp, s, d_count); break;
+      case 1: rs_pass<1>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 2: rs_pass<2>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 3: rs_pass<3>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 4: rs_pass<4>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 5: rs_pass<5>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 6: rs_pass<6>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 7: rs_pass<7>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
+      case 8: rs_pass<8>(ki, vi, ko, vo, n, sh, hist, scan_tmp, s, d_count); break;
       default: fail(SJ_ERR_INVALID_ARG, "radix digit width must be 1..8");
     }
     cur ^= 1;
