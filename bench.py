@@ -448,6 +448,13 @@ def main():
             else:
                 # algorithmic: one d-long dot product per unordered pair
                 flops_total += 2.0 * d * (info["candidates"] + n) / 2.0
+                # the matrix-core form's floor: its MFMA time, or one vector
+                # lane operation (the threshold compare) per pair, whichever
+                # is longer
+                npair = (info["candidates"] + n) / 2.0
+                floor_s = max(2.0 * d * npair / (PEAK_MFMA_16BIT_TFLOPS * 1e12),
+                              npair / (PEAK_FP32_VALU_TFLOPS * 1e12 / 2.0))
+                row["ms_floor_mfma_or_compare"] = round(floor_s * 1e3, 3)
             time_total += ms / 1e3
             per_eps[t] = row
         return per_eps, flops_total, time_total
@@ -498,7 +505,9 @@ def main():
         cper, cfl, ctime = per_eps_table(crecs, prec == "fp32")
         cach = cfl / ctime / 1e12 if ctime > 0 else 0.0
         cpeak = PEAK_FP32_VALU_TFLOPS if prec == "fp32" else PEAK_MFMA_16BIT_TFLOPS
+        cfloor = sum(r.get("ms_floor_mfma_or_compare", 0.0) for r in cper.values())
         compare[prec] = {"value": ccand / celapsed, "ms_per_step": celapsed * 1e3 / a.steps,
+                         "kernel_frac_of_floor": (cfloor / 1e3 / ctime) if ctime > 0 else 0.0,
                          "speedup_vs_headline": (ccand / celapsed) / value,
                          "result_pairs_per_s": sum(r[2] for r in crecs) / celapsed,
                          "per_epsilon": cper,
