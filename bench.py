@@ -5,6 +5,11 @@ sort of the result in device memory) for every epsilon of the workload's
 sweep, on synthetic data already resident in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+Other lines (not the headline): --workload batched_256 (many joins in one
+launch), --query-sets N (the general join of N entity-partitioned query
+sets), --k-sweep (index-search against distance work per k), --host-io
+(PCIe-inclusive), --sortidu (SORTIDU on), --precision / --compare (filters).
 """
 from __future__ import annotations
 
