@@ -264,6 +264,28 @@ uint64_t build_neighbors(sj_index &ix, const sj_index &E, NbrParams np, BuildTmp
   return h_c;
 }
 
+// Share of the lane work of the FP32 units of tq queries that falls on
+// live query slots: candidates C over the sum, over the query cells, of the
+// cell's slots (its query count rounded up to tq) times its candidates
+// (cand_sum, per cell, from build_neighbors).  Low when much of the work is
+// in cells holding far fewer queries than a unit has slots.
+double live_slot_share(const sj_index &ix, const uint64_t *cand_sum, uint32_t tq, hipStream_t s) {
+  const uint64_t nc = ix.ncell;
+  if (!nc || !ix.candidates) return 1.0;
+  ScratchScope scope;  // the read-back below synchronises the stream
+  TmpBuf w, tot, scan;
+  w.alloc(nc * 8);
+  tot.alloc(64);
+  scan.alloc(scan_tmp_bytes(nc) + 64);
+  launch_cell_slot_work(nc, ix.cell_start.as<uint32_t>(), cand_sum, tq, w.as<uint64_t>(), s);
+  exclusive_scan_u64(w.as<uint64_t>(), w.as<uint64_t>(), nc, tot.as<uint64_t>(), scan.p, s);
+  uint64_t h = 0;
+  SJ_HIP(hipMemcpyAsync(&h, tot.p, 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  return h ? (double)ix.candidates / (double)h : 1.0;
+}
+constexpr double kLiveSlotShareMin = 0.75;  // below it, units of one query per lane
+
 // Candidate runs (sym: only cells B >= A) into off/runs.
 uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &t, hipStream_t s) {
   const uint64_t nc = ix.ncell;
@@ -701,7 +723,13 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   ix.n_runs_sym = build_runs(ix, 1, ix.run_off_sym, ix.runs_sym, t, s);
   ix.n_runs_full = build_runs(ix, 0, ix.run_off_full, ix.runs_full, t, s);
   if (ix.opt.precision == SJ_PREC_FP32) choose_fp32_form(ix, s);
-  ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form);
+  // one query per lane when units of the class's width would spend more
+  // than a quarter of their lane work on idle query slots (many small cells)
+  ix.small_cells =
+      live_slot_share(ix, t.cand_sum.as<uint64_t>(),
+                      64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form, false), s) <
+      kLiveSlotShareMin;
+  ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form, ix.small_cells);
   uint64_t ev = 0;
   DevBuf probe, probe_r;
   const bool su = ix.opt.sortidu != 0;  // units from per-block SORTIDU ranges
@@ -870,6 +898,11 @@ void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream
   }
   if (q.ncell == 0) return finish();
   q.candidates = build_neighbors(q, E, g.np, t, s, true);
+  q.small_cells =  // as for an index, over the query cells
+      live_slot_share(q, t.cand_sum.as<uint64_t>(),
+                      64u * (uint32_t)fp32_rq_for(q.dp, q.norm_form, false), s) <
+      kLiveSlotShareMin;
+  q.tq = 64u * (uint32_t)fp32_rq_for(q.dp, q.norm_form, q.small_cells);
   q.n_runs_full = build_runs(q, 0, q.run_off_full, q.runs_full, t, s);
   if (q.norm_form) {  // the queries' table of the norm form (E holds the candidates')
     const NormParams np = norm_params(q);
@@ -979,7 +1012,7 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
   a.capacity = cap;
   a.cursor = ix.counters.as<unsigned long long>();
   a.rechecks = ix.counters.as<unsigned long long>() + 1;
-  a.rq = fp32_rq_for(ix.dp, ix.norm_form);
+  a.rq = fp32_rq_for(ix.dp, ix.norm_form, ix.small_cells);
   a.norm = ix.norm_form ? 1 : 0;
   a.QA = ix.norm_qa.as<float>();
   a.CR = E.norm_cr.as<float>();

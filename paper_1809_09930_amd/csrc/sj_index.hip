@@ -603,6 +603,17 @@ __global__ __launch_bounds__(kBlock) void k_gather_wu(const WorkUnit *__restrict
   dst[i] = src[(uint32_t)keys[i]];
 }
 
+// out[A] = (query slots of cell A's units of tq queries) * cand_sum[A]: the
+// lane work of A's units, idle slots included
+__global__ void k_cell_slot_work(uint64_t ncell, const uint32_t *__restrict__ cell_start,
+                                 const uint64_t *__restrict__ cand_sum, uint32_t tq,
+                                 uint64_t *__restrict__ out) {
+  const uint64_t A = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (A >= ncell) return;
+  const uint64_t m = cell_start[A + 1] - cell_start[A];
+  out[A] = (m + tq - 1) / tq * tq * cand_sum[A];
+}
+
 __global__ void k_cell_products(uint64_t ncell, const uint32_t *__restrict__ cell_start,
                                 const uint64_t *__restrict__ cand_sum, uint64_t *__restrict__ out) {
   const uint64_t A = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -786,6 +797,14 @@ void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint
   if (!ncell) return;
   hipLaunchKernelGGL(k_cell_products, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, ncell,
                      cell_start, cand_sum, out);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_cell_slot_work(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
+                           uint32_t tq, uint64_t *out, hipStream_t s) {
+  if (!ncell) return;
+  hipLaunchKernelGGL(k_cell_slot_work, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, ncell,
+                     cell_start, cand_sum, tq, out);
   SJ_HIP(hipGetLastError());
 }
 

@@ -111,6 +111,10 @@ void launch_gather_wu(const WorkUnit *src, const uint64_t *keys, uint64_t n, Wor
                       hipStream_t s);
 void launch_cell_products(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
                           uint64_t *out, hipStream_t s);
+// out[A] = ceil(|A| / tq) * tq * cand_sum[A] (lane work of A's units of tq
+// query slots, idle slots included)
+void launch_cell_slot_work(uint64_t ncell, const uint32_t *cell_start, const uint64_t *cand_sum,
+                           uint32_t tq, uint64_t *out, hipStream_t s);
 
 // counts[i] += number of keys (i << 32 | .) among the sorted keys
 // [0, count) (counts zeroed by the caller; chunks may be added one by one).

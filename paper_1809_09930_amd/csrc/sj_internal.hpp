@@ -135,13 +135,14 @@ struct JoinLaunch {
   uint64_t capacity;
   unsigned long long *cursor;    // pairs produced (may exceed capacity)
   unsigned long long *rechecks;  // FP64 rechecks performed
-  int rq;                   // queries per lane (1, 2 or 4); units hold 64*rq queries
+  int rq;                   // queries per lane (1, 2 or 4; fp32_rq_for); units hold 64*rq queries
   int norm;                 // 1: norm form with the tables QA / CR
   const float *QA, *CR;     // [.][norm_table_row(dp)] query (of Xq) / candidate (of X) tables
 };
 
 // Queries per lane the FP32 kernel uses for padded dimension dp.
-int fp32_rq_for(uint32_t dp, bool norm);
+// (1 when small_cells: the units of small cells use one query per lane.)
+int fp32_rq_for(uint32_t dp, bool norm, bool small_cells);
 // Floats per point in each norm-form table.
 int norm_table_row(uint32_t dp);
 // Builds the norm-form tables of the cell-ordered rows X ([n][dp]) for the

@@ -598,12 +598,8 @@ __global__ __launch_bounds__(kBlock) void k_unpack(const uint64_t *__restrict__ 
   }
 }
 
-template <int DP, bool kNorm, bool kSC>
-void launch_form(const JoinLaunch &a, hipStream_t s) {
-  const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (grid == 0) return;
-  constexpr int kRq = kNorm ? (DP <= 24 ? SJ_NORM_RQ_SMALL : (DP <= 64 ? SJ_NORM_RQ_MID : 1))
-                            : (DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1));
+template <int DP, int kRq, bool kNorm, bool kSC>
+void launch_rq(const JoinLaunch &a, uint32_t grid, hipStream_t s) {
   if (a.count_only)
     hipLaunchKernelGGL((k_count_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
                        a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d,
@@ -615,6 +611,20 @@ void launch_form(const JoinLaunch &a, hipStream_t s) {
                        a.lo, a.hi, a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks,
                        a.QA, a.CR);
   SJ_HIP(hipGetLastError());
+}
+
+// Queries per lane: the class default, or one when the cells are small
+// (a.rq == 1: a cell's queries would leave most lanes of a wider unit idle).
+template <int DP, bool kNorm, bool kSC>
+void launch_form(const JoinLaunch &a, hipStream_t s) {
+  const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (grid == 0) return;
+  constexpr int kRq = kNorm ? (DP <= 24 ? SJ_NORM_RQ_SMALL : (DP <= 64 ? SJ_NORM_RQ_MID : 1))
+                            : (DP <= 24 ? SJ_FP32_RQ_SMALL : (DP <= 64 ? SJ_FP32_RQ_MID : 1));
+  if (kRq != 1 && a.rq == 1)
+    launch_rq<DP, 1, kNorm, kSC>(a, grid, s);
+  else
+    launch_rq<DP, kRq, kNorm, kSC>(a, grid, s);
 }
 
 template <int DP>
@@ -646,7 +656,8 @@ uint32_t padded_dim(uint32_t d) {
   return (d + 15) / 16 * 16;
 }
 
-int fp32_rq_for(uint32_t dp, bool norm) {
+int fp32_rq_for(uint32_t dp, bool norm, bool small_cells) {
+  if (small_cells) return 1;
   if (norm) return dp <= 24 ? SJ_NORM_RQ_SMALL : (dp <= 64 ? SJ_NORM_RQ_MID : 1);
   return dp <= 24 ? SJ_FP32_RQ_SMALL : (dp <= 64 ? SJ_FP32_RQ_MID : 1);
 }

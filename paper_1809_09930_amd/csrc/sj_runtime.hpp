@@ -222,6 +222,7 @@ struct sj_index {
   const sj_index *entries = nullptr;
   std::atomic<uint32_t> refs{1};  // the caller's handle plus the query handles built on it
   bool batch_job = false;  // built for the batched path: no single-join work units
+  bool small_cells = false;  // FP32 units of 64 queries (most lane work in small cells)
   uint64_t n_near = 0;    // points in cells (a query handle drops far queries)
   sj::Geometry geom{};    // grid of the build (k, key and neighbour parameters)
   std::vector<float> mfma_centre;  // matrix-core centring of the indexed set
