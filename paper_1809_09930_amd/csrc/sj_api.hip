@@ -104,11 +104,6 @@ constexpr double kWidthSlack = 1.0 + 1.0 / (1 << 20);  // cell side = eps * (1 +
 #define SJ_WU_BY_STRETCH 1
 #endif
 constexpr bool kWuByStretch = SJ_WU_BY_STRETCH != 0;  // join work units in stretch order
-// mean points per cell below which the matrix-core single join uses per-wave units
-#ifndef SJ_WAVE_UNITS_BELOW
-#define SJ_WAVE_UNITS_BELOW 128
-#endif
-constexpr double kWaveUnitsBelow = SJ_WAVE_UNITS_BELOW;
 
 // Fine (Morton) ordering inside cells: dimensions and bits per dimension.
 #ifndef SJ_FINE_DIMS
@@ -749,10 +744,12 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     mfma_prepare(ix, s);
     ix.tq_m = 32u * (uint32_t)mfma_qb(ix.kp);         // per wave (batched kernel)
     ix.tc_m = choose_tc(ev, ix.tq_m);
-    // single join: workgroup units, or per-wave units when the cells are
-    // much smaller than a workgroup's query slots
+    // single join: workgroup units, or per-wave units when more than a
+    // quarter of the workgroup units' lane work would fall on idle query
+    // slots (the work-weighted test of the FP32 join)
     const uint32_t tq_wg = mfma_wg_queries(ix.kp);
-    ix.mfma_per_wave = ix.ncell > 0 && (double)ix.n / (double)ix.ncell < kWaveUnitsBelow;
+    ix.mfma_per_wave =
+        live_slot_share(ix, t.cand_sum.as<uint64_t>(), tq_wg, s) < kLiveSlotShareMin;
     ix.tq_single = ix.mfma_per_wave ? mfma_wave_queries() : tq_wg;
     ix.tc_single = ix.mfma_per_wave ? choose_tc(ev, ix.tq_single)
                                     : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
@@ -947,7 +944,8 @@ void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream
                            E.mfma_max.as<unsigned long long>(), q.thi.as<float>(),
                            q.tlo.as<float>(), s);
     const uint32_t tq_wg = mfma_wg_queries(q.kp);
-    q.mfma_per_wave = (double)q.n_near / (double)q.ncell < kWaveUnitsBelow;
+    q.mfma_per_wave =
+        live_slot_share(q, t.cand_sum.as<uint64_t>(), tq_wg, s) < kLiveSlotShareMin;
     q.tq_single = q.mfma_per_wave ? mfma_wave_queries() : tq_wg;
     q.tc_single = q.mfma_per_wave ? choose_tc(ev, q.tq_single)
                                   : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
