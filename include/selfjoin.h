@@ -101,6 +101,15 @@ typedef struct sj_options {
  *               stays narrow against eps^2. */
 enum sj_fp32_form { SJ_FP32_AUTO = 0, SJ_FP32_DIFFERENCE = 1, SJ_FP32_NORM = 2 };
 
+/* Work units of the single-join distance kernel (sj_info.units), chosen at
+ * build from the cells' sizes; either gives the same result.
+ *   CELL:        a unit holds the queries of one cell (FP32: 64 lanes with up
+ *                to 4 queries each; matrix cores: a workgroup of 256 queries).
+ *   SMALL_CELLS: taken when more than a quarter of the lane work of CELL units
+ *                would fall on idle query slots (FP32: one query per lane;
+ *                matrix cores: one wave of 32 queries). */
+enum sj_units { SJ_UNITS_CELL = 1, SJ_UNITS_SMALL_CELLS = 2 };
+
 /* Fills *opts with the defaults: k = 0 (auto, 4..8), reorder = 1,
  * shortc = 1, precision = SJ_PREC_FP32, batch_pairs = 0, min_batches = 0,
  * mem_budget = 0, fp32_form = SJ_FP32_AUTO, sortidu = 0.  Callers built against an
@@ -169,6 +178,7 @@ typedef struct sj_info {
     float    ms_run;          /* device time of the whole last run */
     uint32_t join_launches;   /* launches of the distance kernel in the last run (reruns after an undersized buffer included) */
     uint32_t fp32_form;       /* form of the FP32 filter (enum sj_fp32_form; 0 on the matrix-core path) */
+    uint32_t units;           /* work units of the distance kernel (enum sj_units; set by the build, 0 for an empty input) */
 } sj_info;
 
 /*

@@ -725,6 +725,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
                       64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form, false), s) <
       kLiveSlotShareMin;
   ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form, ix.small_cells);
+  ix.info.units = ix.small_cells ? SJ_UNITS_SMALL_CELLS : SJ_UNITS_CELL;
   uint64_t ev = 0;
   DevBuf probe, probe_r;
   const bool su = ix.opt.sortidu != 0;  // units from per-block SORTIDU ranges
@@ -750,6 +751,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     const uint32_t tq_wg = mfma_wg_queries(ix.kp);
     ix.mfma_per_wave =
         live_slot_share(ix, t.cand_sum.as<uint64_t>(), tq_wg, s) < kLiveSlotShareMin;
+    ix.info.units = ix.mfma_per_wave ? SJ_UNITS_SMALL_CELLS : SJ_UNITS_CELL;
     ix.tq_single = ix.mfma_per_wave ? mfma_wave_queries() : tq_wg;
     ix.tc_single = ix.mfma_per_wave ? choose_tc(ev, ix.tq_single)
                                     : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);
@@ -900,6 +902,7 @@ void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream
                       64u * (uint32_t)fp32_rq_for(q.dp, q.norm_form, false), s) <
       kLiveSlotShareMin;
   q.tq = 64u * (uint32_t)fp32_rq_for(q.dp, q.norm_form, q.small_cells);
+  q.info.units = q.small_cells ? SJ_UNITS_SMALL_CELLS : SJ_UNITS_CELL;
   q.n_runs_full = build_runs(q, 0, q.run_off_full, q.runs_full, t, s);
   if (q.norm_form) {  // the queries' table of the norm form (E holds the candidates')
     const NormParams np = norm_params(q);
@@ -946,6 +949,7 @@ void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream
     const uint32_t tq_wg = mfma_wg_queries(q.kp);
     q.mfma_per_wave =
         live_slot_share(q, t.cand_sum.as<uint64_t>(), tq_wg, s) < kLiveSlotShareMin;
+    q.info.units = q.mfma_per_wave ? SJ_UNITS_SMALL_CELLS : SJ_UNITS_CELL;
     q.tq_single = q.mfma_per_wave ? mfma_wave_queries() : tq_wg;
     q.tc_single = q.mfma_per_wave ? choose_tc(ev, q.tq_single)
                                   : std::max<uint32_t>(1024, choose_tc(ev, tq_wg) * 4);

@@ -30,6 +30,8 @@ SJ_FP32_AUTO = 0
 SJ_FP32_DIFFERENCE = 1
 SJ_FP32_NORM = 2
 FP32_FORMS = {"auto": SJ_FP32_AUTO, "difference": SJ_FP32_DIFFERENCE, "norm": SJ_FP32_NORM}
+SJ_UNITS_CELL = 1
+SJ_UNITS_SMALL_CELLS = 2
 
 EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_build_query",
             "selfjoin_run",
@@ -75,7 +77,8 @@ class SjInfo(ctypes.Structure):
                 ("ms_sort", ctypes.c_float),
                 ("ms_run", ctypes.c_float),
                 ("join_launches", ctypes.c_uint32),
-                ("fp32_form", ctypes.c_uint32)]
+                ("fp32_form", ctypes.c_uint32),
+                ("units", ctypes.c_uint32)]
 
 
 class SjJob(ctypes.Structure):

@@ -407,6 +407,30 @@ def test_fp32_form_automatic_choice():
     assert info["fp32_form"] == 1
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_both_unit_kinds_match_oracle(prec):
+    """The build takes units of one cell's queries for large cells and the
+    small-cell units (FP32: one query per lane; matrix cores: one wave) when
+    most lane work of cell units would fall on idle query slots; both kinds
+    give the oracle's result."""
+    kinds = {}
+    # 8 cells of about 500 points, 16 cells of about 250: cell units
+    kinds["d1_large"] = assert_same_as_oracle(datagen.uniform_grid(4000, 1, 41), 0.125,
+                                              precision=prec)["units"]
+    kinds["d2_large"] = assert_same_as_oracle(datagen.uniform_grid(4000, 2, 42), 0.25,
+                                              precision=prec)["units"]
+    # two tight clusters in 16 dimensions, each within eps of itself
+    std = np.full(16, 0.002)
+    C = datagen.gaussian_mixture(3000, 16, 2, std, 43)
+    kinds["d16_clusters"] = assert_same_as_oracle(C, 0.05, precision=prec)["units"]
+    # cells of one or two points: small-cell units
+    for d, seed in ((2, 44), (16, 45)):
+        P = datagen.uniform_grid(3000, d, seed)
+        kinds[f"d{d}_small"] = assert_same_as_oracle(P, calibrated(P, 4), precision=prec)["units"]
+    assert kinds["d1_large"] == kinds["d2_large"] == 1, kinds
+    assert kinds["d2_small"] == kinds["d16_small"] == 2, kinds
+
+
 @pytest.mark.parametrize("opts", [dict(), dict(precision="fp16"), dict(batch_pairs=3000),
                                   dict(min_batches=4, precision="bf16")])
 def test_csr_neighbour_table(opts):
