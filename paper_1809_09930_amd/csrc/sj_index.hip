@@ -241,9 +241,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_write(const uint64_t *__restric
 // search over the non-empty cell ids).  One wave per query cell, 64 offsets
 // per step; the cell-key table is staged in LDS, whole when it fits, else
 // as a fence of every stride-th key that narrows the search to a short
-// stretch of the table in global memory.
+// stretch of the table in global memory.  The searches wait on dependent
+// loads, so a workgroup of 16 waves shares one fence: two of them fill a CU
+// with 32 waves where workgroups of 4 waves would leave it at 8.
 // ---------------------------------------------------------------------------
 constexpr int kFenceMax = 8192;  // 64 KiB of u64 keys in LDS
+constexpr int kNbrBlock = 1024;
+constexpr int kNbrWaves = kNbrBlock / kWave;
 
 __device__ __forceinline__ int64_t find_cell(uint64_t key, const uint64_t *__restrict__ fence,
                                              uint32_t nfence, uint32_t fstride,
@@ -269,33 +273,34 @@ __device__ __forceinline__ int64_t find_cell(uint64_t key, const uint64_t *__res
 
 // Query cells are qkey[0 .. nq) (the table itself in a self-join); the
 // table is cell_key[0 .. ncell) with its cell_start.
-__global__ __launch_bounds__(kBlock) void k_neighbors(
+__global__ __launch_bounds__(kNbrBlock) void k_neighbors(
     int pass, const uint64_t *__restrict__ qkey, uint64_t nq,
     const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ cell_start,
     uint64_t ncell, NbrParams np, uint32_t *__restrict__ nbr_count,
     uint64_t *__restrict__ cand_sum, const uint32_t *__restrict__ nbr_off,
     uint32_t *__restrict__ nbr_cell) {
   __shared__ uint64_t fence[kFenceMax];
-  for (uint32_t i = threadIdx.x; i < np.nfence; i += kBlock)
+  for (uint32_t i = threadIdx.x; i < np.nfence; i += kNbrBlock)
     fence[i] = cell_key[(uint64_t)i * np.fstride];
   __syncthreads();
   const uint32_t l = lane_id();
-  const uint64_t wid = (uint64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-  const uint64_t nw = (uint64_t)gridDim.x * kWavesPerBlock;
+  const uint64_t wid = (uint64_t)blockIdx.x * kNbrWaves + threadIdx.x / kWave;
+  const uint64_t nw = (uint64_t)gridDim.x * kNbrWaves;
   for (uint64_t A = wid; A < nq; A += nw) {
     const uint64_t keyA = qkey[A];
     int64_t cA[kKeyMaxDims];
     for (uint32_t r = 0; r < np.k; ++r) cA[r] = (int64_t)((keyA / np.mult[r]) % np.m[r]);
     uint32_t count = 0, wpos = (pass == 1) ? nbr_off[A] : 0u;
     uint64_t csum = 0;
-    for (uint64_t base = 0; base < np.n_off; base += kWave) {
-      const uint64_t o = base + l;
-      bool ok = o < np.n_off;
+    // n_off = 3^k <= 3^16 < 2^32: the offset digits are taken in 32 bits
+    for (uint32_t base = 0; base < (uint32_t)np.n_off; base += kWave) {
+      const uint32_t o = base + l;
+      bool ok = o < (uint32_t)np.n_off;
       uint64_t keyB = keyA;
-      uint64_t rem = o;
+      uint32_t rem = o;
       for (int r = (int)np.k - 1; r >= 0; --r) {  // dimension 0 is the most significant digit
-        const int64_t delta = (int64_t)(rem % 3) - 1;
-        rem /= 3;
+        const int64_t delta = (int64_t)(rem % 3u) - 1;
+        rem /= 3u;
         const int64_t c = cA[r] + delta;
         ok = ok && c >= 0 && c < (int64_t)np.m[r];
         keyB += (uint64_t)delta * np.mult[r];
@@ -722,8 +727,8 @@ void launch_neighbors(int pass, const uint64_t *qkey, uint64_t nq, const uint64_
                       uint32_t *nbr_cell, hipStream_t s) {
   if (!nq || !ncell) return;
   const uint64_t waves = nq;
-  uint32_t grid = (uint32_t)std::min<uint64_t>((waves + kWavesPerBlock - 1) / kWavesPerBlock, 4096);
-  hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(kBlock), 0, s, pass, qkey, nq, cell_key,
+  uint32_t grid = (uint32_t)std::min<uint64_t>((waves + kNbrWaves - 1) / kNbrWaves, 1024);
+  hipLaunchKernelGGL(k_neighbors, dim3(grid), dim3(kNbrBlock), 0, s, pass, qkey, nq, cell_key,
                      cell_start, ncell, np, nbr_count, cand_sum, nbr_off, nbr_cell);
   SJ_HIP(hipGetLastError());
 }
