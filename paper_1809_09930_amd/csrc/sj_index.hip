@@ -249,30 +249,37 @@ constexpr int kFenceMax = 8192;  // 64 KiB of u64 keys in LDS
 constexpr int kNbrBlock = 1024;
 constexpr int kNbrWaves = kNbrBlock / kWave;
 
-__device__ __forceinline__ int64_t find_cell(uint64_t key, const uint64_t *__restrict__ fence,
-                                             uint32_t nfence, uint32_t fstride,
-                                             const uint64_t *__restrict__ cell_key,
-                                             uint64_t ncell) {
-  // last fence entry <= key
-  uint32_t lo = 0, hi = nfence;
+// First table position whose key is >= key (ncell if none).  The fence
+// holds cell_key[f * fstride]; when fstride is 1 it is the whole table.
+__device__ __forceinline__ uint64_t lower_bound_cell(uint64_t key,
+                                                    const uint64_t *__restrict__ fence,
+                                                    uint32_t nfence, uint32_t fstride,
+                                                    const uint64_t *__restrict__ cell_key,
+                                                    uint64_t ncell) {
+  uint32_t lo = 0, hi = nfence;  // first fence entry >= key
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (fence[mid] <= key) lo = mid + 1; else hi = mid;
+    if (fence[mid] < key) lo = mid + 1; else hi = mid;
   }
-  if (lo == 0) return -1;
-  const uint32_t f = lo - 1;
-  if (fstride == 1) return fence[f] == key ? (int64_t)f : -1;
-  uint64_t a = (uint64_t)f * fstride, b = a + fstride;
+  if (fstride == 1 || lo == 0) return (uint64_t)lo * fstride;
+  // cell_key[(lo-1) fstride] < key <= cell_key[lo fstride] (or the end)
+  uint64_t a = (uint64_t)(lo - 1) * fstride + 1, b = (uint64_t)lo * fstride;
   if (b > ncell) b = ncell;
   while (a < b) {
     const uint64_t mid = (a + b) >> 1;
     if (cell_key[mid] < key) a = mid + 1; else b = mid;
   }
-  return (a < ncell && cell_key[a] == key) ? (int64_t)a : -1;
+  return a;
 }
 
 // Query cells are qkey[0 .. nq) (the table itself in a self-join); the
-// table is cell_key[0 .. ncell) with its cell_start.
+// table is cell_key[0 .. ncell) with its cell_start.  The 3^k offsets are
+// taken in groups of three that differ only in the last indexed dimension,
+// the least significant digit of the key (multiplier 1): their keys are
+// consecutive, so one search finds the position of the smallest and the
+// other two are the entries after it.  Each lane takes one group; groups
+// and the cells inside a group come in ascending key order, so the
+// neighbour list of a cell is written sorted.
 __global__ __launch_bounds__(kNbrBlock) void k_neighbors(
     int pass, const uint64_t *__restrict__ qkey, uint64_t nq,
     const uint64_t *__restrict__ cell_key, const uint32_t *__restrict__ cell_start,
@@ -286,35 +293,52 @@ __global__ __launch_bounds__(kNbrBlock) void k_neighbors(
   const uint32_t l = lane_id();
   const uint64_t wid = (uint64_t)blockIdx.x * kNbrWaves + threadIdx.x / kWave;
   const uint64_t nw = (uint64_t)gridDim.x * kNbrWaves;
+  const uint32_t kl = np.k - 1;                   // the last indexed dimension
+  const uint32_t ng = (uint32_t)(np.n_off / 3);  // 3^(k-1) <= 3^15 groups
   for (uint64_t A = wid; A < nq; A += nw) {
     const uint64_t keyA = qkey[A];
     int64_t cA[kKeyMaxDims];
     for (uint32_t r = 0; r < np.k; ++r) cA[r] = (int64_t)((keyA / np.mult[r]) % np.m[r]);
+    const bool lo_ok = cA[kl] >= 1;                       // the cell below exists
+    const bool hi_ok = cA[kl] + 1 < (int64_t)np.m[kl];  // the cell above exists
     uint32_t count = 0, wpos = (pass == 1) ? nbr_off[A] : 0u;
     uint64_t csum = 0;
-    // n_off = 3^k <= 3^16 < 2^32: the offset digits are taken in 32 bits
-    for (uint32_t base = 0; base < (uint32_t)np.n_off; base += kWave) {
-      const uint32_t o = base + l;
-      bool ok = o < (uint32_t)np.n_off;
-      uint64_t keyB = keyA;
-      uint32_t rem = o;
-      for (int r = (int)np.k - 1; r >= 0; --r) {  // dimension 0 is the most significant digit
+    for (uint32_t base = 0; base < ng; base += kWave) {
+      const uint32_t g = base + l;
+      bool ok = g < ng;
+      uint64_t keyB = keyA;  // the group's key with the last digit of A
+      uint32_t rem = g;
+      for (int r = (int)kl - 1; r >= 0; --r) {  // dimension 0 is the most significant digit
         const int64_t delta = (int64_t)(rem % 3u) - 1;
         rem /= 3u;
         const int64_t c = cA[r] + delta;
         ok = ok && c >= 0 && c < (int64_t)np.m[r];
         keyB += (uint64_t)delta * np.mult[r];
       }
-      int64_t B = -1;
-      if (ok) B = find_cell(keyB, fence, np.nfence, np.fstride, cell_key, ncell);
-      const bool found = B >= 0;
-      const uint64_t m = ballot(found);
+      // keys keyB - 1, keyB, keyB + 1 (those inside the grid), ascending
+      int64_t Bx[3] = {-1, -1, -1};
+      if (ok) {
+        const uint64_t first = lo_ok ? keyB - 1 : keyB;
+        uint64_t q = lower_bound_cell(first, fence, np.nfence, np.fstride, cell_key, ncell);
+        for (uint32_t t = 0; t < 3; ++t) {
+          const uint64_t kk = keyB + t - 1;
+          if ((t == 0 && !lo_ok) || (t == 2 && !hi_ok)) continue;
+          // q is the first position with key >= kk
+          if (q < ncell && (np.fstride == 1 ? fence[q] : cell_key[q]) == kk) Bx[t] = (int64_t)q++;
+        }
+      }
+      const uint64_t m0 = ballot(Bx[0] >= 0), m1 = ballot(Bx[1] >= 0), m2 = ballot(Bx[2] >= 0);
+      const uint32_t found = (uint32_t)(__builtin_popcountll(m0) + __builtin_popcountll(m1) +
+                                        __builtin_popcountll(m2));
       if (pass == 0) {
-        count += (uint32_t)__builtin_popcountll(m);
-        if (found) csum += (uint64_t)(cell_start[B + 1] - cell_start[B]);
+        count += found;
+        for (uint32_t t = 0; t < 3; ++t)
+          if (Bx[t] >= 0) csum += (uint64_t)(cell_start[Bx[t] + 1] - cell_start[Bx[t]]);
       } else {
-        if (found) nbr_cell[wpos + lanes_below(m)] = (uint32_t)B;
-        wpos += (uint32_t)__builtin_popcountll(m);
+        uint32_t w = wpos + lanes_below(m0) + lanes_below(m1) + lanes_below(m2);
+        for (uint32_t t = 0; t < 3; ++t)
+          if (Bx[t] >= 0) nbr_cell[w++] = (uint32_t)Bx[t];
+        wpos += found;
       }
     }
     if (pass == 0) {
