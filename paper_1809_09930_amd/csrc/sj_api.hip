@@ -1079,17 +1079,28 @@ uint64_t read_counter(sj_index &ix, int which, hipStream_t s) {
 // a count-only pass over a fraction of the points).  Counts pairs the FP32
 // filter cannot reject, so it is an upper-bound estimate.  The sample is
 // 1/64 of the queries, at least 1024 and at most 8192 of them, so it stays
-// a small part of the join's work for small and mid-sized inputs too.
+// a small part of the join's work for small and mid-sized inputs too.  It
+// takes runs of 8 consecutive positions (mostly of one cell): a wave then
+// counts up to 8 sampled queries against a cell's candidates where single
+// positions would leave it one, which matters when cells are small.
+constexpr uint32_t kSampleRun = 8;
+
 uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   const uint64_t n = ix.n_near;  // query positions in cells
   const uint64_t target = std::min<uint64_t>(8192, std::max<uint64_t>(1024, n / 64));
-  const uint64_t stride = n <= target ? 1 : n / target;
-  const uint64_t nq = (n + stride - 1) / stride;
+  uint64_t stride = 1, nq = n;
+  uint32_t run = 1;
+  if (n > target) {
+    run = kSampleRun;
+    const uint64_t nrun = target / run;  // >= 128
+    stride = n / nrun;                   // >= run, as n > nrun * run
+    nq = nrun * run;                     // last position (nrun-1) stride + run-1 < n
+  }
   ScratchScope scope;  // the read-back of the count below synchronises the stream
   TmpBuf ql;
   DevBuf wu;
   ql.alloc(nq * 4);
-  launch_iota_strided(ql.as<uint32_t>(), nq, stride, s);
+  launch_iota_strided(ql.as<uint32_t>(), nq, stride, run, s);
   uint64_t ev = 0;
   // the matrix-core path counts with its own filter (no keys are stored at
   // capacity 0); the FP32 path has a count-only kernel

@@ -102,8 +102,10 @@ void radix_sort_u64(uint64_t *keys[2], uint32_t *vals[2], uint64_t n,
                     const int *widths = nullptr);
 void launch_fill_u64(unsigned long long *p, uint64_t count, unsigned long long v, hipStream_t s);
 
-// out[i] = i * stride; widen u32 -> u64; narrow u64 -> u32 (low half).
-void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, hipStream_t s);
+// out[i] = (i / run) * stride + i % run (runs of `run` consecutive values,
+// stride >= run apart); widen u32 -> u64; narrow u64 -> u32 (low half).
+void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, uint32_t run,
+                         hipStream_t s);
 void launch_widen(const uint32_t *in, uint64_t *out, uint64_t count, hipStream_t s);
 void launch_narrow(const uint64_t *in, uint32_t *out, uint64_t count, hipStream_t s);
 

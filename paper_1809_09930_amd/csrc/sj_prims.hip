@@ -289,9 +289,9 @@ __global__ void k_copy_u64(const uint64_t *__restrict__ in, uint64_t *__restrict
     out[i] = in[i];
 }
 
-__global__ void k_iota_strided(uint32_t *out, uint64_t count, uint64_t stride) {
+__global__ void k_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, uint32_t run) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < count) out[i] = (uint32_t)(i * stride);
+  if (i < count) out[i] = (uint32_t)((i / run) * stride + i % run);
 }
 __global__ void k_widen(const uint32_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t count) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -304,10 +304,12 @@ __global__ void k_narrow(const uint64_t *__restrict__ in, uint32_t *__restrict__
 
 }  // namespace
 
-void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, hipStream_t s) {
+void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, uint32_t run,
+                         hipStream_t s) {
   if (!count) return;
+  if (run == 0 || (run > 1 && stride < run)) fail(SJ_ERR_INVALID_ARG, "iota runs overlap");
   hipLaunchKernelGGL(k_iota_strided, dim3((uint32_t)((count + kBlock - 1) / kBlock)), dim3(kBlock),
-                     0, s, out, count, stride);
+                     0, s, out, count, stride, run);
   SJ_HIP(hipGetLastError());
 }
 void launch_widen(const uint32_t *in, uint64_t *out, uint64_t count, hipStream_t s) {
