@@ -1105,9 +1105,12 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   // the matrix-core path counts with its own filter (no keys are stored at
   // capacity 0); the FP32 path has a count-only kernel
   const bool mf = ix.prec != SJ_PREC_FP32;
+  // candidate chunks of at most 4096: the sample's few units are split
+  // finely enough to spread over the chip
   const uint64_t nwu = build_workunits(ix, 0, ql.as<uint32_t>(), nq, ix.run_off_full,
                                        ix.runs_full, mf ? ix.tq_single : ix.tq,
-                                       mf ? ix.tc_single : 4096, wu, &ev, s);
+                                       mf ? std::min<uint32_t>(ix.tc_single, 4096) : 4096, wu,
+                                       &ev, s);
   SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
   join_launch(ix, wu, nwu, ix.runs_full, ql.as<uint32_t>(), 0, 1, nullptr, 0, s, ms);
   const uint64_t cnt = read_counter(ix, 0, s);
