@@ -171,3 +171,57 @@ def make_job(spec) -> np.ndarray:
         return uniform_grid(spec["n"], spec["d"], spec["seed"])
     std = uniform_std(spec["d"], 0.01, 0.3, spec["seed"] + 500)
     return gaussian_mixture(spec["n"], spec["d"], 10, std, spec["seed"])
+
+
+# ---------------------------------------------------------------------------
+# Off-grid float32 inputs.  These are drawn in binary64 and rounded to the
+# nearest float32 with no snapping to a coarse grid, so coordinates of one
+# dimension sit in different binades and their float32 differences round.
+# They exercise the error bounds of the device filters, which the grid data
+# above (exact differences) never reach.
+# ---------------------------------------------------------------------------
+OFFGRID_KINDS = ("uniform64", "normal_binades", "loguniform_signed", "mixture_f32")
+
+
+def offgrid(kind: str, n: int, d: int, seed: int) -> np.ndarray:
+    """n x d float32 of one of OFFGRID_KINDS:
+      uniform64          U[0,1) in binary64, rounded to float32;
+      normal_binades     per dimension scale 10^U(-2,1) and an offset of 0 (values
+                         of both signs around zero) or U(-2,2) scales, plus
+                         scale * N(0,1);
+      loguniform_signed  random sign times 2^U(-20,3): magnitudes over 23 binades;
+      mixture_f32        10 Gaussians, centres U[0,1)^d, per-dimension std decaying
+                         from 0.2 to 0.002 (shuffled), not clipped or rounded."""
+    rng = np.random.default_rng(seed)
+    if kind == "uniform64":
+        x = rng.random((n, d))
+    elif kind == "normal_binades":
+        scale = 10.0 ** rng.uniform(-2.0, 1.0, size=d)
+        offset = np.where(rng.random(d) < 0.5, 0.0, rng.uniform(-2.0, 2.0, size=d)) * scale
+        x = offset + scale * rng.standard_normal((n, d))
+    elif kind == "loguniform_signed":
+        mag = np.exp2(rng.uniform(-20.0, 3.0, size=(n, d)))
+        x = np.where(rng.random((n, d)) < 0.5, -mag, mag)
+    elif kind == "mixture_f32":
+        std = decaying_std(d, 0.2, 0.002, seed + 500)
+        centers = rng.random((10, d))
+        lab = rng.integers(0, 10, size=n)
+        x = centers[lab] + rng.standard_normal((n, d)) * std
+    else:
+        raise KeyError(kind)
+    return x.astype(np.float32)
+
+
+def partners_near_radius(base: np.ndarray, eps: float, count: int, seed: int,
+                         steps=(-3, -2, -1, 0, 1, 2, 3), unit: float = 2.0 ** -20):
+    """For `count` rows p of `base`, a partner p + eps * (1 + s * unit) * v with
+    v a random unit direction (binary64) and s drawn from `steps`, rounded to
+    the nearest float32.  The partners' distances to their rows fall within a
+    few float32 roundings of eps, inside the device filters' error bands."""
+    rng = np.random.default_rng(seed)
+    rows = rng.choice(len(base), size=count, replace=count > len(base))
+    v = rng.standard_normal((count, base.shape[1]))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    s = rng.choice(np.asarray(steps, dtype=np.float64), size=count)
+    q = base[rows].astype(np.float64) + (eps * (1.0 + s * unit))[:, None] * v
+    return q.astype(np.float32)

@@ -608,3 +608,58 @@ def test_full_size_results_identical_across_filters(workload, target, k):
         else:
             assert torch.equal(off, ref[0]), opts
             assert torch.equal(nb, ref[1]), opts
+
+
+# --------------------------------------------------------------------------
+# The metric's numerator: the ordered candidate count C of Section 3.2.1
+# (every point's adjacent non-empty cells, summed) reported by the device
+# equals the oracle's grid join at the same k, dimension order, origin and
+# cell width, on workloads where the grid is not degenerate.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("opts", [dict(), dict(precision="fp16"), dict(sortidu=True),
+                                  dict(k=3), dict(reorder=False)])
+@pytest.mark.parametrize("case", ["mixture50_d18", "mixture20_d90", "syn_d16", "syn_d64",
+                                  "offgrid_mixture"])
+def test_candidates_equal_oracle_grid(case, opts):
+    from paper_1809_09930_amd import selfjoin as sj
+    if case == "mixture50_d18":
+        P = datagen.make_workload("mixture50_5m_d18", n=30000)
+        eps = calibrated(P, 50, stride=29)
+    elif case == "mixture20_d90":
+        P = datagen.make_workload("mixture20_515k_d90", n=8000)
+        eps = calibrated(P, 50, stride=7)
+    elif case == "syn_d16":
+        P, eps = datagen.make_workload("syn_2m_d16", n=20000), 0.05
+    elif case == "syn_d64":
+        P, eps = datagen.make_workload("syn_2m_d64", n=6000), 0.16
+    else:
+        P = datagen.offgrid("mixture_f32", 30000, 18, 97)
+        eps = calibrated(P, 50, stride=29)
+    n, d = P.shape
+    print("case candidates", case, opts, flush=True)
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps, **opts)
+    try:
+        total = sj.selfjoin_run(h)
+        gi = torch.empty(total, dtype=torch.int32, device="cuda")
+        gj = torch.empty(total, dtype=torch.int32, device="cuda")
+        sj.selfjoin_fetch_pairs(h, 0, gi, gj, None, max_pairs=total)
+        info = sj.selfjoin_get_info(h)
+        perm = sj.selfjoin_get_perm(h, d)
+    finally:
+        sj.selfjoin_free(h)
+    k = info["k"]
+    oi, oj, cand = oracle.grid_join(P, eps, np.asarray(perm[:k], dtype=np.uint32))
+    assert info["candidates"] == cand, (info["candidates"], cand, k)
+    assert cand <= n * n
+    if case in ("mixture50_d18", "offgrid_mixture"):
+        assert cand * 4 < n * n  # clustered: far from the all-pairs count
+    assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
+    # symmetric tiles: each unordered candidate pair once, plus the part of
+    # the diagonal tiles (a query block against its own cell's run) above
+    # the diagonal, bounded by a 256-query block per work unit
+    lo = (cand + n) // 2
+    if opts.get("sortidu"):
+        assert info["evaluated"] <= lo + 256 * n
+    else:
+        assert lo <= info["evaluated"] <= lo + 256 * n, (info["evaluated"], lo)
