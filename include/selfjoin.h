@@ -224,6 +224,26 @@ int selfjoin_fetch_offsets(sj_index *idx, uint64_t *offsets, void *stream);
 int selfjoin_build_query(const sj_index *entries, const float *queries, uint64_t m,
                          void *stream, sj_index **out);
 
+/*
+ * As selfjoin_fetch_offsets, for callers that cannot allocate memory (tight
+ * serving loops, code that must not call hipMalloc in its steady state): it
+ * allocates nothing.  Its temporaries (the scan's partial sums, the per-row
+ * counts for host output, the staging of a host-resident result) live in
+ * one fixed 64 MiB device array that the library holds on each device it
+ * runs on until the process ends.
+ *   offsets  host or device, n + 1 entries, caller-owned.  Device offsets
+ *            are counted and scanned in place (any n); host offsets need
+ *            (n + 1) * 8 bytes of the array for the counts, so n can be at
+ *            most about 6.2 * 10^6 for host output.
+ * Every call on a device shares that device's array.  The library takes a
+ * per-device lock for the call and completes the call's device work before
+ * returning, so calls from threads of one process do not overlap; calls
+ * from several processes on one device share nothing.
+ * Errors: as selfjoin_fetch_offsets, plus SJ_ERR_INVALID_ARG when n is too
+ * large for the fixed array (selfjoin_fetch_offsets has no such limit).
+ */
+int selfjoin_fetch_offsets_noalloc(sj_index *idx, uint64_t *offsets, void *stream);
+
 /* info->struct_size must be set by the caller. */
 int selfjoin_get_info(const sj_index *idx, sj_info *info);
 

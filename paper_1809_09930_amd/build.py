@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libselfjoin.so")
-SOURCES = ["sj_prims.hip", "sj_index.hip", "sj_join.hip", "sj_mfma.hip", "sj_api.hip", "sj_batch.hip"]
+SOURCES = ["sj_prims.hip", "sj_index.hip", "sj_join.hip", "sj_mfma.hip", "sj_api.hip", "sj_batch.hip",
+           "sj_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

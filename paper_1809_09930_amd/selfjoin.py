@@ -35,7 +35,8 @@ SJ_UNITS_SMALL_CELLS = 2
 
 EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_build_query",
             "selfjoin_run",
-            "selfjoin_fetch_pairs", "selfjoin_fetch_offsets", "selfjoin_get_info",
+            "selfjoin_fetch_pairs", "selfjoin_fetch_offsets", "selfjoin_fetch_offsets_noalloc",
+            "selfjoin_get_info",
             "selfjoin_get_perm",
             "selfjoin_free", "selfjoin_last_error", "selfjoin_run_batched",
             "selfjoin_batch_replay", "selfjoin_batch_range", "selfjoin_batch_fetch",
@@ -142,6 +143,8 @@ def load_library(path: str = LIB_PATH):
     lib.selfjoin_fetch_pairs.argtypes = [vp, u64, u64, vp, vp, vp, ctypes.POINTER(u64), vp]
     lib.selfjoin_fetch_offsets.argtypes = [vp, vp, vp]
     lib.selfjoin_fetch_offsets.restype = ctypes.c_int
+    lib.selfjoin_fetch_offsets_noalloc.argtypes = [vp, vp, vp]
+    lib.selfjoin_fetch_offsets_noalloc.restype = ctypes.c_int
     lib.selfjoin_fetch_pairs.restype = ctypes.c_int
     lib.selfjoin_get_info.argtypes = [vp, ctypes.POINTER(SjInfo)]
     lib.selfjoin_get_info.restype = ctypes.c_int
@@ -267,6 +270,15 @@ def selfjoin_fetch_offsets(handle, offsets, stream=None) -> None:
         raise ValueError("offsets must be contiguous")
     _check(load_library().selfjoin_fetch_offsets(handle, offsets.data_ptr(),
                                                  _stream_handle(stream)))
+
+
+def selfjoin_fetch_offsets_noalloc(handle, offsets, stream=None) -> None:
+    """As selfjoin_fetch_offsets, with every temporary in the library's fixed
+    per-device array: the call allocates no memory."""
+    if not offsets.is_contiguous():
+        raise ValueError("offsets must be contiguous")
+    _check(load_library().selfjoin_fetch_offsets_noalloc(handle, offsets.data_ptr(),
+                                                         _stream_handle(stream)))
 
 
 def selfjoin_get_info(handle) -> dict:
