@@ -57,7 +57,8 @@ extern "C" {
 #define SJ_ERR_INVALID_ARG   -1  /* NULL pointer, n or d out of range, epsilon <= 0 or not finite, NaN/Inf coordinates, bad option */
 #define SJ_ERR_OUT_OF_MEMORY -2  /* a device or pinned-host allocation failed */
 #define SJ_ERR_DEVICE        -3  /* a HIP runtime call failed */
-#define SJ_ERR_KEY_OVERFLOW  -4  /* an explicit k makes the linearised cell id exceed 63 bits */
+#define SJ_ERR_KEY_OVERFLOW  -4  /* an explicit k makes the linearised cell id exceed 63 bits, or the
+                                    adjacency lists of the cells exceed 2^32 - 1 entries */
 #define SJ_ERR_STATE         -5  /* call out of order, e.g. fetch before run */
 #define SJ_ERR_RANGE         -6  /* fetch offset beyond the result */
 
@@ -126,8 +127,9 @@ void selfjoin_default_options(sj_options *opts);
  *   opts     NULL for the defaults.
  *   out      receives the new handle; release it with selfjoin_free.
  * Errors: SJ_ERR_INVALID_ARG for bad arguments or non-finite coordinates,
- * SJ_ERR_KEY_OVERFLOW when an explicit k cannot be linearised in 63 bits
- * (automatic k lowers k instead), SJ_ERR_OUT_OF_MEMORY, SJ_ERR_DEVICE.
+ * SJ_ERR_KEY_OVERFLOW when an explicit k cannot be linearised in 63 bits or
+ * gives more than 2^32 - 1 adjacent-cell entries over all non-empty cells
+ * (automatic k stays below both limits), SJ_ERR_OUT_OF_MEMORY, SJ_ERR_DEVICE.
  */
 int selfjoin_build_index(const float *points, uint64_t n, uint32_t d,
                          double epsilon, const sj_options *opts, void *stream,

@@ -23,6 +23,7 @@
  * every (i, i) and both (i, j) and (j, i) (Section 3.1; the selectivity
  * equation of Section 5.2 subtracts |D| self pairs from |R|).
  */
+#define _GNU_SOURCE /* qsort_r: comparators take their context as an argument */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -269,8 +270,6 @@ typedef struct {
     uint32_t k;
 } grid_ctx;
 
-static grid_ctx g_ctx; /* used only by the qsort comparator, set under lock */
-
 static int cmp_coord(const int64_t *a, const int64_t *b, uint32_t k)
 {
     for (uint32_t r = 0; r < k; ++r) {
@@ -280,11 +279,11 @@ static int cmp_coord(const int64_t *a, const int64_t *b, uint32_t k)
     return 0;
 }
 
-static int cmp_point(const void *pa, const void *pb)
+static int cmp_point(const void *pa, const void *pb, void *arg)
 {
+    const grid_ctx *g = (const grid_ctx *)arg;
     uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
-    int c = cmp_coord(g_ctx.coord + (uint64_t)a * g_ctx.k,
-                      g_ctx.coord + (uint64_t)b * g_ctx.k, g_ctx.k);
+    int c = cmp_coord(g->coord + (uint64_t)a * g->k, g->coord + (uint64_t)b * g->k, g->k);
     if (c) return c;
     return (a > b) - (a < b);
 }
@@ -330,14 +329,16 @@ int64_t oracle_grid(const float *P, uint64_t n, uint32_t d, double eps,
     uint64_t *offs = (uint64_t *)calloc(n, sizeof(uint64_t));
     uint64_t *cand = (uint64_t *)calloc(n, sizeof(uint64_t));
     uint64_t *cstart = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
-    if (!coord || !order || !rowcnt || !offs || !cand || !cstart) return -2;
+    if (!coord || !order || !rowcnt || !offs || !cand || !cstart) {
+        free(coord); free(order); free(rowcnt); free(offs); free(cand); free(cstart);
+        return -2;
+    }
     oracle_cell_coords(P, n, d, eps, k, dims, origin_zero, width_factor, coord);
 
     /* points grouped by cell: sort by coordinate vector (lookup array) */
     for (uint64_t i = 0; i < n; ++i) order[i] = (uint32_t)i;
-    g_ctx.coord = coord;
-    g_ctx.k = k;
-    qsort(order, n, sizeof(uint32_t), cmp_point);
+    grid_ctx ctx = {coord, k};
+    qsort_r(order, n, sizeof(uint32_t), cmp_point, &ctx);
 
     /* non-empty cells: first position of each distinct coordinate vector */
     uint64_t ncell = 0;
@@ -458,13 +459,13 @@ typedef struct {
     const float *P;
     uint32_t d, u;
 } u_ctx;
-static u_ctx g_uctx; /* qsort comparator context, single-threaded use */
 
-static int cmp_by_u(const void *pa, const void *pb)
+static int cmp_by_u(const void *pa, const void *pb, void *arg)
 {
+    const u_ctx *c = (const u_ctx *)arg;
     const uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
-    const float ua = g_uctx.P[(uint64_t)a * g_uctx.d + g_uctx.u];
-    const float ub = g_uctx.P[(uint64_t)b * g_uctx.d + g_uctx.u];
+    const float ua = c->P[(uint64_t)a * c->d + c->u];
+    const float ub = c->P[(uint64_t)b * c->d + c->u];
     if (ua < ub) return -1;
     if (ua > ub) return 1;
     return (a > b) - (a < b);
@@ -485,9 +486,7 @@ int64_t oracle_sortidu_candidates(const float *P, uint64_t n, uint32_t d,
     const double pu = (double)P[query * d + u];
     uint64_t n_off = 1, w = 0;
     for (uint32_t r = 0; r < k; ++r) n_off *= 3;
-    g_uctx.P = P;
-    g_uctx.d = d;
-    g_uctx.u = u;
+    u_ctx uctx = {P, d, u};
     for (uint64_t o = 0; o < n_off; ++o) {
         int64_t nb[20];
         uint64_t rem = o;
@@ -496,7 +495,7 @@ int64_t oracle_sortidu_candidates(const float *P, uint64_t n, uint32_t d,
         uint64_t m = 0;
         for (uint64_t j = 0; j < n; ++j)
             if (cmp_coord(coord + j * k, nb, k) == 0) cell[m++] = (uint32_t)j;
-        qsort(cell, m, sizeof(uint32_t), cmp_by_u);
+        qsort_r(cell, m, sizeof(uint32_t), cmp_by_u, &uctx);
         /* r: first point with u >= p(u) - eps, i.e. the smallest u within eps */
         uint64_t lo = 0, hi = m;
         while (lo < hi) {

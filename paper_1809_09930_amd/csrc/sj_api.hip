@@ -242,6 +242,18 @@ uint64_t build_neighbors(sj_index &ix, const sj_index &E, NbrParams np, BuildTmp
   uint64_t h_c = 0;
   SJ_HIP(hipMemcpyAsync(&h_c, d_c, 8, hipMemcpyDeviceToHost, s));
   if (keep) {
+    // the adjacency lists use 32-bit offsets: their total, summed in 64 bits
+    // (the C scan above no longer needs t.prod), must stay below 2^32
+    launch_widen(t.nbr_count.as<uint32_t>(), t.prod.as<uint64_t>(), nc + 1, s);
+    uint64_t *d_nn64 = reinterpret_cast<uint64_t *>(t.small.as<char>() + 24);
+    exclusive_scan_u64(t.prod.as<uint64_t>(), t.prod.as<uint64_t>(), nc + 1, d_nn64, t.scan.p, s);
+    uint64_t h_nn64 = 0;
+    SJ_HIP(hipMemcpyAsync(&h_nn64, d_nn64, 8, hipMemcpyDeviceToHost, s));
+    SJ_HIP(hipStreamSynchronize(s));
+    if (h_nn64 > 0xffffffffull)
+      fail(SJ_ERR_KEY_OVERFLOW, "the adjacency lists over k=" + std::to_string(ix.geom.k) +
+                                    " dimensions hold " + std::to_string(h_nn64) +
+                                    " cells, more than 2^32 - 1; use a smaller k");
     ix.nbr_off.alloc((nc + 1) * 4);
     uint32_t *d_nn = reinterpret_cast<uint32_t *>(t.small.as<char>() + 16);
     exclusive_scan_u32(t.nbr_count.as<uint32_t>(), ix.nbr_off.as<uint32_t>(), nc + 1, d_nn,
@@ -692,6 +704,10 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
       Geometry gk;
       if (!make_geometry(ix, k, gk)) break;  // longer keys would overflow: stop
       const uint64_t C = build_grid(ix, P, gk, t, s, false);
+      // adjacency lists that could pass 2^32 - 1 entries (at most 3^k, and
+      // at most #G, per cell) rule out this k and every larger one
+      const double nc_k = (double)ix.ncell;
+      if (nc_k * std::min<double>((double)gk.np.n_off, nc_k) > 4294967295.0) break;
       const double cost = (double)C * 0.5 / kPairsPerSec +
                           (double)ix.ncell * (double)gk.np.n_off / kLookupsPerSec;
       if (!have || cost < best * (1.0 - 1e-9)) {
@@ -1250,6 +1266,7 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) 
                     cap, s, &ms_join);
         got = read_counter(ix, 0, s);
         if (got <= cap) break;
+        if (attempt == 2) fail(SJ_ERR_DEVICE, "batch result count did not settle");
         cap = got;
       }
       ix.info.rechecks += read_counter(ix, 1, s);

@@ -48,6 +48,33 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Canonical predicate of Section 3.1 on positions of cell-ordered rows: row a
+// of XA against row b of XB (rows of dp floats in the reordered dimension
+// order), summed in binary64 in the caller's dimension order (inv_perm maps a
+// caller dimension to its reordered position), every operation separately
+// rounded (no contraction), accepted iff the sum is <= eps2.  Every device
+// filter sends the pairs it cannot decide here, so this is the one place the
+// include/exclude decision is taken in FP64.
+#ifndef SJ_RECHECK_INLINE
+#define SJ_RECHECK_INLINE __noinline__
+#endif
+static __device__ SJ_RECHECK_INLINE bool canonical_within(const float *__restrict__ XA, uint32_t a,
+                                                          const float *__restrict__ XB, uint32_t b,
+                                                          const uint16_t *__restrict__ inv_perm,
+                                                          uint32_t d, uint32_t dp, double eps2) {
+#pragma clang fp contract(off)
+  const float *pa = XA + (uint64_t)a * dp;
+  const float *pb = XB + (uint64_t)b * dp;
+  double acc = 0.0;
+  for (uint32_t t = 0; t < d; ++t) {
+    const uint32_t r = inv_perm[t];
+    const double diff = (double)pa[r] - (double)pb[r];
+    const double sq = diff * diff;
+    acc = acc + sq;
+  }
+  return acc <= eps2;
+}
+
 // float <-> order-preserving uint32 (for atomic min/max of finite floats)
 __device__ __host__ __forceinline__ uint32_t float_to_ordered(float f) {
   uint32_t u = __builtin_bit_cast(uint32_t, f);

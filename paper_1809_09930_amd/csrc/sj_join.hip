@@ -95,24 +95,6 @@ static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 flo
 #define SJ_NORM_RQ_MID 1
 #endif
 
-// Canonical predicate on positions a, b of the cell-ordered rows.
-__device__ __noinline__ bool canonical_within(const float *__restrict__ XA, uint32_t a,
-                                              const float *__restrict__ XB, uint32_t b,
-                                              const uint16_t *__restrict__ inv_perm, uint32_t d,
-                                              uint32_t dp, double eps2) {
-#pragma clang fp contract(off)
-  const float *pa = XA + (uint64_t)a * dp;
-  const float *pb = XB + (uint64_t)b * dp;
-  double acc = 0.0;
-  for (uint32_t t = 0; t < d; ++t) {
-    const uint32_t r = inv_perm[t];
-    const double diff = (double)pa[r] - (double)pb[r];
-    const double sq = diff * diff;
-    acc = acc + sq;
-  }
-  return acc <= eps2;
-}
-
 struct WaveStage {
   uint64_t *buf;  // this wave's LDS slice
   uint32_t cnt;   // wave-uniform fill level

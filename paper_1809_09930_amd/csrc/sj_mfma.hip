@@ -4,12 +4,13 @@
 // Form.  With a fixed centre c, every point is stored as x~ = Q(x - c) in
 // FP16 or BF16 (Q = round to nearest; magnitudes below the format's
 // smallest normal are flushed to 0).  For a candidate row a and a query
-// column b one 32x32 MFMA tile accumulates
-//     D = n_a - 2 a~ . b~        (n_a = |a~|^2, folded in as 2 or 3 exact
-//                                 16-bit pieces in spare K columns)
-// so that D + n_b is the squared distance of the quantised points.
-// The operands are laid out K-contiguous: A rows [a~ | pieces of n_a | 0],
-// B columns [-2 b~ | 1 .. 1 | 0]; scaling by -2 is exact.
+// column b one 32x32 MFMA tile computes
+//     D = fl32(n_a) - 2 a~ . b~        (n_a = |a~|^2 in FP64)
+// with fl32(n_a) as the tile's initial accumulator, so that D + n_b is the
+// squared distance of the quantised points up to the FP32 accumulation
+// error and the rounding of n_a (the fold residual |n_a - fl32(n_a)|), both
+// inside the band.  The operands are laid out K-contiguous and zero-padded
+// to K: A rows [a~ | 0], B columns [-2 b~ | 0]; scaling by -2 is exact.
 //
 // Band.  Per query b the FP64 preparation below gives thresholds
 // Thi(b) >= D for every candidate the canonical predicate accepts, and
@@ -218,30 +219,6 @@ __global__ __launch_bounds__(kBlock) void k_mfma_thresholds(
   tlo[p] = round_down_f32(tlo_v);
 }
 
-// ---------------------------------------------------------------------------
-#ifndef SJ_RECHECK_INLINE
-#define SJ_RECHECK_INLINE __noinline__
-#endif
-// Canonical predicate on positions (caller's dimension order, FP64, no
-// contraction): row a of XA (queries) against row b of XB (candidates).
-// ---------------------------------------------------------------------------
-__device__ SJ_RECHECK_INLINE bool canonical_within_m(const float *__restrict__ XA, uint32_t a,
-                                                     const float *__restrict__ XB, uint32_t b,
-                                                     const uint16_t *__restrict__ inv_perm,
-                                                     uint32_t d, uint32_t dp, double eps2) {
-#pragma clang fp contract(off)
-  const float *pa = XA + (uint64_t)a * dp;
-  const float *pb = XB + (uint64_t)b * dp;
-  double acc = 0.0;
-  for (uint32_t t = 0; t < d; ++t) {
-    const uint32_t r = inv_perm[t];
-    const double diff = (double)pa[r] - (double)pb[r];
-    const double sq = diff * diff;
-    acc = acc + sq;
-  }
-  return acc <= eps2;
-}
-
 struct Stage {
   uint64_t *buf;
   uint32_t cnt;
@@ -364,7 +341,7 @@ __device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const floa
           bs.st.cnt += nb;
         } else {
           if (band)
-            acc_ok = canonical_within_m(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
+            acc_ok = canonical_within(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
           n_recheck += (uint64_t)__builtin_popcountll(bm);
         }
       }
@@ -421,7 +398,7 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
           bs.st.cnt += nb;
         } else {
           if (band)
-            acc_ok = canonical_within_m(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
+            acc_ok = canonical_within(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
           n_recheck += (uint64_t)__builtin_popcountll(bm);
         }
       }
@@ -790,7 +767,7 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck(
       const uint64_t key = v.band[i];
       q = (uint32_t)(key >> 32);
       c = (uint32_t)key;
-      ok = canonical_within_m(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
+      ok = canonical_within(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
     }
     const uint64_t am = ballot(ok);
     if (am == 0) continue;
@@ -898,7 +875,7 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck_batched(
       const uint32_t job = (uint32_t)(key >> 40);
       const uint32_t q = (uint32_t)((key >> 20) & kMask), c = (uint32_t)(key & kMask);
       const MfmaView &v = jobs[job].view;
-      ok = canonical_within_m(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
+      ok = canonical_within(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
       two = ok && v.symmetric && q != c;
       rkey = ((uint64_t)job << 40) | ((uint64_t)c << 20) | q;
     }

@@ -663,3 +663,40 @@ def test_candidates_equal_oracle_grid(case, opts):
         assert info["evaluated"] <= lo + 256 * n
     else:
         assert lo <= info["evaluated"] <= lo + 256 * n, (info["evaluated"], lo)
+
+
+# --------------------------------------------------------------------------
+# Boundary cases of the index build and of the result budget.
+# --------------------------------------------------------------------------
+def test_explicit_k_overflows():
+    """An explicit k whose cell id cannot be linearised in 63 bits, and one
+    whose adjacency lists exceed 2^32 - 1 entries: both SJ_ERR_KEY_OVERFLOW;
+    automatic k on the same sets stays within both limits and is exact."""
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.uniform_grid(3000, 16, 401)  # 20 cells per dimension at eps 0.05
+    with pytest.raises(sj.SelfJoinError) as e:
+        sj.selfjoin_build_index(torch.from_numpy(P).cuda(), 0.05, k=16)
+    assert e.value.code == sj.SJ_ERR_KEY_OVERFLOW
+    assert_same_as_oracle(P, 0.05)
+    # 4^10 lattice points of spacing 1 at eps 0.9: one point per cell, each
+    # cell adjacent to 2.5^10 non-empty cells on average, 10^10 entries
+    g = np.indices((4,) * 10, dtype=np.float32).reshape(10, -1).T.copy()
+    with pytest.raises(sj.SelfJoinError) as e:
+        sj.selfjoin_build_index(torch.from_numpy(g).cuda(), 0.9, k=10)
+    assert e.value.code == sj.SJ_ERR_KEY_OVERFLOW
+    assert "2^32" in str(e.value)
+    h = sj.selfjoin_build_index(torch.from_numpy(g).cuda(), 0.9)
+    try:
+        assert sj.selfjoin_run(h) == len(g)  # spacing 1 > eps: self pairs only
+    finally:
+        sj.selfjoin_free(h)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_mem_budget_forces_batches(prec):
+    """A device budget too small for the result in one batch: the result is
+    produced in several batches and streamed to host memory, unchanged."""
+    P = datagen.offgrid("uniform64", 2500, 16, 402)
+    eps = calibrated(P, 30)
+    info = assert_same_as_oracle(P, eps, precision=prec, mem_budget=20 * 4000)
+    assert info["batches"] >= 3 and info["result_on_host"] == 1
