@@ -1001,8 +1001,13 @@ MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist,
 
 // One launch of the distance kernel over a set of work units.
 bool debug_undersize();
+int debug_hits_mode();
 uint64_t read_counter(sj_index &ix, int which, hipStream_t s);
 constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
+#ifndef SJ_FREQUENT_HITS_PER_TILE
+#define SJ_FREQUENT_HITS_PER_TILE 0.5
+#endif
+constexpr double kFrequentHitsPerTile = SJ_FREQUENT_HITS_PER_TILE;
 
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
                  const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
@@ -1048,6 +1053,9 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     m.cursor = a.cursor;
     m.rechecks = a.rechecks;
     m.per_wave = ix.mfma_per_wave ? 1 : 0;
+    // more than about one hit per two 32 x 32 tiles: scan elements directly
+    m.hits_frequent = ix.hit_density * 1024.0 > kFrequentHitsPerTile ? 1 : 0;
+    if (const int forced = debug_hits_mode(); forced >= 0) m.hits_frequent = forced;
     if (count_only) {
       launch_join_mfma(m, s);  // band pairs rechecked in place
     } else {
@@ -1134,8 +1142,9 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   if (mf) {
     // band pairs of the sample (rechecked in place here) size the deferred
     // recheck list of the join
-    const double band = (double)read_counter(ix, 1, s) * scale;
-    ix.band_hint = (uint64_t)std::ceil(band * 1.25) + (1u << 16);
+    const double nband = (double)read_counter(ix, 1, s);
+    ix.band_hint = (uint64_t)std::ceil(nband * scale * 1.25) + (1u << 16);
+    ix.hit_density = ev ? ((double)cnt + nband) / (double)ev : 0.0;
   }
   return (uint64_t)std::ceil((double)cnt * scale);
 }
@@ -1434,6 +1443,11 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   }
   SJ_HIP(hipStreamSynchronize(s));
   *n_written = cnt;
+}
+
+int debug_hits_mode() {
+  const char *v = std::getenv("SJ_DEBUG_HITS");
+  return v && (v[0] == '0' || v[0] == '1') ? v[0] - '0' : -1;
 }
 
 bool debug_undersize() {

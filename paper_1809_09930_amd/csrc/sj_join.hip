@@ -87,6 +87,13 @@ static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 flo
 #ifndef SJ_SWEEP_MODE
 #define SJ_SWEEP_MODE 1
 #endif
+// Query-box prefilter: 1 = candidates are first tested in batches of 64
+// (one per lane) against the bounding box of the wave's queries over the
+// first kBoxDims dimensions, and only those whose lower bound on the
+// squared distance to the box passes `hi` are evaluated query by query
+#ifndef SJ_BOX_FILTER
+#define SJ_BOX_FILTER 1
+#endif
 // the same for the norm form
 #ifndef SJ_NORM_RQ_SMALL
 #define SJ_NORM_RQ_SMALL 4
@@ -115,6 +122,13 @@ __device__ __forceinline__ void stage_flush(WaveStage &st, uint64_t *__restrict_
   __builtin_amdgcn_wave_barrier();
   st.cnt = 0;
 }
+
+// dimensions of the query box (the first ones in the variance order)
+#ifndef SJ_BOX_DIMS
+#define SJ_BOX_DIMS 8
+#endif
+template <int DP>
+constexpr int kBoxDims = DP < SJ_BOX_DIMS ? DP : SJ_BOX_DIMS;
 
 template <int DP, int RQ>
 struct Lanes {
@@ -346,6 +360,13 @@ __device__ __forceinline__ void join_body(
 
   Lanes<DP, RQ> L;
   NormLanes<DP, RQ, kNorm> NL;
+  constexpr int NB = kBoxDims<DP>;
+  float blo[NB], bhi[NB];  // this lane's part of the query box
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    blo[t] = __builtin_inff();
+    bhi[t] = -__builtin_inff();
+  }
 #pragma unroll
   for (int r = 0; r < RQ; ++r) {
     const uint32_t slot = wu.q0 + (uint32_t)r * kWave + l;
@@ -363,6 +384,14 @@ __device__ __forceinline__ void join_body(
       L.q[r][4 * t + 1] = sc * v.y;
       L.q[r][4 * t + 2] = sc * v.z;
       L.q[r][4 * t + 3] = sc * v.w;
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (4 * t + i < NB && live) {
+          blo[4 * t + i] = __builtin_fminf(blo[4 * t + i], vv[i]);
+          bhi[4 * t + i] = __builtin_fmaxf(bhi[4 * t + i], vv[i]);
+        }
+      }
     }
     if constexpr (kNorm) {
       const float *qa = QA + (uint64_t)p * norm_row(DP);
@@ -371,6 +400,20 @@ __device__ __forceinline__ void join_body(
       if (!live) NL.qa[r][0] = __builtin_inff();
     }
   }
+  // the box of the wave's live queries, made wave-uniform (scalar registers)
+#if SJ_BOX_FILTER
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    float a = blo[t], b = bhi[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a = __builtin_fminf(a, __shfl_xor(a, off));
+      b = __builtin_fmaxf(b, __shfl_xor(b, off));
+    }
+    blo[t] = __builtin_bit_cast(float, uniform_u32(__builtin_bit_cast(uint32_t, a)));
+    bhi[t] = __builtin_bit_cast(float, uniform_u32(__builtin_bit_cast(uint32_t, b)));
+  }
+#endif
   // in symmetric contiguous mode candidates below q1 need the per-lane
   // "query position <= candidate position" filter; beyond it all pass
   const uint32_t filt_end = (symmetric && !qlist) ? wu.q1 : 0u;
@@ -421,6 +464,53 @@ __device__ __forceinline__ void join_body(
         if (++c >= to) break;
         next();
       }
+#elif SJ_BOX_FILTER
+      // batches of 64 candidates: lane l bounds the squared distance from
+      // candidate b0 + l to the query box over the first NB dimensions.
+      // Every query of the box is at least that far (in FP32 the bound is a
+      // sum of at most DP rounded squares, within the error `hi` already
+      // allows for), so a candidate with bound > hi is rejected for all of
+      // them; the others are evaluated in order, the head of the next one
+      // loaded ahead.
+      for (uint32_t b0 = from; b0 < to; b0 += kWave) {
+        const uint32_t cl = b0 + l < to ? b0 + l : b0;
+        const float4 *brow = reinterpret_cast<const float4 *>(X + (uint64_t)cl * DP);
+        float lb = 0.0f;
+#pragma unroll
+        for (int t4 = 0; t4 < NB / 4; ++t4) {
+          const float4 v = brow[t4];
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float g = __builtin_fmaxf(
+                __builtin_fmaxf(blo[4 * t4 + i] - vv[i], vv[i] - bhi[4 * t4 + i]), 0.0f);
+            lb = __builtin_fmaf(g, g, lb);
+          }
+        }
+        uint64_t keep = ballot(b0 + l < to && lb <= hi);
+        if (keep == 0) continue;
+        uint32_t c = b0 + (uint32_t)__builtin_ctzll(keep);
+        keep &= keep - 1;
+        crow = X + (uint64_t)c * DP;
+        if (kNorm) ccr = CR + (uint64_t)c * NR;
+        Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
+        for (;;) {
+          const bool more = keep != 0;
+          const uint32_t cn = more ? b0 + (uint32_t)__builtin_ctzll(keep) : c;
+          Head<DP, kNorm> hn = h;
+          if (more)
+            hn = load_head<DP, kNorm>(X + (uint64_t)cn * DP,
+                                      kNorm ? CR + (uint64_t)cn * NR : nullptr);
+          eval(h, c);
+          if (!more) break;
+          keep &= keep - 1;
+          c = cn;
+          h = hn;
+          crow = X + (uint64_t)c * DP;
+          if (kNorm) ccr = CR + (uint64_t)c * NR;
+        }
+      }
+      (void)next;
 #elif SJ_SWEEP_MODE == 1
       Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
       for (uint32_t c = from; c < to; ++c) {

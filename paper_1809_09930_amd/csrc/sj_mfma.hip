@@ -418,6 +418,79 @@ __device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const 
   }
 }
 
+// Hit path for tiles where hits are common (clustered data: a few result or
+// band pairs in most tiles).  No minimum over the tile first: the 16 element
+// compares of a query block are the wave masks themselves, taken four
+// elements at a time, and only elements with a hit do the row checks and
+// the emission.  Rows are valid without a check when the whole 32-row block
+// lies before cend.
+template <int QB>
+__device__ __forceinline__ void tiles_hits_scan(const float16v (&acc)[QB], const float (&th)[QB],
+                                                const float (&tl)[QB],
+                                                const uint32_t (&qpos)[QB], uint32_t c0,
+                                                uint32_t cend, uint32_t half, const MfmaView &v,
+                                                Stage &st, BandSink &bs,
+                                                uint64_t *__restrict__ out, uint64_t capacity,
+                                                unsigned long long *__restrict__ cursor,
+                                                uint64_t &n_recheck) {
+  const bool sym = v.symmetric != 0;
+  const bool full = c0 + 32u <= cend;  // wave-uniform
+  const uint32_t cbase = c0 + 4u * half;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint64_t hm[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hm[i] = ballot(acc[j][4 * g + i] <= th[j]);
+      if ((hm[0] | hm[1] | hm[2] | hm[3]) == 0) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (hm[i] == 0) continue;
+        const int e = 4 * g + i;
+        const bool h = acc[j][e] <= th[j];
+        const uint32_t cp = cbase + (uint32_t)(8 * g + i);
+        const bool ok = h && (full || cp < cend) && (!sym || qpos[j] <= cp);
+        bool acc_ok = ok && acc[j][e] <= tl[j];
+        const bool band = ok && !acc_ok;
+        const uint64_t bm = ballot(band);
+        if (bm) {
+          if (bs.buf) {  // deferred: the pair waits in the band list
+            const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
+            if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
+            if (band)
+              bs.st.buf[bs.st.cnt + lanes_below(bm)] =
+                  v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+            bs.st.cnt += nb;
+          } else {
+            if (band)
+              acc_ok = canonical_within(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
+            n_recheck += (uint64_t)__builtin_popcountll(bm);
+          }
+        }
+        const uint64_t am = ballot(acc_ok);
+        if (am == 0) continue;
+        const bool two = acc_ok && sym && qpos[j] != cp;
+        const uint64_t m2 = ballot(two);
+        const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+        if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
+        const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+        if (acc_ok) {
+          st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+          if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
+        }
+        st.cnt += total;
+      }
+    }
+  }
+}
+
+// Hit modes of the single-join kernels: kHitsRare tests the minimum of each
+// tile first and enters a hit path only for tiles with a hit; kHitsFrequent
+// goes straight to the element scan.
+constexpr int kHitsRare = 0;
+constexpr int kHitsFrequent = 1;
+
 // K padding above which the workgroup kernel takes the accumulator-based
 // hit path; the persistent batched kernel holds all its variants in one
 // register allocation and keeps the mask path throughout.
@@ -459,7 +532,7 @@ struct BlockIter {
 // One work unit of the matrix-core filter: QB query column blocks against
 // the candidate blocks of the unit's runs.  Accepted pairs are staged as
 // keys key_hi | pos_q << pshift | pos_c.
-template <int KP, int FMT, int QB>
+template <int KP, int FMT, int QB, int HM = kHitsRare>
 __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu, Stage &st,
                                           BandSink &bs, float *__restrict__ nrm,
                                           uint64_t *__restrict__ out, uint64_t capacity,
@@ -527,7 +600,10 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
 #pragma unroll
       for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
     }
-    if (ballot(tiles_any<QB>(acc, th))) {
+    if constexpr (HM == kHitsFrequent) {
+      tiles_hits_scan<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
+                          n_recheck);
+    } else if (ballot(tiles_any<QB>(acc, th))) {
       if constexpr (KP > SJ_BATCH_HIT_ACC_ABOVE_KP)
         tiles_hits_acc<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
                            n_recheck);
@@ -551,7 +627,7 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
 #ifndef SJ_WAVE_QB
 #define SJ_WAVE_QB 1
 #endif
-template <int KP, int FMT>
+template <int KP, int FMT, int HM>
 __global__ __launch_bounds__(kBlock) void k_join_mfma_wave(MfmaView v,
                                                            const WorkUnit *__restrict__ wus,
                                                            uint64_t n_wu, uint64_t *__restrict__ out,
@@ -568,7 +644,8 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wave(MfmaView v,
   Stage st{&stage_mem[w][0], 0u};
   BandSink bs{v.band, v.band_cap, v.band_cursor, Stage{&band_mem[w][0], 0u}};
   uint64_t n_recheck = 0;
-  mfma_unit<KP, FMT, SJ_WAVE_QB>(v, wu, st, bs, &nrm_mem[w][0], out, capacity, cursor, n_recheck);
+  mfma_unit<KP, FMT, SJ_WAVE_QB, HM>(v, wu, st, bs, &nrm_mem[w][0], out, capacity, cursor,
+                                     n_recheck);
   flush(st, out, capacity, cursor);
   if (bs.buf) flush(bs.st, bs.buf, bs.cap, bs.cursor);
   if (lane_id() == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
@@ -594,7 +671,7 @@ constexpr int kChunk = 64;  // candidate rows per LDS stage (2 MFMA row blocks)
 #endif
 static_assert(kChunk == 64, "the workgroup kernel pipelines exactly two 32-row blocks per chunk");
 
-template <int KP, int FMT, int QB>
+template <int KP, int FMT, int QB, int HM>
 __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
                                                          const WorkUnit *__restrict__ wus,
                                                          uint64_t n_wu, uint64_t *__restrict__ out,
@@ -671,7 +748,10 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   // c0, valid below cend
   auto epilogue = [&](const float16v(&acc)[QB], uint32_t c0,
                       uint32_t cend) __attribute__((always_inline)) {
-    if (ballot(tiles_any<QB>(acc, th))) {
+    if constexpr (HM == kHitsFrequent) {
+      tiles_hits_scan<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
+                          n_recheck);
+    } else if (ballot(tiles_any<QB>(acc, th))) {
       if constexpr (KP > SJ_HIT_ACC_ABOVE_KP)
         tiles_hits_acc<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
                            n_recheck);
@@ -946,12 +1026,23 @@ void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   if (!grid) return;
   constexpr int QB = KP <= 64 ? SJ_WG_QB_SMALL : SJ_WG_QB_LARGE;
   MfmaView v = a.view;
-  if (a.per_wave)  // one wave per work unit
-    hipLaunchKernelGGL((k_join_mfma_wave<KP, FMT>), dim3(grid), dim3(kBlock), 0, s, v, a.wu,
-                       a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
-  else  // one workgroup per work unit (4 waves x 32*QB queries)
-    hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB>), dim3((uint32_t)a.n_wu), dim3(kBlock), 0, s,
-                       v, a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
+  if (a.per_wave) {  // one wave per work unit
+    if (a.hits_frequent)
+      hipLaunchKernelGGL((k_join_mfma_wave<KP, FMT, kHitsFrequent>), dim3(grid), dim3(kBlock), 0,
+                         s, v, a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
+    else
+      hipLaunchKernelGGL((k_join_mfma_wave<KP, FMT, kHitsRare>), dim3(grid), dim3(kBlock), 0, s,
+                         v, a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
+  } else {  // one workgroup per work unit (4 waves x 32*QB queries)
+    if (a.hits_frequent)
+      hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB, kHitsFrequent>), dim3((uint32_t)a.n_wu),
+                         dim3(kBlock), 0, s, v, a.wu, a.n_wu, a.out, a.capacity, a.cursor,
+                         a.rechecks);
+    else
+      hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB, kHitsRare>), dim3((uint32_t)a.n_wu),
+                         dim3(kBlock), 0, s, v, a.wu, a.n_wu, a.out, a.capacity, a.cursor,
+                         a.rechecks);
+  }
   SJ_HIP(hipGetLastError());
 }
 

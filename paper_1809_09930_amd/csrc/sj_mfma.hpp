@@ -48,6 +48,7 @@ struct MfmaLaunch {
   uint64_t capacity;
   unsigned long long *cursor, *rechecks;
   int per_wave;  // 1: one wave per work unit (units of mfma_wave_queries())
+  int hits_frequent;  // 1: most tiles hold a result or band pair (no per-tile minimum first)
 };
 
 // One job of a batched launch.

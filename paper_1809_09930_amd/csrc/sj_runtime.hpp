@@ -256,6 +256,7 @@ struct sj_index {
   DevBuf band;                  // deferred recheck list of the matrix-core join
   uint64_t band_cap = 0;
   uint64_t band_hint = 0;       // its expected size from the sampled count
+  double hit_density = 0.0;     // result + band pairs per evaluated pair of the sampled count
   bool norm_form = false;       // FP32 filter in norm form
   DevBuf norm_qa, norm_cr;      // its per-point tables
   DevBuf wu_m;
@@ -303,6 +304,10 @@ MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist,
 // join) far too small, so the device-side overflow detection and the
 // resize-and-rerun paths are exercised.
 bool debug_undersize();
+// Test hook: SJ_DEBUG_HITS=0 or 1 forces the hit mode of the matrix-core
+// single-join kernels (rare: per-tile minimum first; frequent: element scan)
+// instead of the choice from the sampled count; -1 when unset.
+int debug_hits_mode();
 
 template <typename F>
 int guarded(F &&f) {

@@ -700,3 +700,42 @@ def test_mem_budget_forces_batches(prec):
     eps = calibrated(P, 30)
     info = assert_same_as_oracle(P, eps, precision=prec, mem_budget=20 * 4000)
     assert info["batches"] >= 3 and info["result_on_host"] == 1
+
+
+@pytest.mark.parametrize("mode", ["0", "1"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_matrix_core_hit_modes(mode, prec, monkeypatch):
+    """Both hit paths of the matrix-core kernels (per-tile minimum first, or
+    the direct element scan the build picks when most tiles hold a hit),
+    forced on the same inputs: clustered small cells (per-wave units),
+    uniform data (workgroup units), off-grid partners at eps, a query join."""
+    monkeypatch.setenv("SJ_DEBUG_HITS", mode)
+    std = datagen.decaying_std(18, 0.2, 0.002, 11)
+    P = datagen.gaussian_mixture(5000, 18, 20, std, 11)
+    assert_same_as_oracle(P, calibrated(P, 30), precision=prec)
+    P = datagen.uniform_grid(3000, 16, 1)
+    assert_same_as_oracle(P, calibrated(P, 32), precision=prec)
+    P = datagen.uniform_grid(1500, 64, 4)
+    assert_same_as_oracle(P, calibrated(P, 16), precision=prec)
+    base = datagen.offgrid("mixture_f32", 1500, 24, 5)
+    eps = calibrated(base, 8)
+    P = np.concatenate([base, datagen.partners_near_radius(base, eps, 700, 6)])
+    assert assert_same_as_oracle(P, eps, precision=prec)["rechecks"] > 0
+    from paper_1809_09930_amd import selfjoin as sj
+    E = datagen.offgrid("normal_binades", 3000, 10, 7)
+    Q = np.concatenate([E[:500], datagen.partners_near_radius(E, 0.3, 600, 8)])
+    he = sj.selfjoin_build_index(torch.from_numpy(E).cuda(), 0.3, precision=prec)
+    try:
+        hq = sj.selfjoin_build_query(he, torch.from_numpy(Q).cuda())
+        try:
+            total = sj.selfjoin_run(hq)
+            gi = torch.empty(total, dtype=torch.int32, device="cuda")
+            gj = torch.empty(total, dtype=torch.int32, device="cuda")
+            sj.selfjoin_fetch_pairs(hq, 0, gi, gj, None, max_pairs=total)
+        finally:
+            sj.selfjoin_free(hq)
+    finally:
+        sj.selfjoin_free(he)
+    oi, oj = oracle.join(Q, E, 0.3)
+    assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
