@@ -996,18 +996,23 @@ MfmaView mfma_view(const sj_index &ix, const uint2 *runs, const uint32_t *qlist,
   v.symmetric = sym;
   v.pshift = 32;
   v.key_hi = 0;
+  v.hi = ix.hi32;
+  v.pad_row = (uint32_t)E.n;  // rows n .. n_pad-1: zero operands, norm +inf
   return v;
 }
 
 // One launch of the distance kernel over a set of work units.
 bool debug_undersize();
 int debug_hits_mode();
+int debug_box_mode();
 uint64_t read_counter(sj_index &ix, int which, hipStream_t s);
 constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
-#ifndef SJ_FREQUENT_HITS_PER_TILE
-#define SJ_FREQUENT_HITS_PER_TILE 0.5
-#endif
-constexpr double kFrequentHitsPerTile = SJ_FREQUENT_HITS_PER_TILE;
+// result + band pairs per 32 x 32 tile above which the matrix-core kernels
+// scan tile elements directly instead of testing each tile's minimum first
+constexpr double kFrequentHitsNarrow = 0.2;  // K padding <= 48 (mask hit path)
+constexpr double kFrequentHitsWide = 0.05;   // K padding > 48 (accumulator hit path)
+constexpr uint32_t kBoxMaxDims = 32;  // dimensions up to which workgroup units use the box
+constexpr double kBoxMaxHitsPerTile = 0.1;  // and hits per 32 x 32 tile below which
 
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
                  const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
@@ -1053,9 +1058,18 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     m.cursor = a.cursor;
     m.rechecks = a.rechecks;
     m.per_wave = ix.mfma_per_wave ? 1 : 0;
-    // more than about one hit per two 32 x 32 tiles: scan elements directly
-    m.hits_frequent = ix.hit_density * 1024.0 > kFrequentHitsPerTile ? 1 : 0;
+    // tiles with a hit common enough: scan elements directly (measured
+    // break-even: about one hit per five 32 x 32 tiles against the mask
+    // path of K <= 48, one per twenty against the accumulator path above)
+    const double per_tile = ix.hit_density * 1024.0;
+    m.hits_frequent = per_tile > (ix.kp > 48 ? kFrequentHitsWide : kFrequentHitsNarrow) ? 1 : 0;
     if (const int forced = debug_hits_mode(); forced >= 0) m.hits_frequent = forced;
+    // the query-box prefilter pays where 8 dimensions are a good part of
+    // the distance (the bound uses the first 8 of the variance order) and
+    // most candidates are far (measured: 2M x 16 uniform FP16 joins 25 % and
+    // 13 % faster at 0.004 and 0.03 hits per tile, 15 % slower at 0.26)
+    m.box = !m.per_wave && ix.d <= kBoxMaxDims && per_tile < kBoxMaxHitsPerTile ? 1 : 0;
+    if (const int forced = debug_box_mode(); forced >= 0) m.box = m.per_wave ? 0 : forced;
     if (count_only) {
       launch_join_mfma(m, s);  // band pairs rechecked in place
     } else {
@@ -1443,6 +1457,11 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   }
   SJ_HIP(hipStreamSynchronize(s));
   *n_written = cnt;
+}
+
+int debug_box_mode() {
+  const char *v = std::getenv("SJ_DEBUG_BOX");
+  return v && (v[0] == '0' || v[0] == '1') ? v[0] - '0' : -1;
 }
 
 int debug_hits_mode() {

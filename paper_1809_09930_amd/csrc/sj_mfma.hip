@@ -824,6 +824,309 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
 }
 
+// Hit path of QB tiles whose 32 rows are the positions rows[0 .. nrows)
+// (rows past nrows are padding with norm +inf): as tiles_hits_scan, with each
+// hit's candidate position read from the row table.
+template <int QB>
+__device__ __forceinline__ void tiles_hits_rows(const float16v (&acc)[QB], const float (&th)[QB],
+                                                const float (&tl)[QB],
+                                                const uint32_t (&qpos)[QB],
+                                                const uint32_t *__restrict__ rows, uint32_t nrows,
+                                                uint32_t half, const MfmaView &v, Stage &st,
+                                                BandSink &bs, uint64_t *__restrict__ out,
+                                                uint64_t capacity,
+                                                unsigned long long *__restrict__ cursor,
+                                                uint64_t &n_recheck) {
+  const bool sym = v.symmetric != 0;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint64_t hm[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) hm[i] = ballot(acc[j][4 * g + i] <= th[j]);
+      if ((hm[0] | hm[1] | hm[2] | hm[3]) == 0) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (hm[i] == 0) continue;
+        const uint32_t ri = (uint32_t)(8 * g + i) + 4u * half;
+        const bool live = ri < nrows;
+        const uint32_t cp = rows[live ? ri : 0u];
+        const bool ok = acc[j][4 * g + i] <= th[j] && live && (!sym || qpos[j] <= cp);
+        bool acc_ok = ok && acc[j][4 * g + i] <= tl[j];
+        const bool band = ok && !acc_ok;
+        const uint64_t bm = ballot(band);
+        if (bm) {
+          if (bs.buf) {
+            const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
+            if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
+            if (band)
+              bs.st.buf[bs.st.cnt + lanes_below(bm)] =
+                  v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+            bs.st.cnt += nb;
+          } else {
+            if (band)
+              acc_ok = canonical_within(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
+            n_recheck += (uint64_t)__builtin_popcountll(bm);
+          }
+        }
+        const uint64_t am = ballot(acc_ok);
+        if (am == 0) continue;
+        const bool two = acc_ok && sym && qpos[j] != cp;
+        const uint64_t m2 = ballot(two);
+        const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+        if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
+        const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+        if (acc_ok) {
+          st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
+          if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
+        }
+        st.cnt += total;
+      }
+    }
+  }
+}
+
+// The workgroup kernel with the query-box prefilter.  The workgroup's
+// queries span a box over the first kBoxDims dimensions (FP32 rows, the
+// variance order).  The unit's candidate positions are tested 256 at a time
+// (one per thread): the squared distance from a candidate to the box bounds
+// its squared distance to every query of the workgroup from below, and in
+// FP32 the bound is a sum of at most dp rounded squares, within the error
+// the FP32 reject threshold `hi` allows for, so a candidate whose bound
+// exceeds `hi` is rejected for all of them.  Survivors enter a ring of
+// positions in LDS; each chunk of the matrix tiles takes the next 64 of
+// them (gathered rows, positions kept beside the rows), so the tiles hold
+// only candidates that can be within eps of some query.  The rows of the
+// next chunk are fetched during the tiles of the current one, as in
+// k_join_mfma_wg.
+constexpr int kBoxDims = 8;
+constexpr uint32_t kRing = 512;  // >= 127 pending + one window of 256
+
+template <int KP, int FMT, int QB, int HM>
+__global__ __launch_bounds__(kBlock) void k_join_mfma_wg_box(MfmaView v,
+                                                             const WorkUnit *__restrict__ wus,
+                                                             uint64_t n_wu,
+                                                             uint64_t *__restrict__ out,
+                                                             uint64_t capacity,
+                                                             unsigned long long *__restrict__ cursor,
+                                                             unsigned long long *__restrict__ rechecks) {
+  typedef typename Fmt<FMT>::V8 V8;
+  constexpr int KS = KP / 16;
+  constexpr int RV = KP / 8;
+  constexpr int CHUNK_VECS = kChunk * RV;
+  constexpr int PER_THREAD = (CHUNK_VECS + kBlock - 1) / kBlock;
+  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  __shared__ V8 tile[2][CHUNK_VECS];
+  __shared__ __align__(16) float tile_n[2][kChunk];
+  __shared__ uint32_t tile_pos[2][kChunk];
+  __shared__ uint64_t band_mem[kWavesPerBlock][kBandStage];
+  __shared__ uint32_t ring[kRing];
+  __shared__ float wbox[kWavesPerBlock][2 * kBoxDims];
+  __shared__ uint32_t wcnt[kWavesPerBlock];
+  const uint64_t u = blockIdx.x;
+  if (u >= n_wu) return;  // whole workgroup leaves together
+  const WorkUnit wu = wus[u];
+  const uint32_t w = uniform_u32(threadIdx.x / kWave);
+  const uint32_t l = lane_id();
+  const uint32_t half = l >> 5, col = l & 31;
+  const V8 *__restrict__ XA = static_cast<const V8 *>(v.XA);
+  const V8 *__restrict__ XB = static_cast<const V8 *>(v.XB);
+
+  // this wave's query columns, and their part of the box
+  V8 B[QB][KS];
+  float th[QB], tl[QB];
+  uint32_t qpos[QB];
+  float blo[kBoxDims], bhi[kBoxDims];
+#pragma unroll
+  for (int t = 0; t < kBoxDims; ++t) {
+    blo[t] = __builtin_inff();
+    bhi[t] = -__builtin_inff();
+  }
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    const uint32_t slot = wu.q0 + (w * QB + (uint32_t)j) * 32 + col;
+    const bool live = slot < wu.q1;
+    const uint32_t p = live ? (v.qlist ? v.qlist[slot] : slot) : 0u;
+    qpos[j] = live ? p : 0xffffffffu;
+    th[j] = live ? v.thi[p] : -__builtin_inff();
+    tl[j] = live ? v.tlo[p] : -__builtin_inff();
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) B[j][ks] = XB[(uint64_t)p * RV + ks * 2 + half];
+    const float4 *qr = reinterpret_cast<const float4 *>(v.Xq + (uint64_t)p * v.dp);
+#pragma unroll
+    for (int t4 = 0; t4 < kBoxDims / 4; ++t4) {
+      const float4 x = qr[t4];
+      const float xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (live) {
+          blo[4 * t4 + i] = __builtin_fminf(blo[4 * t4 + i], xv[i]);
+          bhi[4 * t4 + i] = __builtin_fmaxf(bhi[4 * t4 + i], xv[i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kBoxDims; ++t) {
+    float a = blo[t], b = bhi[t];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a = __builtin_fminf(a, __shfl_xor(a, off));
+      b = __builtin_fmaxf(b, __shfl_xor(b, off));
+    }
+    if (l == 0) {
+      wbox[w][t] = a;
+      wbox[w][kBoxDims + t] = b;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kBoxDims; ++t) {
+    float a = wbox[0][t], b = wbox[0][kBoxDims + t];
+#pragma unroll
+    for (int i = 1; i < kWavesPerBlock; ++i) {
+      a = __builtin_fminf(a, wbox[i][t]);
+      b = __builtin_fmaxf(b, wbox[i][kBoxDims + t]);
+    }
+    blo[t] = __builtin_bit_cast(float, uniform_u32(__builtin_bit_cast(uint32_t, a)));
+    bhi[t] = __builtin_bit_cast(float, uniform_u32(__builtin_bit_cast(uint32_t, b)));
+  }
+  const float hi = v.hi;
+  Stage st{&stage_mem[w][0], 0u};
+  BandSink bs{v.band, v.band_cap, v.band_cursor, Stage{&band_mem[w][0], 0u}};
+  uint64_t n_recheck = 0;
+
+  // candidate stream (uniform over the workgroup) and the ring of survivors
+  uint32_t r = wu.run_first, c = wu.c_begin;
+  uint32_t ce = (r == wu.run_last) ? wu.c_end : v.runs[r].y;
+  auto normalise = [&]() {
+    while (c >= ce && r < wu.run_last) {
+      ++r;
+      c = v.runs[r].x;
+      ce = (r == wu.run_last) ? wu.c_end : v.runs[r].y;
+    }
+  };
+  normalise();
+  uint32_t head = 0, tail = 0;  // ring positions (uniform; differ by <= 383)
+  // test windows until at least `want` survivors wait or the stream ends
+  auto fill = [&](uint32_t want) __attribute__((always_inline)) {
+    while (tail - head < want && c < ce) {
+      const uint32_t wl = ce - c < (uint32_t)kBlock ? ce - c : (uint32_t)kBlock;
+      const uint32_t p = c + threadIdx.x;
+      const bool valid = threadIdx.x < wl;
+      const float4 *xr = reinterpret_cast<const float4 *>(v.X + (uint64_t)(valid ? p : c) * v.dp);
+      float lb = 0.0f;
+#pragma unroll
+      for (int t4 = 0; t4 < kBoxDims / 4; ++t4) {
+        const float4 x = xr[t4];
+        const float xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float g = __builtin_fmaxf(
+              __builtin_fmaxf(blo[4 * t4 + i] - xv[i], xv[i] - bhi[4 * t4 + i]), 0.0f);
+          lb = __builtin_fmaf(g, g, lb);
+        }
+      }
+      const bool keep = valid && lb <= hi;
+      const uint64_t km = ballot(keep);
+      if (l == 0) wcnt[w] = (uint32_t)__builtin_popcountll(km);
+      __syncthreads();
+      uint32_t before = 0, total = 0;
+#pragma unroll
+      for (int i = 0; i < kWavesPerBlock; ++i) {
+        const uint32_t ci = wcnt[i];
+        before += (uint32_t)i < w ? ci : 0u;
+        total += ci;
+      }
+      if (keep) ring[(tail + before + lanes_below(km)) % kRing] = p;
+      __syncthreads();  // the ring is read and wcnt rewritten after this
+      tail += total;
+      c += wl;
+      normalise();
+    }
+  };
+  V8 pre[PER_THREAD];
+  float pre_n = 0.0f;
+  uint32_t pre_p = 0;
+  // rows [head, head + nr) of the ring into registers (padding rows past nr)
+  auto gather = [&](uint32_t nr) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
+      if (e < (uint32_t)CHUNK_VECS) {
+        const uint32_t rr = e / RV;
+        const uint32_t pos = rr < nr ? ring[(head + rr) % kRing] : v.pad_row;
+        pre[i] = XA[(uint64_t)pos * RV + e % RV];
+      }
+    }
+    if (threadIdx.x < (uint32_t)kChunk) {
+      const uint32_t rr = threadIdx.x;
+      pre_p = rr < nr ? ring[(head + rr) % kRing] : v.pad_row;
+      pre_n = v.cn[pre_p];
+    }
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
+      if (e < (uint32_t)CHUNK_VECS) tile[buf][e] = pre[i];
+    }
+    if (threadIdx.x < (uint32_t)kChunk) {
+      tile_n[buf][threadIdx.x] = pre_n;
+      tile_pos[buf][threadIdx.x] = pre_p;
+    }
+  };
+  auto block_mfma = [&](int buf, int blk, float16v(&acc)[QB]) __attribute__((always_inline)) {
+    V8 A[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RV + ks * 2 + half];
+    const float16v c0 = norm_init(&tile_n[buf][blk * 32], half);
+#pragma unroll
+    for (int j = 0; j < QB; ++j) {
+      acc[j] = Fmt<FMT>::mfma(A[0], B[j][0], c0);
+#pragma unroll
+      for (int ks = 1; ks < KS; ++ks) acc[j] = Fmt<FMT>::mfma(A[ks], B[j][ks], acc[j]);
+    }
+  };
+
+  fill(kChunk);
+  uint32_t ncur = tail - head < (uint32_t)kChunk ? tail - head : (uint32_t)kChunk;
+  if (ncur == 0) return;  // every candidate rejected by the box (uniform)
+  gather(ncur);
+  store(0);
+  head += ncur;
+  __syncthreads();
+  int cur = 0;
+  for (;;) {
+    fill(kChunk);
+    const uint32_t nn = tail - head < (uint32_t)kChunk ? tail - head : (uint32_t)kChunk;
+    if (nn) gather(nn);  // in flight during the tiles below
+#pragma nounroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const uint32_t nb = ncur > 32u * (uint32_t)blk ? ncur - 32u * (uint32_t)blk : 0u;
+      if (nb == 0) break;
+      float16v acc[QB];
+      block_mfma(cur, blk, acc);
+      bool any = true;
+      if constexpr (HM != kHitsFrequent) any = ballot(tiles_any<QB>(acc, th)) != 0;
+      if (any)
+        tiles_hits_rows<QB>(acc, th, tl, qpos, &tile_pos[cur][blk * 32],
+                            nb < 32u ? nb : 32u, half, v, st, bs, out, capacity, cursor,
+                            n_recheck);
+    }
+    if (!nn) break;
+    store(cur ^ 1);
+    head += nn;
+    __syncthreads();
+    cur ^= 1;
+    ncur = nn;
+  }
+  if (bs.buf) flush(bs.st, bs.buf, bs.cap, bs.cursor);
+  flush(st, out, capacity, cursor);
+  if (l == 0 && n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
+}
+
 // Deferred FP64 recheck of the band pairs of a launch: one pair per lane,
 // all lanes busy, instead of the few band lanes of one tile element at a
 // time.  Accepted pairs are staged and appended like the join's own.
@@ -1020,6 +1323,9 @@ __global__ __launch_bounds__(kBlock) void k_pos_to_id(uint64_t *__restrict__ key
   }
 }
 
+// K padding up to which the workgroup kernel has the query-box form
+constexpr int kBoxMaxKp = 32;
+
 template <int KP, int FMT>
 void launch_kp(const MfmaLaunch &a, hipStream_t s) {
   const uint32_t grid = (uint32_t)((a.n_wu + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -1033,6 +1339,17 @@ void launch_kp(const MfmaLaunch &a, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_join_mfma_wave<KP, FMT, kHitsRare>), dim3(grid), dim3(kBlock), 0, s,
                          v, a.wu, a.n_wu, a.out, a.capacity, a.cursor, a.rechecks);
+  } else if (KP <= kBoxMaxKp && a.box) {  // one workgroup per unit, query-box prefilter
+    if constexpr (KP <= kBoxMaxKp) {
+      if (a.hits_frequent)
+        hipLaunchKernelGGL((k_join_mfma_wg_box<KP, FMT, QB, kHitsFrequent>),
+                           dim3((uint32_t)a.n_wu), dim3(kBlock), 0, s, v, a.wu, a.n_wu, a.out,
+                           a.capacity, a.cursor, a.rechecks);
+      else
+        hipLaunchKernelGGL((k_join_mfma_wg_box<KP, FMT, QB, kHitsRare>), dim3((uint32_t)a.n_wu),
+                           dim3(kBlock), 0, s, v, a.wu, a.n_wu, a.out, a.capacity, a.cursor,
+                           a.rechecks);
+    }
   } else {  // one workgroup per work unit (4 waves x 32*QB queries)
     if (a.hits_frequent)
       hipLaunchKernelGGL((k_join_mfma_wg<KP, FMT, QB, kHitsFrequent>), dim3((uint32_t)a.n_wu),

@@ -36,6 +36,11 @@ struct MfmaView {
   uint64_t *band;
   uint64_t band_cap;
   unsigned long long *band_cursor;
+  // Query-box prefilter of the workgroup kernel: `hi` is the FP32 reject
+  // threshold of a sum of at most dp squared differences (the FP32
+  // filter's); pad_row is a candidate row with zero operands and norm +inf.
+  float hi;
+  uint32_t pad_row;
 };
 
 struct MfmaLaunch {
@@ -49,6 +54,7 @@ struct MfmaLaunch {
   unsigned long long *cursor, *rechecks;
   int per_wave;  // 1: one wave per work unit (units of mfma_wave_queries())
   int hits_frequent;  // 1: most tiles hold a result or band pair (no per-tile minimum first)
+  int box;            // workgroup units: candidates tested against the query box first
 };
 
 // One job of a batched launch.

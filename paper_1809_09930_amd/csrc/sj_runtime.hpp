@@ -308,6 +308,9 @@ bool debug_undersize();
 // single-join kernels (rare: per-tile minimum first; frequent: element scan)
 // instead of the choice from the sampled count; -1 when unset.
 int debug_hits_mode();
+// Test hook: SJ_DEBUG_BOX=0 or 1 switches the query-box prefilter of the
+// matrix-core workgroup kernel off or on (default: on up to 32 dimensions).
+int debug_box_mode();
 
 template <typename F>
 int guarded(F &&f) {

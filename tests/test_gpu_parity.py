@@ -739,3 +739,44 @@ def test_matrix_core_hit_modes(mode, prec, monkeypatch):
     oi, oj = oracle.join(Q, E, 0.3)
     assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
     assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
+
+
+@pytest.mark.parametrize("box", ["0", "1"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_matrix_core_query_box(box, prec, monkeypatch):
+    """The workgroup matrix-core kernel with its query-box prefilter off and
+    on, in both hit modes: uniform data (every cell adjacent), grid data and
+    off-grid data with partners at eps, d from 2 to 32, the symmetric self-join,
+    several batches and a query join."""
+    from paper_1809_09930_amd import selfjoin as sj
+    monkeypatch.setenv("SJ_DEBUG_BOX", box)
+    for mode in ("0", "1"):
+        monkeypatch.setenv("SJ_DEBUG_HITS", mode)
+        for n, d, seed, target in ((4000, 16, 31, 8), (3000, 2, 32, 20), (2500, 32, 33, 12),
+                                   (1999, 8, 34, 40)):
+            P = datagen.uniform_grid(n, d, seed)
+            assert_same_as_oracle(P, calibrated(P, target), precision=prec)
+        base = datagen.offgrid("uniform64", 2500, 12, 35)
+        eps = calibrated(base, 6)
+        P = np.concatenate([base, datagen.partners_near_radius(base, eps, 800, 36)])
+        assert assert_same_as_oracle(P, eps, precision=prec)["rechecks"] > 0
+    assert_same_as_oracle(datagen.uniform_grid(3000, 16, 37), 0.55, precision=prec,
+                          batch_pairs=6000)
+    E = datagen.offgrid("uniform64", 5000, 16, 38)
+    Q = np.concatenate([datagen.offgrid("uniform64", 1200, 16, 39),
+                        datagen.partners_near_radius(E, 0.5, 500, 40)])
+    he = sj.selfjoin_build_index(torch.from_numpy(E).cuda(), 0.5, precision=prec)
+    try:
+        hq = sj.selfjoin_build_query(he, torch.from_numpy(Q).cuda())
+        try:
+            total = sj.selfjoin_run(hq)
+            gi = torch.empty(total, dtype=torch.int32, device="cuda")
+            gj = torch.empty(total, dtype=torch.int32, device="cuda")
+            sj.selfjoin_fetch_pairs(hq, 0, gi, gj, None, max_pairs=total)
+        finally:
+            sj.selfjoin_free(hq)
+    finally:
+        sj.selfjoin_free(he)
+    oi, oj = oracle.join(Q, E, 0.5)
+    assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
+    assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
