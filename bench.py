@@ -626,10 +626,12 @@ def main():
     head, flops, tjoin = summarise(P, recs, elapsed, a.steps, len(targets), a.precision)
     achieved = flops / tjoin / 1e12 if tjoin > 0 else 0.0
     cand = sum(r[3]["candidates"] for r in recs)
-    # algorithmic HBM bytes of one join launch (one epsilon): the points once
-    # and 8 bytes per emitted pair
-    mean_pairs = float(np.mean([r[2] for r in recs]))
-    alg_bytes = n * d * 4 + mean_pairs * 8
+    # algorithmic HBM bytes of one join launch: the points once and 8 bytes
+    # per emitted pair, at the epsilon the traffic counters were taken at
+    # (the middle target of the sweep)
+    mid_t = targets[len(targets) // 2]
+    mid_pairs = next(r[2] for r in recs if r[0] == mid_t)
+    alg_bytes = n * d * 4 + mid_pairs * 8
     traffic = traffic_for_join() if fp32 and a.workload == "uniform_2m_d16" else None
     out = {
         "metric": "candidate distance evals/s (exact pair set)",
@@ -661,7 +663,8 @@ def main():
                      "kernel": "k_join_fp32" if fp32 else "k_join_mfma",
                      "mean_launch_ms": head["mean_join_launch_ms"],
                      "algorithmic_bytes": alg_bytes,
-                     "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None},
+                     "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None,
+                     "traffic_epsilon": eps_list[len(targets) // 2]},
     }
     if fp32:
         out["roofline"]["peak_nonpacked"] = PEAK_FP32_NONPACKED_TFLOPS

@@ -82,18 +82,18 @@ static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 flo
 #ifndef SJ_FP32_RQ_MID
 #define SJ_FP32_RQ_MID 1    // dp <= 64
 #endif
-// candidate loop: 0 plain, 1 with a one-candidate look-ahead of the first
-// test's values, 2 the same unrolled by two
-#ifndef SJ_SWEEP_MODE
-#define SJ_SWEEP_MODE 1
-#endif
-// Query-box prefilter: 1 = candidates are first tested in batches of 64
-// (one per lane) against the bounding box of the wave's queries over the
-// first kBoxDims dimensions, and only those whose lower bound on the
-// squared distance to the box passes `hi` are evaluated query by query
+// Query-box prefilter up to 32 padded dimensions: candidates are first
+// tested in batches of 64 (one per lane) against the bounding box of the
+// wave's queries over the first kBoxDims dimensions, and only those whose
+// lower bound on the squared distance to the box passes `hi` are evaluated
+// query by query.  Above 32 dimensions the first 8 hold too little of the
+// distance to reject anything (2M x 64 and 515k x 90: 5 and 14 % slower
+// with the test), so candidates are swept one by one.
 #ifndef SJ_BOX_FILTER
 #define SJ_BOX_FILTER 1
 #endif
+template <int DP>
+constexpr bool kBoxOn = SJ_BOX_FILTER && DP <= 32;
 // the same for the norm form
 #ifndef SJ_NORM_RQ_SMALL
 #define SJ_NORM_RQ_SMALL 4
@@ -401,9 +401,8 @@ __device__ __forceinline__ void join_body(
     }
   }
   // the box of the wave's live queries, made wave-uniform (scalar registers)
-#if SJ_BOX_FILTER
 #pragma unroll
-  for (int t = 0; t < NB; ++t) {
+  for (int t = 0; t < (kBoxOn<DP> ? NB : 0); ++t) {
     float a = blo[t], b = bhi[t];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -413,7 +412,6 @@ __device__ __forceinline__ void join_body(
     blo[t] = __builtin_bit_cast(float, uniform_u32(__builtin_bit_cast(uint32_t, a)));
     bhi[t] = __builtin_bit_cast(float, uniform_u32(__builtin_bit_cast(uint32_t, b)));
   }
-#endif
   // in symmetric contiguous mode candidates below q1 need the per-lane
   // "query position <= candidate position" filter; beyond it all pass
   const uint32_t filt_end = (symmetric && !qlist) ? wu.q1 : 0u;
@@ -449,82 +447,62 @@ __device__ __forceinline__ void join_body(
         crow += DP;
         if (kNorm) ccr += NR;
       };
-#if SJ_SWEEP_MODE == 2
-      // two heads in alternation, so a look-ahead never overwrites the head
-      // in use
-      Head<DP, kNorm> h0 = load_head<DP, kNorm>(crow, ccr), h1;
-      uint32_t c = from;
-      for (;;) {
-        h1 = load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
-        eval(h0, c);
-        if (++c >= to) break;
-        next();
-        h0 = load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
-        eval(h1, c);
-        if (++c >= to) break;
-        next();
-      }
-#elif SJ_BOX_FILTER
-      // batches of 64 candidates: lane l bounds the squared distance from
-      // candidate b0 + l to the query box over the first NB dimensions.
-      // Every query of the box is at least that far (in FP32 the bound is a
-      // sum of at most DP rounded squares, within the error `hi` already
-      // allows for), so a candidate with bound > hi is rejected for all of
-      // them; the others are evaluated in order, the head of the next one
-      // loaded ahead.
-      for (uint32_t b0 = from; b0 < to; b0 += kWave) {
-        const uint32_t cl = b0 + l < to ? b0 + l : b0;
-        const float4 *brow = reinterpret_cast<const float4 *>(X + (uint64_t)cl * DP);
-        float lb = 0.0f;
+      if constexpr (kBoxOn<DP>) {
+        // batches of 64 candidates: lane l bounds the squared distance from
+        // candidate b0 + l to the query box over the first NB dimensions.
+        // Every query of the box is at least that far (in FP32 the bound is a
+        // sum of at most DP rounded squares, within the error `hi` already
+        // allows for), so a candidate with bound > hi is rejected for all of
+        // them; the others are evaluated in order, the head of the next one
+        // loaded ahead.
+        for (uint32_t b0 = from; b0 < to; b0 += kWave) {
+          const uint32_t cl = b0 + l < to ? b0 + l : b0;
+          const float4 *brow = reinterpret_cast<const float4 *>(X + (uint64_t)cl * DP);
+          float lb = 0.0f;
 #pragma unroll
-        for (int t4 = 0; t4 < NB / 4; ++t4) {
-          const float4 v = brow[t4];
-          const float vv[4] = {v.x, v.y, v.z, v.w};
+          for (int t4 = 0; t4 < NB / 4; ++t4) {
+            const float4 v = brow[t4];
+            const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float g = __builtin_fmaxf(
-                __builtin_fmaxf(blo[4 * t4 + i] - vv[i], vv[i] - bhi[4 * t4 + i]), 0.0f);
-            lb = __builtin_fmaf(g, g, lb);
+            for (int i = 0; i < 4; ++i) {
+              const float g = __builtin_fmaxf(
+                  __builtin_fmaxf(blo[4 * t4 + i] - vv[i], vv[i] - bhi[4 * t4 + i]), 0.0f);
+              lb = __builtin_fmaf(g, g, lb);
+            }
           }
-        }
-        uint64_t keep = ballot(b0 + l < to && lb <= hi);
-        if (keep == 0) continue;
-        uint32_t c = b0 + (uint32_t)__builtin_ctzll(keep);
-        keep &= keep - 1;
-        crow = X + (uint64_t)c * DP;
-        if (kNorm) ccr = CR + (uint64_t)c * NR;
-        Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
-        for (;;) {
-          const bool more = keep != 0;
-          const uint32_t cn = more ? b0 + (uint32_t)__builtin_ctzll(keep) : c;
-          Head<DP, kNorm> hn = h;
-          if (more)
-            hn = load_head<DP, kNorm>(X + (uint64_t)cn * DP,
-                                      kNorm ? CR + (uint64_t)cn * NR : nullptr);
-          eval(h, c);
-          if (!more) break;
+          uint64_t keep = ballot(b0 + l < to && lb <= hi);
+          if (keep == 0) continue;
+          uint32_t c = b0 + (uint32_t)__builtin_ctzll(keep);
           keep &= keep - 1;
-          c = cn;
-          h = hn;
           crow = X + (uint64_t)c * DP;
           if (kNorm) ccr = CR + (uint64_t)c * NR;
+          Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
+          for (;;) {
+            const bool more = keep != 0;
+            const uint32_t cn = more ? b0 + (uint32_t)__builtin_ctzll(keep) : c;
+            Head<DP, kNorm> hn = h;
+            if (more)
+              hn = load_head<DP, kNorm>(X + (uint64_t)cn * DP,
+                                        kNorm ? CR + (uint64_t)cn * NR : nullptr);
+            eval(h, c);
+            if (!more) break;
+            keep &= keep - 1;
+            c = cn;
+            h = hn;
+            crow = X + (uint64_t)c * DP;
+            if (kNorm) ccr = CR + (uint64_t)c * NR;
+          }
+        }
+      } else {
+        Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
+        for (uint32_t c = from; c < to; ++c) {
+          const Head<DP, kNorm> hn =
+              load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
+          eval(h, c);
+          h = hn;
+          next();
         }
       }
-      (void)next;
-#elif SJ_SWEEP_MODE == 1
-      Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
-      for (uint32_t c = from; c < to; ++c) {
-        const Head<DP, kNorm> hn = load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
-        eval(h, c);
-        h = hn;
-        next();
-      }
-#else
-      for (uint32_t c = from; c < to; ++c) {
-        eval(load_head<DP, kNorm>(crow, ccr), c);
-        next();
-      }
-#endif
     };
     sweep(cb, mid, std::true_type{});
     sweep(mid, ce, std::false_type{});
