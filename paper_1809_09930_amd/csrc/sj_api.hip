@@ -1011,7 +1011,7 @@ constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
 // scan tile elements directly instead of testing each tile's minimum first
 constexpr double kFrequentHitsNarrow = 0.2;  // K padding <= 48 (mask hit path)
 constexpr double kFrequentHitsWide = 0.05;   // K padding > 48 (accumulator hit path)
-constexpr uint32_t kBoxMaxDims = 32;  // dimensions up to which workgroup units use the box
+constexpr uint32_t kBoxMaxDims = 24;  // dimensions up to which workgroup units use the box
 constexpr double kBoxMaxHitsPerTile = 0.1;  // and hits per 32 x 32 tile below which
 
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,

@@ -82,18 +82,18 @@ static_assert(n_checkpoints(128) + 1 <= 16, "norm table rows hold at most 16 flo
 #ifndef SJ_FP32_RQ_MID
 #define SJ_FP32_RQ_MID 1    // dp <= 64
 #endif
-// Query-box prefilter up to 32 padded dimensions: candidates are first
+// Query-box prefilter up to 24 padded dimensions: candidates are first
 // tested in batches of 64 (one per lane) against the bounding box of the
 // wave's queries over the first kBoxDims dimensions, and only those whose
 // lower bound on the squared distance to the box passes `hi` are evaluated
-// query by query.  Above 32 dimensions the first 8 hold too little of the
-// distance to reject anything (2M x 64 and 515k x 90: 5 and 14 % slower
-// with the test), so candidates are swept one by one.
+// query by query.  Above 24 dimensions the first 8 hold too little of the
+// distance to reject enough (32-D exponential set 44 % slower with the test,
+// 2M x 64 and 515k x 90 5 and 14 %), so candidates are swept one by one.
 #ifndef SJ_BOX_FILTER
 #define SJ_BOX_FILTER 1
 #endif
 template <int DP>
-constexpr bool kBoxOn = SJ_BOX_FILTER && DP <= 32;
+constexpr bool kBoxOn = SJ_BOX_FILTER && DP <= 24;
 // the same for the norm form
 #ifndef SJ_NORM_RQ_SMALL
 #define SJ_NORM_RQ_SMALL 4
