@@ -325,6 +325,28 @@ int selfjoin_batch_get_info(const sj_batch *batch, sj_batch_info *info);
 /* Releases the batch and all its memory.  NULL is ignored. */
 void selfjoin_batch_free(sj_batch *batch);
 
+/* ------------------------------------------------------------------------
+ * Device memory held between calls.
+ *
+ * Device blocks the library frees (result buffers, work lists, sort and
+ * build temporaries) go to a per-device cache once the device has finished
+ * the work queued before the free, and later calls on that device reuse
+ * them instead of calling hipMalloc and hipFree again.  The cache holds at
+ * most a quarter of the device's memory, or SJ_CACHE_BYTES bytes when that
+ * environment variable is set when the device is first used (0: no
+ * caching).  Cached blocks count as free memory for the automatic memory
+ * budget, and an allocation that fails empties the device's cache and is
+ * tried once more; memory that other code of the process wants (a tensor
+ * library's own allocator) is not given back by itself.
+ * ---------------------------------------------------------------------- */
+
+/* Frees every block cached for the current device, and the calling
+ * thread's kept build temporaries.  *released (may be NULL) receives the
+ * cached bytes freed.  Call it with no run of the library in flight on the
+ * device from another thread.  Errors: SJ_ERR_DEVICE when the current
+ * device cannot be read. */
+int selfjoin_release_cache(uint64_t *released);
+
 /* Message of the calling thread's last error ("" if none). */
 const char *selfjoin_last_error(void);
 

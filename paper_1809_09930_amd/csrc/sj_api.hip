@@ -9,7 +9,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -19,6 +21,132 @@
 namespace sj {
 
 thread_local std::string g_last_error;
+
+namespace {
+
+constexpr int kCacheDevices = 64;
+
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> blocks;  // capacity -> block
+  size_t bytes = 0;                      // sum of the cached capacities
+  size_t cap = 0;
+  bool cap_known = false;
+};
+
+BlockCache g_cache[kCacheDevices];
+
+// capacities are rounded so that nearby requests share blocks
+size_t block_round(size_t b) {
+  const size_t g = b < ((size_t)1 << 20) ? 4096 : ((size_t)2 << 20);
+  return (b + g - 1) / g * g;
+}
+
+// cache limit of the current device, read once: SJ_CACHE_BYTES, else a
+// quarter of the device's memory
+size_t cache_cap(BlockCache &c) {
+  if (!c.cap_known) {
+    c.cap_known = true;
+    const char *v = std::getenv("SJ_CACHE_BYTES");
+    if (v && *v) {
+      c.cap = (size_t)std::strtoull(v, nullptr, 10);
+    } else {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        tot = 0;
+      }
+      c.cap = tot / 4;
+    }
+  }
+  return c.cap;
+}
+
+void free_all_locked(BlockCache &c) {
+  for (auto &kv : c.blocks) (void)hipFree(kv.second);
+  c.blocks.clear();
+  c.bytes = 0;
+}
+
+}  // namespace
+
+void *dev_alloc(size_t bytes, size_t *got, int *dev) {
+  int d = 0;
+  SJ_HIP(hipGetDevice(&d));
+  *dev = d;
+  const size_t want = block_round(std::max<size_t>(bytes, 1));
+  if (d >= 0 && d < kCacheDevices) {
+    BlockCache &c = g_cache[d];
+    std::lock_guard<std::mutex> lock(c.mu);
+    // smallest cached block that holds the request and is at most about
+    // twice its size
+    auto it = c.blocks.lower_bound(want);
+    if (it != c.blocks.end() && it->first <= std::max(2 * want, want + ((size_t)1 << 20))) {
+      void *p = it->second;
+      *got = it->first;
+      c.bytes -= it->first;
+      c.blocks.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess && d >= 0 && d < kCacheDevices) {
+    (void)hipGetLastError();
+    BlockCache &c = g_cache[d];
+    {
+      std::lock_guard<std::mutex> lock(c.mu);
+      free_all_locked(c);
+    }
+    e = hipMalloc(&p, want);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(want) + " bytes failed");
+  }
+  *got = want;
+  return p;
+}
+
+void dev_free(void *p, size_t got, int dev) {
+  if (!p) return;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) {
+    (void)hipGetLastError();
+    cur = -1;
+  }
+  if (dev != cur || dev < 0 || dev >= kCacheDevices) {
+    (void)hipFree(p);
+    return;
+  }
+  BlockCache &c = g_cache[dev];
+  std::lock_guard<std::mutex> lock(c.mu);
+  if (got > cache_cap(c) - std::min(c.bytes, cache_cap(c))) {
+    (void)hipFree(p);
+    return;
+  }
+  // the block may still be read or written by queued work on any stream;
+  // the next user may run on another stream
+  if (hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(p);
+    return;
+  }
+  c.blocks.emplace(got, p);
+  c.bytes += got;
+}
+
+size_t dev_cached_bytes(int dev) {
+  if (dev < 0 || dev >= kCacheDevices) return 0;
+  std::lock_guard<std::mutex> lock(g_cache[dev].mu);
+  return g_cache[dev].bytes;
+}
+
+void dev_cache_release(int dev) {
+  if (dev < 0 || dev >= kCacheDevices) return;
+  std::lock_guard<std::mutex> lock(g_cache[dev].mu);
+  free_all_locked(g_cache[dev]);
+}
 
 Scratch &thread_scratch() {
   thread_local Scratch s;
@@ -37,13 +165,10 @@ void *Scratch::take(size_t bytes) {
     ++cur_;
     used_ = 0;
   }
-  const size_t size = std::max<size_t>(b, (size_t)8 << 20);
-  void *p = nullptr;
-  if (hipMalloc(&p, size) != hipSuccess) {
-    (void)hipGetLastError();
-    fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(size) + " bytes failed");
-  }
-  chunks_.push_back({p, size});
+  size_t size = std::max<size_t>(b, (size_t)8 << 20);
+  int dev = 0;
+  void *p = dev_alloc(size, &size, &dev);
+  chunks_.push_back({p, size, dev});
   cur_ = chunks_.size() - 1;
   used_ = b;
   return p;
@@ -58,7 +183,7 @@ void Scratch::release(bool error) {
   // free everything (a free waits for the device)
   const size_t keep = error ? 0 : keep_bytes;
   while (!chunks_.empty() && total > keep) {
-    (void)hipFree(chunks_.back().p);
+    dev_free(chunks_.back().p, chunks_.back().size, chunks_.back().dev);
     total -= chunks_.back().size;
     chunks_.pop_back();
   }
@@ -1169,7 +1294,10 @@ uint64_t default_budget() {
     (void)hipGetLastError();
     return 1ull << 32;
   }
-  return (uint64_t)((double)fr * 0.7);
+  int dev = 0;
+  SJ_HIP(hipGetDevice(&dev));
+  // blocks the library's cache holds are free for this run
+  return (uint64_t)((double)(fr + dev_cached_bytes(dev)) * 0.7);
 }
 
 void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s) {
@@ -1604,6 +1732,17 @@ void selfjoin_free(sj_index *idx) {
     delete idx;
     idx = e;
   }
+}
+
+int selfjoin_release_cache(uint64_t *released) {
+  return sj::guarded([&] {
+    int dev = 0;
+    SJ_HIP(hipGetDevice(&dev));
+    thread_scratch().trim();
+    const size_t b = dev_cached_bytes(dev);
+    dev_cache_release(dev);
+    if (released) *released = b;
+  });
 }
 
 const char *selfjoin_last_error(void) { return sj::g_last_error.c_str(); }

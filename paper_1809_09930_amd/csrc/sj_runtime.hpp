@@ -20,28 +20,42 @@ namespace sj {
 
 extern thread_local std::string g_last_error;
 
+// Device blocks of the library go through a per-device cache: a freed block
+// is kept (after the device has finished all queued work, as hipFree would
+// wait) and handed to the next request of a size it fits without wasting
+// more than half of it.  Repeated joins then allocate nothing, and do not
+// pay the driver's occasional long hipMalloc / hipFree of multi-GB blocks.
+// The cache holds at most a quarter of the device's memory (SJ_CACHE_BYTES
+// overrides; 0 turns caching off); a failed allocation empties the device's
+// cache and tries once more.  dev_alloc returns the block's capacity in
+// *got and its device in *dev.
+void *dev_alloc(size_t bytes, size_t *got, int *dev);
+void dev_free(void *p, size_t got, int dev);
+// bytes held in the cache of device `dev` (idle, reusable by the library)
+size_t dev_cached_bytes(int dev);
+// frees every cached block of device `dev`
+void dev_cache_release(int dev);
+
 // Device allocation owned by a handle.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  size_t got = 0;
+  int dev = 0;
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() { reset(); }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(p, got, dev);
     p = nullptr;
     bytes = 0;
+    got = 0;
   }
   void alloc(size_t b) {
     reset();
     if (b == 0) b = 256;
-    hipError_t e = hipMalloc(&p, b);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      fail(SJ_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(b) + " bytes failed");
-    }
+    p = dev_alloc(b, &got, &dev);
     bytes = b;
   }
   void ensure(size_t b) {
@@ -76,6 +90,7 @@ class Scratch {
   struct Chunk {
     void *p;
     size_t size;
+    int dev;
   };
   std::vector<Chunk> chunks_;
   size_t cur_ = 0, used_ = 0;

@@ -40,7 +40,7 @@ EXPORTED = ("selfjoin_default_options", "selfjoin_build_index", "selfjoin_build_
             "selfjoin_get_perm",
             "selfjoin_free", "selfjoin_last_error", "selfjoin_run_batched",
             "selfjoin_batch_replay", "selfjoin_batch_range", "selfjoin_batch_fetch",
-            "selfjoin_batch_get_info", "selfjoin_batch_free")
+            "selfjoin_batch_get_info", "selfjoin_batch_free", "selfjoin_release_cache")
 
 
 class SjOptions(ctypes.Structure):
@@ -167,6 +167,8 @@ def load_library(path: str = LIB_PATH):
     lib.selfjoin_batch_get_info.restype = ctypes.c_int
     lib.selfjoin_batch_free.argtypes = [vp]
     lib.selfjoin_batch_free.restype = None
+    lib.selfjoin_release_cache.argtypes = [ctypes.POINTER(u64)]
+    lib.selfjoin_release_cache.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -279,6 +281,14 @@ def selfjoin_fetch_offsets_noalloc(handle, offsets, stream=None) -> None:
         raise ValueError("offsets must be contiguous")
     _check(load_library().selfjoin_fetch_offsets_noalloc(handle, offsets.data_ptr(),
                                                          _stream_handle(stream)))
+
+
+def selfjoin_release_cache() -> int:
+    """Free the device blocks the library keeps cached for the current
+    device; returns the bytes freed."""
+    out = ctypes.c_uint64(0)
+    _check(load_library().selfjoin_release_cache(ctypes.byref(out)))
+    return out.value
 
 
 def selfjoin_get_info(handle) -> dict:

@@ -780,3 +780,25 @@ def test_matrix_core_query_box(box, prec, monkeypatch):
     oi, oj = oracle.join(Q, E, 0.5)
     assert np.array_equal(gi.cpu().numpy().view(np.uint32), oi)
     assert np.array_equal(gj.cpu().numpy().view(np.uint32), oj)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_cached_blocks_reused(prec):
+    """Freed device blocks are cached and handed to later runs: a run with
+    many pairs leaves its buffers full of keys, and the smaller and larger
+    runs after it (on the same and on differently sized blocks) must still
+    give the oracle's result; releasing the cache frees what it held, and
+    runs after the release are still exact."""
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.uniform_grid(6000, 12, 91)
+    Q = datagen.offgrid("normal_binades", 3000, 7, 92)
+    big, small = calibrated(P, 120), calibrated(P, 5)
+    sj.selfjoin_release_cache()
+    assert_same_as_oracle(P, big, precision=prec)
+    assert_same_as_oracle(P, small, precision=prec)
+    assert_same_as_oracle(Q, calibrated(Q, 30), precision=prec)
+    assert_same_as_oracle(P, big, precision=prec, batch_pairs=40000)
+    torch.cuda.synchronize()
+    assert sj.selfjoin_release_cache() > 0
+    assert sj.selfjoin_release_cache() == 0
+    assert_same_as_oracle(P, small, precision=prec)
