@@ -141,6 +141,13 @@ int selfjoin_build_index(const float *points, uint64_t n, uint32_t d,
  * The sorted result stays owned by the handle (in device memory when it fits
  * the budget, else in pinned host memory) until selfjoin_free.  Calling it
  * again returns the same total without recomputing.
+ * Batches cover ranges of caller indices in order, so the batches together
+ * hold the result in (i, j) order.  In an FP32 self-join of several
+ * batches each unordered pair is evaluated once: a batch skips candidates
+ * of earlier batches and hands the mirrored pairs of later batches on in
+ * device memory (a spill of about a quarter of |R| at its peak; when the
+ * spill would not fit, or the caller's row order makes it overflow, the
+ * batches run one-directionally instead, with the same result).
  */
 int selfjoin_run(sj_index *idx, void *stream, uint64_t *total_pairs);
 
@@ -169,7 +176,7 @@ typedef struct sj_info {
     uint32_t precision;
     uint64_t n_cells;         /* non-empty grid cells |G| */
     uint64_t candidates;      /* ordered candidate pairs C: sum over points of the sizes of their adjacent non-empty cells */
-    uint64_t evaluated;       /* candidate pairs the distance kernel evaluated (each unordered pair once when tiles are symmetric) */
+    uint64_t evaluated;       /* candidate pairs the distance kernel evaluated (each unordered pair once when tiles are symmetric; about half of the ordered pairs in FP32 multi-batch runs) */
     uint64_t rechecks;        /* pairs sent to the FP64 boundary recheck */
     uint64_t pairs;           /* |R| (valid after run) */
     uint32_t batches;         /* batches used by the last run */
@@ -340,7 +347,9 @@ void selfjoin_batch_free(sj_batch *batch);
  * library's own allocator) is not given back by itself.
  * ---------------------------------------------------------------------- */
 
-/* Frees every block cached for the current device, and the calling
+/* Frees every block cached for the current device, the pinned host blocks
+ * cached for results streamed to the host (SJ_HOST_CACHE_BYTES caps them;
+ * default an eighth of host memory, at most 64 GiB) and the calling
  * thread's kept build temporaries.  *released (may be NULL) receives the
  * cached bytes freed.  Call it with no run of the library in flight on the
  * device from another thread.  Errors: SJ_ERR_DEVICE when the current

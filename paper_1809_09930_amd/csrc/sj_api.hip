@@ -14,7 +14,10 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
+
+#include <unistd.h>
 
 #include "sj_runtime.hpp"
 
@@ -108,7 +111,7 @@ void *dev_alloc(size_t bytes, size_t *got, int *dev) {
   return p;
 }
 
-void dev_free(void *p, size_t got, int dev) {
+void dev_free(void *p, size_t got, int dev, bool idle) {
   if (!p) return;
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess) {
@@ -127,7 +130,7 @@ void dev_free(void *p, size_t got, int dev) {
   }
   // the block may still be read or written by queued work on any stream;
   // the next user may run on another stream
-  if (hipDeviceSynchronize() != hipSuccess) {
+  if (!idle && hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
     (void)hipFree(p);
     return;
@@ -146,6 +149,88 @@ void dev_cache_release(int dev) {
   if (dev < 0 || dev >= kCacheDevices) return;
   std::lock_guard<std::mutex> lock(g_cache[dev].mu);
   free_all_locked(g_cache[dev]);
+}
+
+namespace {
+
+struct HostCache {
+  std::mutex mu;
+  std::multimap<size_t, void *> blocks;
+  size_t bytes = 0;
+  size_t cap = 0;
+  bool cap_known = false;
+};
+
+HostCache g_host_cache;
+
+size_t host_cap(HostCache &c) {
+  if (!c.cap_known) {
+    c.cap_known = true;
+    const char *v = std::getenv("SJ_HOST_CACHE_BYTES");
+    if (v && *v) {
+      c.cap = (size_t)std::strtoull(v, nullptr, 10);
+    } else {
+      const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
+      const size_t ram = pages > 0 && page > 0 ? (size_t)pages * (size_t)page : 0;
+      c.cap = std::min<size_t>(ram / 8, (size_t)64 << 30);
+    }
+  }
+  return c.cap;
+}
+
+}  // namespace
+
+void *host_alloc(size_t bytes, size_t *got) {
+  const size_t want = block_round(std::max<size_t>(bytes, 1));
+  {
+    std::lock_guard<std::mutex> lock(g_host_cache.mu);
+    auto it = g_host_cache.blocks.lower_bound(want);
+    if (it != g_host_cache.blocks.end() &&
+        it->first <= std::max(2 * want, want + ((size_t)1 << 20))) {
+      void *p = it->second;
+      *got = it->first;
+      g_host_cache.bytes -= it->first;
+      g_host_cache.blocks.erase(it);
+      return p;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    host_cache_release();
+    e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(SJ_ERR_OUT_OF_MEMORY, "pinned host allocation of " + std::to_string(want) + " bytes failed");
+  }
+  *got = want;
+  return p;
+}
+
+void host_free(void *p, size_t got) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_host_cache.mu);
+  const size_t cap = host_cap(g_host_cache);
+  if (got > cap - std::min(g_host_cache.bytes, cap)) {
+    (void)hipHostFree(p);
+    return;
+  }
+  g_host_cache.blocks.emplace(got, p);
+  g_host_cache.bytes += got;
+}
+
+size_t host_cached_bytes() {
+  std::lock_guard<std::mutex> lock(g_host_cache.mu);
+  return g_host_cache.bytes;
+}
+
+void host_cache_release() {
+  std::lock_guard<std::mutex> lock(g_host_cache.mu);
+  for (auto &kv : g_host_cache.blocks) (void)hipHostFree(kv.second);
+  g_host_cache.blocks.clear();
+  g_host_cache.bytes = 0;
 }
 
 Scratch &thread_scratch() {
@@ -180,10 +265,11 @@ void Scratch::release(bool error) {
   size_t total = 0;
   for (const Chunk &c : chunks_) total += c.size;
   // after an error, work that used the temporaries may still be queued:
-  // free everything (a free waits for the device)
+  // free everything and wait for the device; otherwise the scope's code has
+  // synchronised every stream that used them
   const size_t keep = error ? 0 : keep_bytes;
   while (!chunks_.empty() && total > keep) {
-    dev_free(chunks_.back().p, chunks_.back().size, chunks_.back().dev);
+    dev_free(chunks_.back().p, chunks_.back().size, chunks_.back().dev, !error);
     total -= chunks_.back().size;
     chunks_.pop_back();
   }
@@ -534,7 +620,7 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
   SJ_HIP(hipStreamSynchronize(s));
   const uint64_t n_wu = (uint32_t)h[0];
   *eval = h[1];
-  out.alloc(n_wu * sizeof(WorkUnit));
+  out.ensure(n_wu * sizeof(WorkUnit));  // kept when it fits: no wait for the device
   if (by_stretch && n_wu > 1) {
     TmpBuf unordered, keys[2], rtmp;
     unordered.alloc(n_wu * sizeof(WorkUnit));
@@ -1141,7 +1227,7 @@ constexpr double kBoxMaxHitsPerTile = 0.1;  // and hits per 32 x 32 tile below w
 
 void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &runs,
                  const uint32_t *qlist, int sym, int count_only, uint64_t *out, uint64_t cap,
-                 hipStream_t s, float *ms) {
+                 hipStream_t s, float *ms, uint32_t skip_below = 0) {
   const sj_index &E = entries_of(ix);  // candidates; ix holds the queries
   JoinLaunch a{};
   a.X = E.X.as<float>();
@@ -1169,6 +1255,8 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
   a.norm = ix.norm_form ? 1 : 0;
   a.QA = ix.norm_qa.as<float>();
   a.CR = E.norm_cr.as<float>();
+  a.skip_below = skip_below;
+  a.skipped = ix.counters.as<unsigned long long>() + 3;
   Event e0, e1;
   SJ_HIP(hipEventRecord(e0.e, s));
   if (ix.prec != SJ_PREC_FP32) {
@@ -1300,13 +1388,15 @@ uint64_t default_budget() {
   return (uint64_t)((double)(fr + dev_cached_bytes(dev)) * 0.7);
 }
 
-void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s) {
+void sort_pairs(sj_index &ix, DevBuf &a, DevBuf &b, uint64_t cnt, hipStream_t s,
+                DevBuf *keep_tmp = nullptr) {
   const uint64_t ne = entries_of(ix).n;
   const uint32_t ibits = bits_for(ix.n ? ix.n - 1 : 0), jbits = bits_for(ne ? ne - 1 : 0);
   std::vector<int> sh, wd;
   digit_plan(jbits, ibits, sh, wd);
-  DevBuf tmp;
-  tmp.alloc(radix_tmp_bytes(cnt));
+  DevBuf own;
+  DevBuf &tmp = keep_tmp ? *keep_tmp : own;  // a caller's buffer outlives the queued sort
+  tmp.ensure(radix_tmp_bytes(cnt));
   uint64_t *kb[2] = {a.as<uint64_t>(), b.as<uint64_t>()};
   radix_sort_u64(kb, nullptr, cnt, sh.data(), (int)sh.size(), tmp.p, s, nullptr, wd.data());
 }
@@ -1351,105 +1441,164 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
   ix.on_host = false;
 }
 
-// Several batches over ranges of caller indices, each a one-directional join
-// of its queries against their adjacent cells, sorted and copied to pinned
-// host memory while the next batch computes (Section 3.2.2, Figure 5).
-void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, hipStream_t s) {
+// The spill of a symmetric batched run overflowed: run one-directionally.
+struct OneWayRetry {};
+
+// Several batches over ranges of caller indices [i0, i1), each sorted and
+// copied to pinned host memory while the next batch computes (Section 3.2.2,
+// Figure 5), through three result slots.  An FP32 self-join takes each
+// unordered pair once (sym): the batch of [i0, i1) skips candidates below i0
+// (their pairs belong to an earlier batch, which took them), keeps (i, j)
+// for j >= i and mirrors it to (j, i), into this batch when j < i1, else
+// into a device spill that the batch holding j takes up.  Other runs
+// (matrix cores, query joins) join a batch's queries against all their
+// candidates.  Buffers live across batches, so that no free in the loop
+// waits for the copies in flight.
+void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, bool sym, hipStream_t s) {
   const uint64_t n = ix.n;
   uint64_t nb = std::max<uint64_t>(1, (est + per_batch - 1) / per_batch);
   nb = std::max<uint64_t>(nb, ix.opt.min_batches ? ix.opt.min_batches : 1);
   nb = std::min<uint64_t>(nb, n);
-  hipStream_t cs = nullptr;
-  SJ_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  constexpr int kSlots = 3;
   struct Slot {
-    DevBuf keys, tmp2;
+    DevBuf keys, other, sort_tmp;
     Event done_copy;
     bool busy = false;
-  } slots[2];
+  } slots[kSlots];
+  struct Copy {
+    hipStream_t cs = nullptr;
+    ~Copy() {
+      if (cs) {
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamDestroy(cs);
+      }
+    }
+  } copy;
+  SJ_HIP(hipStreamCreateWithFlags(&copy.cs, hipStreamNonBlocking));
   ix.host_res.clear();
   ix.host_cnt.clear();
   ix.total = 0;
   ix.info.rechecks = 0;
-  uint64_t evaluated = 0;
+  uint64_t evaluated = 0, skipped = 0;
   float ms_join = 0.0f;
-  std::vector<std::pair<uint64_t, uint64_t>> ranges;
-  for (uint64_t b = 0; b < nb; ++b) ranges.push_back({n * b / nb, n * (b + 1) / nb});
+  const bool mf = ix.prec != SJ_PREC_FP32;
+  // spill of mirrored pairs for later batches: about a quarter of the
+  // result at its peak when caller order is unrelated to position
+  DevBuf spill[2], cnt2;
+  uint64_t spill_n = 0, spill_cap = 0;
+  int sc = 0;
+  if (sym) {
+    spill_cap = est / 4 + est / 8 + (1u << 16);
+    if (debug_undersize()) spill_cap = 16;
+    spill[0].alloc(spill_cap * 8);
+    spill[1].alloc(spill_cap * 8);
+    cnt2.alloc(64);
+  }
   const uint32_t bits = bits_for(n - 1);
+  std::vector<int> qsh;
+  for (uint32_t b = 0; b < bits; b += 8) qsh.push_back((int)b);
+  DevBuf qk[2], rt, p32, wu;
+  std::vector<std::unique_ptr<Event>> sort_ev;  // (start, end) of each sort, read at the end
   uint64_t slot = 0;
-  for (size_t bi = 0; bi < ranges.size(); ++bi) {
-    const uint64_t i0 = ranges[bi].first, i1 = ranges[bi].second;
+  for (uint64_t bi = 0; bi < nb; ++bi) {
+    const uint64_t i0 = n * bi / nb, i1 = n * (bi + 1) / nb;
     if (i1 <= i0) continue;
     const uint64_t nq = i1 - i0;
-    // positions of the batch's queries, ascending
-    DevBuf qk[2], rt;
-    qk[0].alloc(nq * 8);
-    qk[1].alloc(nq * 8);
-    {
-      // positions of the caller indices [i0, i1), sorted on the device
-      std::vector<int> sh;
-      for (uint32_t b = 0; b < bits; b += 8) sh.push_back((int)b);
-      DevBuf p32;
-      p32.alloc(nq * 4);
-      launch_widen(ix.pos_of.as<uint32_t>() + i0, qk[0].as<uint64_t>(), nq, s);
-      rt.alloc(radix_tmp_bytes(nq));
-      uint64_t *kb[2] = {qk[0].as<uint64_t>(), qk[1].as<uint64_t>()};
-      radix_sort_u64(kb, nullptr, nq, sh.data(), (int)sh.size(), rt.p, s);
-      launch_narrow(kb[0], p32.as<uint32_t>(), nq, s);
-      DevBuf wu;
-      uint64_t ev = 0;
-      const bool mf = ix.prec != SJ_PREC_FP32;
-      const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
-                                           ix.runs_full, mf ? ix.tq_single : ix.tq,
-                                           mf ? ix.tc_single : ix.tc, wu, &ev, s, kWuByStretch);
-      evaluated += ev;
-      Slot &sl = slots[slot & 1];
-      if (sl.busy) {
-        SJ_HIP(hipEventSynchronize(sl.done_copy.e));
-        sl.busy = false;
+    // positions of the caller indices [i0, i1), sorted on the device
+    qk[0].ensure(nq * 8);
+    qk[1].ensure(nq * 8);
+    p32.ensure(nq * 4);
+    launch_widen(ix.pos_of.as<uint32_t>() + i0, qk[0].as<uint64_t>(), nq, s);
+    rt.ensure(radix_tmp_bytes(nq));
+    uint64_t *kb[2] = {qk[0].as<uint64_t>(), qk[1].as<uint64_t>()};
+    radix_sort_u64(kb, nullptr, nq, qsh.data(), (int)qsh.size(), rt.p, s);
+    launch_narrow(kb[0], p32.as<uint32_t>(), nq, s);
+    uint64_t ev = 0;
+    const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
+                                         ix.runs_full, mf ? ix.tq_single : ix.tq,
+                                         mf ? ix.tc_single : ix.tc, wu, &ev, s, kWuByStretch);
+    evaluated += ev;
+    Slot &sl = slots[slot % kSlots];
+    if (sl.busy) {
+      SJ_HIP(hipEventSynchronize(sl.done_copy.e));
+      sl.busy = false;
+    }
+    // a batch holds about est / nb pairs (min_batches may ask for more
+    // batches than the budget needs)
+    const uint64_t expect = std::min(per_batch, est / nb + est / nb / 4);
+    uint64_t cap = expect + expect / 8 + (1u << 16);
+    if (debug_undersize()) cap = std::max<uint64_t>(1, expect / 16);
+    uint64_t got = 0;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      sl.keys.ensure(cap * 8);
+      SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 32, s));
+      join_launch(ix, wu, nwu, ix.runs_full, p32.as<uint32_t>(), 0, 0, sl.keys.as<uint64_t>(),
+                  cap, s, &ms_join, sym ? (uint32_t)i0 : 0u);
+      uint64_t c4[4];
+      SJ_HIP(hipMemcpyAsync(c4, ix.counters.p, 32, hipMemcpyDeviceToHost, s));
+      SJ_HIP(hipStreamSynchronize(s));
+      got = c4[0];
+      if (got <= cap) {
+        ix.info.rechecks += c4[1];
+        skipped += c4[3];
+        break;
       }
-      uint64_t cap = per_batch + per_batch / 8 + (1u << 16);
-      if (debug_undersize()) cap = std::max<uint64_t>(1, per_batch / 16);
-      uint64_t got = 0;
-      for (int attempt = 0; attempt < 3; ++attempt) {
-        sl.keys.ensure(cap * 8);
-        SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
-        join_launch(ix, wu, nwu, ix.runs_full, p32.as<uint32_t>(), 0, 0, sl.keys.as<uint64_t>(),
-                    cap, s, &ms_join);
-        got = read_counter(ix, 0, s);
-        if (got <= cap) break;
-        if (attempt == 2) fail(SJ_ERR_DEVICE, "batch result count did not settle");
-        cap = got;
-      }
-      ix.info.rechecks += read_counter(ix, 1, s);
-      sl.tmp2.ensure(std::max<uint64_t>(got, 1) * 8);
-      Event e0, e1;
-      SJ_HIP(hipEventRecord(e0.e, s));
+      if (attempt == 2) fail(SJ_ERR_DEVICE, "batch result count did not settle");
+      cap = got;
+    }
+    auto e0 = std::make_unique<Event>(), e1 = std::make_unique<Event>();
+    SJ_HIP(hipEventRecord(e0->e, s));
+    DevBuf *res = &sl.keys;
+    uint64_t cnt = got;
+    if (sym) {
+      // this batch's pairs: the kept and mirrored join output, and the
+      // spilled mirrors of earlier batches that belong here
+      const uint64_t cap_o = 2 * got + spill_n + 1;
+      sl.other.ensure(cap_o * 8);
+      auto *c2 = cnt2.as<unsigned long long>();
+      launch_fill_u64(c2, 2, 0ull, s);
+      launch_spill_take(spill[sc].as<uint64_t>(), spill_n, (uint32_t)i1, sl.other.as<uint64_t>(),
+                        c2, cap_o, spill[sc ^ 1].as<uint64_t>(), c2 + 1, spill_cap, s);
+      launch_mirror_split(sl.keys.as<uint64_t>(), got, (uint32_t)i1, sl.other.as<uint64_t>(), c2,
+                          cap_o, spill[sc ^ 1].as<uint64_t>(), c2 + 1, spill_cap, s);
+      uint64_t h2[2];
+      SJ_HIP(hipMemcpyAsync(h2, c2, 16, hipMemcpyDeviceToHost, s));
+      SJ_HIP(hipStreamSynchronize(s));
+      if (h2[1] > spill_cap) throw OneWayRetry{};
+      spill_n = h2[1];
+      sc ^= 1;
+      cnt = h2[0];  // <= cap_o by construction
+      sl.keys.ensure(std::max<uint64_t>(cnt, 1) * 8);  // the sort's second buffer
+      sort_pairs(ix, sl.other, sl.keys, cnt, s, &sl.sort_tmp);
+      res = &sl.other;
+    } else {
       if (mf)
         launch_pos_to_id(sl.keys.as<uint64_t>(), got, ix.orig_id.as<uint32_t>(),
                          entries_of(ix).orig_id.as<uint32_t>(), s);
-      sort_pairs(ix, sl.keys, sl.tmp2, got, s);
-      SJ_HIP(hipEventRecord(e1.e, s));
-      PinnedBuf hb;
-      hb.alloc(std::max<uint64_t>(got, 1) * 8);
-      Event ready;
-      SJ_HIP(hipEventRecord(ready.e, s));
-      SJ_HIP(hipStreamWaitEvent(cs, ready.e, 0));
-      SJ_HIP(hipMemcpyAsync(hb.p, sl.keys.p, got * 8, hipMemcpyDeviceToHost, cs));
-      SJ_HIP(hipEventRecord(sl.done_copy.e, cs));
-      sl.busy = true;
-      SJ_HIP(hipEventSynchronize(e1.e));
-      ix.info.ms_sort += elapsed_ms(e0, e1);
-      ix.host_res.push_back(std::move(hb));
-      ix.host_cnt.push_back(got);
-      ix.total += got;
-      ++slot;
+      sl.other.ensure(std::max<uint64_t>(got, 1) * 8);
+      sort_pairs(ix, sl.keys, sl.other, got, s, &sl.sort_tmp);
     }
+    SJ_HIP(hipEventRecord(e1->e, s));
+    sort_ev.push_back(std::move(e0));
+    sort_ev.push_back(std::move(e1));
+    PinnedBuf hb;
+    hb.alloc(std::max<uint64_t>(cnt, 1) * 8);
+    SJ_HIP(hipStreamWaitEvent(copy.cs, sort_ev.back()->e, 0));
+    SJ_HIP(hipMemcpyAsync(hb.p, res->p, cnt * 8, hipMemcpyDeviceToHost, copy.cs));
+    SJ_HIP(hipEventRecord(sl.done_copy.e, copy.cs));
+    sl.busy = true;
+    ix.host_res.push_back(std::move(hb));
+    ix.host_cnt.push_back(cnt);
+    ix.total += cnt;
+    ++slot;
   }
-  SJ_HIP(hipStreamSynchronize(cs));
-  SJ_HIP(hipStreamDestroy(cs));
+  SJ_HIP(hipStreamSynchronize(copy.cs));
+  if (sym && spill_n) fail(SJ_ERR_DEVICE, "internal: mirrored pairs left after the last batch");
+  for (size_t e = 0; e + 1 < sort_ev.size(); e += 2)
+    ix.info.ms_sort += elapsed_ms(*sort_ev[e], *sort_ev[e + 1]);
   ix.info.ms_join += ms_join;
   ix.info.batches = (uint32_t)ix.host_res.size();
-  ix.info.evaluated = evaluated;
+  ix.info.evaluated = evaluated - std::min(evaluated, skipped);
   ix.on_host = true;
 }
 
@@ -1475,10 +1624,20 @@ void run(sj_index &ix, hipStream_t s) {
     per_batch = std::min(per_batch, fit);
     per_batch = std::min<uint64_t>(per_batch, 1ull << 36);  // 512 GiB of keys: beyond HBM
     const uint32_t min_b = ix.opt.min_batches;
-    if (est + est / 8 <= per_batch && min_b <= 1)
+    if (est + est / 8 <= per_batch && min_b <= 1) {
       run_single(ix, est, s);
-    else
-      run_batched(ix, est, std::max<uint64_t>(per_batch, 1), s);
+    } else {
+      // FP32 self-joins take each unordered pair once across batches when
+      // the spill fits the budget next to the batches
+      const bool sym = ix.prec == SJ_PREC_FP32 && !ix.entries &&
+                       (est / 4 + est / 8) * 16 <= budget / 2;
+      try {
+        run_batched(ix, est, std::max<uint64_t>(per_batch, 1), sym, s);
+      } catch (const OneWayRetry &) {
+        SJ_HIP(hipStreamSynchronize(s));
+        run_batched(ix, est, std::max<uint64_t>(per_batch, 1), false, s);
+      }
+    }
   }
   SJ_HIP(hipEventRecord(e1.e, s));
   SJ_HIP(hipEventSynchronize(e1.e));
@@ -1546,6 +1705,44 @@ void fetch_offsets(sj_index &ix, uint64_t *offsets, hipStream_t s) {
   SJ_HIP(hipStreamSynchronize(s));
 }
 
+// Pairs [first, first + cnt) of a host-resident result (pinned batches of
+// sorted keys i << 32 | j) written to host columns by up to 16 threads.
+void fetch_host_split(const sj_index &ix, uint64_t first, uint64_t cnt, uint32_t *oi,
+                      uint32_t *oj) {
+  if (!cnt || (!oi && !oj)) return;
+  auto part = [&](uint64_t a, uint64_t e) {  // output entries [a, e)
+    uint64_t off = 0, g = first + a;
+    for (size_t b = 0; b < ix.host_res.size() && a < e; ++b) {
+      const uint64_t bc = ix.host_cnt[b];
+      if (g >= off + bc) {
+        off += bc;
+        continue;
+      }
+      const uint64_t *k = static_cast<const uint64_t *>(ix.host_res[b].p) + (g - off);
+      const uint64_t take = std::min(off + bc - g, e - a);
+      for (uint64_t t = 0; t < take; ++t) {
+        const uint64_t key = k[t];
+        if (oi) oi[a + t] = (uint32_t)(key >> 32);
+        if (oj) oj[a + t] = (uint32_t)key;
+      }
+      a += take;
+      g += take;
+      off += bc;
+    }
+  };
+  const uint64_t per = (uint64_t)1 << 22;
+  const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const uint32_t nt = (uint32_t)std::min<uint64_t>(std::min(hw, 16u), (cnt + per - 1) / per);
+  if (nt <= 1) {
+    part(0, cnt);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (uint32_t t = 0; t < nt; ++t)
+    th.emplace_back(part, cnt * t / nt, cnt * (t + 1) / nt);
+  for (auto &x : th) x.join();
+}
+
 void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint32_t *oj,
            float *od, uint64_t *n_written, hipStream_t s) {
   if (!ix.ran) fail(SJ_ERR_STATE, "fetch before a successful run");
@@ -1556,6 +1753,12 @@ void fetch(sj_index &ix, uint64_t first, uint64_t max_pairs, uint32_t *oi, uint3
   const bool dev_j = !oj || is_device_pointer(oj);
   const bool dev_d = !od || is_device_pointer(od);
   const bool all_dev = dev_i && dev_j && dev_d;
+  if (ix.on_host && !od && (!oi || !dev_i) && (!oj || !dev_j)) {
+    // host result into host columns: split the keys on host threads
+    fetch_host_split(ix, first, cnt, oi, oj);
+    *n_written = cnt;
+    return;
+  }
   const uint64_t chunk = 1ull << 24;
   DevBuf keys_stage, si, sj2, sd;
   uint64_t done = 0;
@@ -1739,8 +1942,9 @@ int selfjoin_release_cache(uint64_t *released) {
     int dev = 0;
     SJ_HIP(hipGetDevice(&dev));
     thread_scratch().trim();
-    const size_t b = dev_cached_bytes(dev);
+    const size_t b = dev_cached_bytes(dev) + host_cached_bytes();
     dev_cache_release(dev);
+    host_cache_release();
     if (released) *released = b;
   });
 }

@@ -167,6 +167,8 @@ struct JoinLaunch {
   int rq;                   // queries per lane (1, 2 or 4; fp32_rq_for); units hold 64*rq queries
   int norm;                 // 1: norm form with the tables QA / CR
   const float *QA, *CR;     // [.][norm_table_row(dp)] query (of Xq) / candidate (of X) tables
+  uint32_t skip_below;      // candidates with caller index below this are skipped (0: none)
+  unsigned long long *skipped;  // += skipped candidates x live queries of the wave
 };
 
 // Queries per lane the FP32 kernel uses for padded dimension dp.
@@ -181,6 +183,21 @@ void launch_norm_tables(const float *X, uint64_t n, uint32_t dp, double s_hi, do
 // Padded dimension count the kernels support for d (0 if unsupported).
 uint32_t padded_dim(uint32_t d);
 void launch_join_fp32(const JoinLaunch &a, hipStream_t s);
+
+// Symmetric result batches over caller-index ranges (the batch of queries
+// [i0, i1) runs after every batch below i0).  k_mirror_split takes the
+// batch's join output (i << 32 | j, every j >= i0) and keeps (i, j) when
+// j >= i; for j > i it adds the mirror (j, i) to `out` when j < i1, else to
+// `spill` (a later batch's pair).  k_spill_take moves the spilled pairs with
+// i < i1 from `spill_in` to `out` and the rest to `spill_out`.  Slots are
+// taken with one atomic per block of 16,384 entries and stream; counts
+// beyond a capacity are still counted.
+void launch_mirror_split(const uint64_t *in, uint64_t n, uint32_t i1, uint64_t *out,
+                         unsigned long long *out_cnt, uint64_t out_cap, uint64_t *spill,
+                         unsigned long long *spill_cnt, uint64_t spill_cap, hipStream_t s);
+void launch_spill_take(const uint64_t *spill_in, uint64_t n, uint32_t i1, uint64_t *out,
+                       unsigned long long *out_cnt, uint64_t out_cap, uint64_t *spill_out,
+                       unsigned long long *spill_cnt, uint64_t spill_cap, hipStream_t s);
 
 // Unpack sorted keys [first, first+count) to (i, j) columns and optionally
 // recompute FP32 distances.

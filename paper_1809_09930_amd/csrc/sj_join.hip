@@ -351,7 +351,8 @@ __device__ __forceinline__ void join_body(
     float hi, double eps2, int symmetric, uint64_t *__restrict__ out,
     uint64_t capacity, unsigned long long *__restrict__ cursor,
     unsigned long long *__restrict__ rechecks, uint64_t (*stage_mem)[kStage],
-    const float *__restrict__ QA, const float *__restrict__ CR) {
+    const float *__restrict__ QA, const float *__restrict__ CR, uint32_t skip_below,
+    unsigned long long *__restrict__ skipped) {
   const uint32_t w = uniform_u32(threadIdx.x / kWave);
   const uint64_t u = (uint64_t)blockIdx.x * kWavesPerBlock + w;
   if (u >= n_wu) return;  // whole wave leaves; no workgroup barrier follows
@@ -417,8 +418,12 @@ __device__ __forceinline__ void join_body(
   const uint32_t filt_end = (symmetric && !qlist) ? wu.q1 : 0u;
 
   WaveStage st{kCount ? nullptr : &stage_mem[w][0], 0u};
-  uint64_t n_recheck = 0, n_count = 0;
+  uint64_t n_recheck = 0, n_count = 0, n_skip = 0;
   const bool sym = symmetric != 0;
+  // live queries of the wave (counted per skipped candidate)
+  const uint32_t n_live = uniform_u32(wu.q1 - wu.q0 < (uint32_t)(RQ * kWave)
+                                          ? wu.q1 - wu.q0
+                                          : (uint32_t)(RQ * kWave));
 
   for (uint32_t r = wu.run_first; r <= wu.run_last; ++r) {
     const uint2 run = runs[r];
@@ -470,7 +475,14 @@ __device__ __forceinline__ void join_body(
               lb = __builtin_fmaf(g, g, lb);
             }
           }
-          uint64_t keep = ballot(b0 + l < to && lb <= hi);
+          bool pass = b0 + l < to && lb <= hi;
+          if (skip_below) {
+            // candidates of earlier result batches: their pairs were taken there
+            const bool early = b0 + l < to && orig_id[cl] < skip_below;
+            n_skip += (uint64_t)__builtin_popcountll(ballot(early)) * n_live;
+            pass = pass && !early;
+          }
+          uint64_t keep = ballot(pass);
           if (keep == 0) continue;
           uint32_t c = b0 + (uint32_t)__builtin_ctzll(keep);
           keep &= keep - 1;
@@ -498,7 +510,10 @@ __device__ __forceinline__ void join_body(
         for (uint32_t c = from; c < to; ++c) {
           const Head<DP, kNorm> hn =
               load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
-          eval(h, c);
+          if (skip_below && orig_id[c] < skip_below)
+            n_skip += n_live;  // a pair of an earlier result batch
+          else
+            eval(h, c);
           h = hn;
           next();
         }
@@ -511,6 +526,7 @@ __device__ __forceinline__ void join_body(
   if (l == 0) {
     if (n_recheck) atomicAdd(rechecks, (unsigned long long)n_recheck);
     if (n_count) atomicAdd(cursor, (unsigned long long)n_count);
+    if (n_skip) atomicAdd(skipped, (unsigned long long)n_skip);
   }
 }
 
@@ -522,7 +538,7 @@ __device__ __forceinline__ void join_body(
       float hi, double eps2, int symmetric, uint64_t *__restrict__ out,                         \
       uint64_t capacity, unsigned long long *__restrict__ cursor,                               \
       unsigned long long *__restrict__ rechecks, const float *__restrict__ QA,                  \
-      const float *__restrict__ CR
+      const float *__restrict__ CR, uint32_t skip_below, unsigned long long *__restrict__ skipped
 
 // The distance kernel (queries Xq against candidates X; Xq = X in a
 // self-join): emits result pairs.
@@ -531,7 +547,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fp32(SJ_JOIN_PARAMS) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
   join_body<DP, RQ, false, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d,
                                        lo, hi, eps2, symmetric, out, capacity, cursor, rechecks,
-                                       stage_mem, QA, CR);
+                                       stage_mem, QA, CR, skip_below, skipped);
 }
 
 // The estimation kernel (count only) used to size result buffers.
@@ -539,7 +555,7 @@ template <int DP, int RQ, bool kNorm, bool kSC>
 __global__ __launch_bounds__(kBlock) void k_count_fp32(SJ_JOIN_PARAMS) {
   join_body<DP, RQ, true, kNorm, kSC>(X, orig_id, Xq, qid, inv_perm, wus, n_wu, runs, qlist, d,
                                       lo, hi, eps2, symmetric, out, capacity, cursor, rechecks,
-                                      nullptr, QA, CR);
+                                      nullptr, QA, CR, skip_below, skipped);
 }
 
 // Tables of the norm form, one row of norm_row(DP) floats per point p (the
@@ -654,12 +670,12 @@ void launch_rq(const JoinLaunch &a, uint32_t grid, hipStream_t s) {
     hipLaunchKernelGGL((k_count_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
                        a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d,
                        a.lo, a.hi, a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks,
-                       a.QA, a.CR);
+                       a.QA, a.CR, a.skip_below, a.skipped);
   else
     hipLaunchKernelGGL((k_join_fp32<DP, kRq, kNorm, kSC>), dim3(grid), dim3(kBlock), 0, s, a.X,
                        a.orig_id, a.Xq, a.qid, a.inv_perm, a.wu, a.n_wu, a.runs, a.qlist, a.d,
                        a.lo, a.hi, a.eps2, a.symmetric, a.out, a.capacity, a.cursor, a.rechecks,
-                       a.QA, a.CR);
+                       a.QA, a.CR, a.skip_below, a.skipped);
   SJ_HIP(hipGetLastError());
 }
 

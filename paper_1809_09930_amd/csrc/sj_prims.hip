@@ -302,7 +302,132 @@ __global__ void k_narrow(const uint64_t *__restrict__ in, uint32_t *__restrict__
   if (i < count) out[i] = (uint32_t)in[i];
 }
 
+// Stream split of result keys: every entry gives up to two keys for `out`
+// and one for `spill` (Classify returns them).  A block takes
+// kSplitRounds * kBlock consecutive entries, each wave kSplitRounds rounds of
+// 64; the block counts its outputs first, takes its slots with one atomic
+// per stream, and writes every round's keys to consecutive slots.  Counts go
+// on past the capacities; keys beyond them are dropped.
+constexpr uint32_t kSplitRounds = 64;
+constexpr uint32_t kSplitTile = kSplitRounds * kBlock;
+
+struct SplitKeys {
+  bool a1, a2, sp;        // out gets v1 / v2, spill gets vs
+  uint64_t v1, v2, vs;
+};
+
+template <class Classify>
+__device__ __forceinline__ void split_tile(const uint64_t *__restrict__ in, uint64_t n,
+                                           Classify f, uint64_t *__restrict__ out,
+                                           unsigned long long *__restrict__ out_cnt,
+                                           uint64_t out_cap, uint64_t *__restrict__ spill,
+                                           unsigned long long *__restrict__ spill_cnt,
+                                           uint64_t spill_cap) {
+  constexpr uint32_t kW = kBlock / kWave;
+  __shared__ uint32_t w_out[kW], w_sp[kW];
+  __shared__ unsigned long long b_out, b_sp;
+  const uint32_t w = threadIdx.x / kWave, l = lane_id();
+  const uint64_t base = (uint64_t)blockIdx.x * kSplitTile + (uint64_t)w * kSplitRounds * kWave;
+  uint32_t c_out = 0, c_sp = 0;
+  for (uint32_t r = 0; r < kSplitRounds; ++r) {
+    const uint64_t e = base + (uint64_t)r * kWave + l;
+    const bool valid = e < n;
+    const SplitKeys k = f(valid, valid ? in[e] : 0ull);
+    c_out += (uint32_t)(__builtin_popcountll(ballot(k.a1)) + __builtin_popcountll(ballot(k.a2)));
+    c_sp += (uint32_t)__builtin_popcountll(ballot(k.sp));
+  }
+  if (l == 0) {
+    w_out[w] = c_out;
+    w_sp[w] = c_sp;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t so = 0, ss = 0;
+    for (uint32_t i = 0; i < kW; ++i) {
+      const uint32_t to = w_out[i], ts = w_sp[i];
+      w_out[i] = so;
+      w_sp[i] = ss;
+      so += to;
+      ss += ts;
+    }
+    b_out = so ? atomicAdd(out_cnt, (unsigned long long)so) : 0ull;
+    b_sp = ss ? atomicAdd(spill_cnt, (unsigned long long)ss) : 0ull;
+  }
+  __syncthreads();
+  uint64_t po = b_out + w_out[w], ps = b_sp + w_sp[w];
+  for (uint32_t r = 0; r < kSplitRounds; ++r) {
+    const uint64_t e = base + (uint64_t)r * kWave + l;
+    const bool valid = e < n;
+    const SplitKeys k = f(valid, valid ? in[e] : 0ull);
+    const uint64_t m1 = ballot(k.a1), m2 = ballot(k.a2), ms = ballot(k.sp);
+    if (k.a1) {
+      const uint64_t p = po + lanes_below(m1);
+      if (p < out_cap) out[p] = k.v1;
+    }
+    po += (uint64_t)__builtin_popcountll(m1);
+    if (k.a2) {
+      const uint64_t p = po + lanes_below(m2);
+      if (p < out_cap) out[p] = k.v2;
+    }
+    po += (uint64_t)__builtin_popcountll(m2);
+    if (k.sp) {
+      const uint64_t p = ps + lanes_below(ms);
+      if (p < spill_cap) spill[p] = k.vs;
+    }
+    ps += (uint64_t)__builtin_popcountll(ms);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mirror_split(
+    const uint64_t *__restrict__ in, uint64_t n, uint32_t i1, uint64_t *__restrict__ out,
+    unsigned long long *__restrict__ out_cnt, uint64_t out_cap, uint64_t *__restrict__ spill,
+    unsigned long long *__restrict__ spill_cnt, uint64_t spill_cap) {
+  auto f = [i1](bool valid, uint64_t key) {
+    const uint32_t i = (uint32_t)(key >> 32), j = (uint32_t)key;
+    const bool keep = valid && j >= i;
+    const bool mirror = keep && j > i;
+    const uint64_t mk = ((uint64_t)j << 32) | i;
+    return SplitKeys{keep, mirror && j < i1, mirror && j >= i1, key, mk, mk};
+  };
+  split_tile(in, n, f, out, out_cnt, out_cap, spill, spill_cnt, spill_cap);
+}
+
+__global__ __launch_bounds__(kBlock) void k_spill_take(
+    const uint64_t *__restrict__ spill_in, uint64_t n, uint32_t i1, uint64_t *__restrict__ out,
+    unsigned long long *__restrict__ out_cnt, uint64_t out_cap, uint64_t *__restrict__ spill_out,
+    unsigned long long *__restrict__ spill_cnt, uint64_t spill_cap) {
+  auto f = [i1](bool valid, uint64_t key) {
+    const bool now = valid && (uint32_t)(key >> 32) < i1;
+    return SplitKeys{now, false, valid && !now, key, key, key};
+  };
+  split_tile(spill_in, n, f, out, out_cnt, out_cap, spill_out, spill_cnt, spill_cap);
+}
+
 }  // namespace
+
+void launch_mirror_split(const uint64_t *in, uint64_t n, uint32_t i1, uint64_t *out,
+                         unsigned long long *out_cnt, uint64_t out_cap, uint64_t *spill,
+                         unsigned long long *spill_cnt, uint64_t spill_cap, hipStream_t s) {
+  if (!n) return;
+  if ((n + kSplitTile - 1) / kSplitTile > 0x7fffffffull)
+    fail(SJ_ERR_INVALID_ARG, "mirror split too large");
+  hipLaunchKernelGGL(k_mirror_split, dim3((uint32_t)((n + kSplitTile - 1) / kSplitTile)),
+                     dim3(kBlock), 0,
+                     s, in, n, i1, out, out_cnt, out_cap, spill, spill_cnt, spill_cap);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_spill_take(const uint64_t *spill_in, uint64_t n, uint32_t i1, uint64_t *out,
+                       unsigned long long *out_cnt, uint64_t out_cap, uint64_t *spill_out,
+                       unsigned long long *spill_cnt, uint64_t spill_cap, hipStream_t s) {
+  if (!n) return;
+  if ((n + kSplitTile - 1) / kSplitTile > 0x7fffffffull)
+    fail(SJ_ERR_INVALID_ARG, "spill take too large");
+  hipLaunchKernelGGL(k_spill_take, dim3((uint32_t)((n + kSplitTile - 1) / kSplitTile)),
+                     dim3(kBlock), 0, s,
+                     spill_in, n, i1, out, out_cnt, out_cap, spill_out, spill_cnt, spill_cap);
+  SJ_HIP(hipGetLastError());
+}
 
 void launch_iota_strided(uint32_t *out, uint64_t count, uint64_t stride, uint32_t run,
                          hipStream_t s) {

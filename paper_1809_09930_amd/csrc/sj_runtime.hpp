@@ -29,8 +29,9 @@ extern thread_local std::string g_last_error;
 // overrides; 0 turns caching off); a failed allocation empties the device's
 // cache and tries once more.  dev_alloc returns the block's capacity in
 // *got and its device in *dev.
+// `idle`: the caller knows no queued work uses the block (no wait needed).
 void *dev_alloc(size_t bytes, size_t *got, int *dev);
-void dev_free(void *p, size_t got, int dev);
+void dev_free(void *p, size_t got, int dev, bool idle = false);
 // bytes held in the cache of device `dev` (idle, reusable by the library)
 size_t dev_cached_bytes(int dev);
 // frees every cached block of device `dev`
@@ -58,8 +59,11 @@ struct DevBuf {
     p = dev_alloc(b, &got, &dev);
     bytes = b;
   }
+  // at least b bytes; a block that must grow gets a quarter more, so that
+  // buffers reused across batches of varying size are seldom replaced (a
+  // replacement waits for the device)
   void ensure(size_t b) {
-    if (b > bytes || !p) alloc(b);
+    if (!p || b > got) alloc(b + b / 4);
   }
   template <typename T>
   T *as() const {
@@ -120,23 +124,35 @@ struct TmpBuf {
   }
 };
 
+// Pinned host blocks go through a process-wide cache as device blocks do:
+// a freed block (no device work may use it any more) is kept for the next
+// request it fits, up to SJ_HOST_CACHE_BYTES bytes (default: an eighth of
+// the host's memory, at most 64 GiB; 0 turns caching off).
+void *host_alloc(size_t bytes, size_t *got);
+void host_free(void *p, size_t got);
+size_t host_cached_bytes();
+void host_cache_release();
+
 struct PinnedBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  size_t got = 0;
   PinnedBuf() = default;
   PinnedBuf(const PinnedBuf &) = delete;
   PinnedBuf &operator=(const PinnedBuf &) = delete;
-  PinnedBuf(PinnedBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  PinnedBuf(PinnedBuf &&o) noexcept : p(o.p), bytes(o.bytes), got(o.got) {
+    o.p = nullptr;
+    o.bytes = 0;
+    o.got = 0;
+  }
   ~PinnedBuf() {
-    if (p) (void)hipHostFree(p);
+    if (p) host_free(p, got);
   }
   void alloc(size_t b) {
+    if (p) host_free(p, got);
+    p = nullptr;
     if (b == 0) b = 64;
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      fail(SJ_ERR_OUT_OF_MEMORY, "pinned host allocation of " + std::to_string(b) + " bytes failed");
-    }
+    p = host_alloc(b, &got);
     bytes = b;
   }
 };

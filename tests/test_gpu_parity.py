@@ -802,3 +802,82 @@ def test_cached_blocks_reused(prec):
     assert sj.selfjoin_release_cache() > 0
     assert sj.selfjoin_release_cache() == 0
     assert_same_as_oracle(P, small, precision=prec)
+
+
+def _fetch_all(h, total, device):
+    from paper_1809_09930_amd import selfjoin as sj
+    dev = "cuda" if device else "cpu"
+    oi = torch.empty(total, dtype=torch.int32, device=dev)
+    oj = torch.empty(total, dtype=torch.int32, device=dev)
+    if total:
+        assert sj.selfjoin_fetch_pairs(h, 0, oi, oj, None, max_pairs=total) == total
+    torch.cuda.synchronize()
+    return oi.cpu().numpy().view(np.uint32), oj.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("order", ["random", "sorted", "reversed"])
+@pytest.mark.parametrize("nbatch", [2, 5, 13])
+def test_symmetric_result_batches(order, nbatch):
+    """FP32 self-joins in several result batches take each unordered pair
+    once: a batch skips candidates of earlier batches and mirrors its pairs,
+    later batches' mirrors through a device spill.  The caller's row order
+    decides how much is spilled: rows in random order, sorted along the
+    first coordinate (partners mostly in the same or the next batch) and
+    reversed.  The result must be the oracle's; the evaluated pairs must be
+    about half of the one-directional count."""
+    from paper_1809_09930_amd import selfjoin as sj
+    P = datagen.offgrid("mixture_f32", 5000, 10, 93)
+    if order != "random":
+        P = P[np.argsort(P[:, 0], kind="stable")]
+        if order == "reversed":
+            P = P[::-1].copy()
+    eps = calibrated(P, 40)
+    oi, oj = oracle.bruteforce(P, eps)
+    h = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps, min_batches=nbatch)
+    try:
+        total = sj.selfjoin_run(h)
+        info = sj.selfjoin_get_info(h)
+        assert info["batches"] == nbatch and info["result_on_host"] == 1
+        for device in (True, False):
+            gi, gj = _fetch_all(h, total, device)
+            assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+        # pieces across batch boundaries, into host and device columns
+        for first, cnt in ((0, 1), (total // 3, total // 2), (total - 7, 7), (1, total - 1)):
+            for device in ("cpu", "cuda"):
+                part = torch.empty(cnt, dtype=torch.int32, device=device)
+                assert sj.selfjoin_fetch_pairs(h, first, part, None, None, max_pairs=cnt) == cnt
+                assert np.array_equal(part.cpu().numpy().view(np.uint32), oi[first:first + cnt])
+    finally:
+        sj.selfjoin_free(h)
+    one_way = sj.selfjoin_build_index(torch.from_numpy(P).cuda(), eps, min_batches=nbatch,
+                                      precision="fp16")
+    try:
+        sj.selfjoin_run(one_way)
+        ow = sj.selfjoin_get_info(one_way)["evaluated"]
+    finally:
+        sj.selfjoin_free(one_way)
+    assert info["evaluated"] <= ow
+    if order == "random":  # a candidate is in an earlier batch about half the time
+        assert info["evaluated"] < (0.5 * (nbatch + 1) / nbatch + 0.05) * ow
+
+
+@pytest.mark.parametrize("form", ["difference", "norm"])
+def test_symmetric_batches_spill_overflow_falls_back(form, monkeypatch):
+    """A spill too small for the mirrored pairs (forced by
+    SJ_DEBUG_UNDERSIZE, which also undersizes every batch buffer) makes the
+    run start over one-directionally; the result is still the oracle's."""
+    monkeypatch.setenv("SJ_DEBUG_UNDERSIZE", "1")
+    P = datagen.uniform_grid(3000, 12, 94)
+    info = assert_same_as_oracle(P, calibrated(P, 25), min_batches=4, fp32_form=form)
+    assert info["batches"] == 4
+
+
+def test_symmetric_batches_edge_cases():
+    """Batches that hold one row each, duplicates that straddle batches, a
+    batch with no pairs beyond the diagonal and more batches than rows allow."""
+    P = np.repeat(datagen.uniform_grid(40, 3, 95), 3, axis=0)
+    assert_same_as_oracle(P, 0.05, min_batches=len(P))
+    assert_same_as_oracle(P, 0.05, min_batches=7, shortc=False)
+    far = np.arange(12, dtype=np.float32)[:, None] * np.ones((1, 4), np.float32)
+    info = assert_same_as_oracle(far, 0.5, min_batches=5)
+    assert info["pairs"] == 12
