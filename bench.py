@@ -473,9 +473,32 @@ def bench_host_complete(sj, P, Pd, eps_list, targets, precision):
                    "s_fetch_to_pinned_host": round(t2 - t1, 4),
                    "fetch_GB_per_s": round(total * 8 / max(t2 - t1, 1e-9) / 1e9, 2)}
     elapsed = time.perf_counter() - t_all
+    # the largest result again in batches of at most 1e8 pairs (Section
+    # 3.2.2): each batch sorted and streamed to pinned host memory while the
+    # next one computes; the best of two warm runs against the one-batch run
+    t_big, eps_big = targets[-1], eps_list[-1]
+
+    def once(batch_pairs):
+        t0 = time.perf_counter()
+        h = sj.selfjoin_build_index(Pd, eps_big, precision=precision, batch_pairs=batch_pairs)
+        total = sj.selfjoin_run(h)
+        sj.selfjoin_fetch_pairs(h, 0, oi, oj, None, max_pairs=total)
+        dt = time.perf_counter() - t0
+        info = sj.selfjoin_get_info(h)
+        sj.selfjoin_free(h)
+        return dt, info
+    once(int(1e8))  # warm: the batches' pinned buffers
+    single = min(once(0)[0] for _ in range(2))
+    runs = [once(int(1e8)) for _ in range(2)]
+    multi, minfo = min(runs, key=lambda r: r[0])
+    batched = {"target": t_big, "batch_pairs": int(1e8), "batches": minfo["batches"],
+               "s_one_batch": round(single, 4), "s_batched": round(multi, 4),
+               "ratio": round(multi / single, 3), "evaluated": minfo["evaluated"],
+               "ms_join": round(minfo["ms_join"], 1), "ms_sort": round(minfo["ms_sort"], 1)}
     return {"value": cand / elapsed, "ms_per_step": elapsed * 1e3,
             "result_pairs_per_s": sum(totals) / elapsed, "per_epsilon": rows,
-            "clock": "build + join + sort + every (i, j) pair in pinned host memory"}
+            "clock": "build + join + sort + every (i, j) pair in pinned host memory",
+            "batched": batched}
 
 
 def workload_eps(table, name, targets_arg=""):

@@ -506,17 +506,25 @@ __device__ __forceinline__ void join_body(
           }
         }
       } else {
-        Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
-        for (uint32_t c = from; c < to; ++c) {
-          const Head<DP, kNorm> hn =
-              load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
-          if (skip_below && orig_id[c] < skip_below)
-            n_skip += n_live;  // a pair of an earlier result batch
-          else
-            eval(h, c);
-          h = hn;
-          next();
-        }
+        // one loop without the skip test (every run but the symmetric
+        // batches) and one with it
+        auto walk = [&](auto skip) __attribute__((always_inline)) {
+          Head<DP, kNorm> h = load_head<DP, kNorm>(crow, ccr);
+          for (uint32_t c = from; c < to; ++c) {
+            const Head<DP, kNorm> hn =
+                load_head<DP, kNorm>(crow + DP, kNorm ? ccr + NR : nullptr);
+            if (decltype(skip)::value && orig_id[c] < skip_below)
+              n_skip += n_live;  // a pair of an earlier result batch
+            else
+              eval(h, c);
+            h = hn;
+            next();
+          }
+        };
+        if (skip_below)
+          walk(std::true_type{});
+        else
+          walk(std::false_type{});
       }
     };
     sweep(cb, mid, std::true_type{});

@@ -657,6 +657,14 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wave(MfmaView v,
 // once into a double-buffered LDS stage (global -> registers during the
 // MFMAs of the previous chunk -> LDS) instead of once per wave.
 constexpr int kChunk = 64;  // candidate rows per LDS stage (2 MFMA row blocks)
+// LDS row stride of a staged chunk, in 16-byte vectors.  Lanes read the
+// same vector of 32 consecutive rows; with an odd stride (RV is even) the
+// reads of 8 consecutive rows fall in different bank groups.  Measured: at
+// K = 64 the FP16 join on 2M x 64 takes 246 / 284 ms with the padding and
+// 288 / 319 without; at K = 16 (a 2-way conflict only) the padded form was
+// slower where hits are frequent (207 against 169 ms), so K = 16 keeps the
+// dense rows.
+constexpr int lds_row_vectors(int rv) { return rv >= 4 ? rv + 1 : rv; }
 // query column blocks per wave for K padding up to 64, and above
 #ifndef SJ_WG_QB_SMALL
 #define SJ_WG_QB_SMALL 2
@@ -684,7 +692,8 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   constexpr int CHUNK_VECS = kChunk * RV;         // vectors per LDS stage
   constexpr int PER_THREAD = (CHUNK_VECS + kBlock - 1) / kBlock;
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  __shared__ V8 tile[2][CHUNK_VECS];
+  constexpr int RS = lds_row_vectors(RV);
+  __shared__ V8 tile[2][kChunk * RS];
   __shared__ __align__(16) float tile_n[2][kChunk];  // candidate norms of the chunk
   __shared__ uint64_t band_mem[kWavesPerBlock][kBandStage];
   const uint64_t u = blockIdx.x;
@@ -740,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
-      if (e < (uint32_t)CHUNK_VECS) tile[buf][e] = pre[i];
+      if (e < (uint32_t)CHUNK_VECS) tile[buf][(e / RV) * RS + e % RV] = pre[i];
     }
     if (threadIdx.x < (uint32_t)kChunk) tile_n[buf][threadIdx.x] = pre_n;
   };
@@ -763,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
   auto block_mfma = [&](int buf, int blk, float16v(&acc)[QB]) __attribute__((always_inline)) {
     V8 A[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RV + ks * 2 + half];
+    for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RS + ks * 2 + half];
     const float16v c0 = norm_init(&tile_n[buf][blk * 32], half);
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
@@ -917,7 +926,8 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg_box(MfmaView v,
   constexpr int CHUNK_VECS = kChunk * RV;
   constexpr int PER_THREAD = (CHUNK_VECS + kBlock - 1) / kBlock;
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  __shared__ V8 tile[2][CHUNK_VECS];
+  constexpr int RS = lds_row_vectors(RV);
+  __shared__ V8 tile[2][kChunk * RS];
   __shared__ __align__(16) float tile_n[2][kChunk];
   __shared__ uint32_t tile_pos[2][kChunk];
   __shared__ uint64_t band_mem[kWavesPerBlock][kBandStage];
@@ -1070,7 +1080,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg_box(MfmaView v,
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const uint32_t e = threadIdx.x + (uint32_t)i * kBlock;
-      if (e < (uint32_t)CHUNK_VECS) tile[buf][e] = pre[i];
+      if (e < (uint32_t)CHUNK_VECS) tile[buf][(e / RV) * RS + e % RV] = pre[i];
     }
     if (threadIdx.x < (uint32_t)kChunk) {
       tile_n[buf][threadIdx.x] = pre_n;
@@ -1080,7 +1090,7 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg_box(MfmaView v,
   auto block_mfma = [&](int buf, int blk, float16v(&acc)[QB]) __attribute__((always_inline)) {
     V8 A[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RV + ks * 2 + half];
+    for (int ks = 0; ks < KS; ++ks) A[ks] = tile[buf][(blk * 32 + col) * RS + ks * 2 + half];
     const float16v c0 = norm_init(&tile_n[buf][blk * 32], half);
 #pragma unroll
     for (int j = 0; j < QB; ++j) {
