@@ -327,6 +327,11 @@ constexpr bool kWuByStretch = SJ_WU_BY_STRETCH != 0;  // join work units in stre
 // Cost model for the automatic choice of k (Section 5.5 compares the memory
 // operations of index searches with those of distance calculations): one
 // unit per 3^k-offset lookup of each non-empty cell, one per evaluated pair.
+#ifndef SJ_FP32_CELL_GROUPS
+#define SJ_FP32_CELL_GROUPS 1
+#endif
+
+constexpr bool kFp32CellGroups = SJ_FP32_CELL_GROUPS != 0;
 constexpr double kLookupsPerSec = 2.0e10;
 constexpr double kPairsPerSec = 1.5e12;
 
@@ -526,6 +531,57 @@ uint64_t build_runs(sj_index &ix, int sym, DevBuf &off, DevBuf &runs, BuildTmp &
   return h_tot;
 }
 
+void build_cell_groups(sj_index &ix, uint32_t max_q, CellGroups &g, hipStream_t s) {
+  const uint64_t nc = ix.ncell;
+  std::vector<uint64_t> key(nc);
+  std::vector<uint32_t> start(nc + 1);
+  SJ_HIP(hipMemcpyAsync(key.data(), ix.cell_key.p, nc * 8, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipMemcpyAsync(start.data(), ix.cell_start.p, (nc + 1) * 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  // the last indexed dimension has stride 1 in the cell key: cells of one
+  // row share key / m_last, and key + 1 is the next cell along it
+  const uint64_t m_last = ix.geom.k ? std::max<uint64_t>(1, ix.geom.np.m[ix.geom.k - 1]) : 1;
+  std::vector<uint32_t> first, gstart;
+  first.reserve(nc + 1);
+  gstart.reserve(nc + 1);
+  for (uint64_t a = 0; a < nc;) {
+    first.push_back((uint32_t)a);
+    gstart.push_back(start[a]);
+    uint64_t b = a + 1;
+    while (b < nc && b - a < kGroupMaxCells && key[b] / m_last == key[a] / m_last &&
+           key[b] - key[a] <= 2 && start[b + 1] - start[a] <= max_q)
+      ++b;
+    a = b;
+  }
+  first.push_back((uint32_t)nc);
+  gstart.push_back(start[nc]);
+  const uint64_t ng = first.size() - 1;
+  ScratchScope scope;  // the read-back below synchronises the stream
+  TmpBuf gfirst, cnt, tot, scan;
+  gfirst.alloc((ng + 1) * 4);
+  SJ_HIP(hipMemcpyAsync(gfirst.p, first.data(), (ng + 1) * 4, hipMemcpyHostToDevice, s));
+  g.n = ng;
+  g.start.alloc((ng + 1) * 4);
+  SJ_HIP(hipMemcpyAsync(g.start.p, gstart.data(), (ng + 1) * 4, hipMemcpyHostToDevice, s));
+  cnt.alloc((ng + 1) * 4);
+  SJ_HIP(hipMemsetAsync(cnt.p, 0, (ng + 1) * 4, s));
+  launch_group_runs(0, ng, gfirst.as<uint32_t>(), ix.run_off_sym.as<uint32_t>(),
+                    ix.runs_sym.as<uint2>(), cnt.as<uint32_t>(), nullptr, nullptr, s);
+  g.run_off.alloc((ng + 1) * 4);
+  tot.alloc(64);
+  scan.alloc(scan_tmp_bytes(ng + 1) + 64);
+  exclusive_scan_u32(cnt.as<uint32_t>(), g.run_off.as<uint32_t>(), ng + 1, tot.as<uint32_t>(),
+                     scan.p, s);
+  uint32_t h_tot = 0;
+  SJ_HIP(hipMemcpyAsync(&h_tot, tot.p, 4, hipMemcpyDeviceToHost, s));
+  SJ_HIP(hipStreamSynchronize(s));
+  g.runs.alloc(std::max<uint64_t>(h_tot, 1) * sizeof(uint2));
+  launch_group_runs(1, ng, gfirst.as<uint32_t>(), ix.run_off_sym.as<uint32_t>(),
+                    ix.runs_sym.as<uint2>(), nullptr, g.run_off.as<uint32_t>(),
+                    g.runs.as<uint2>(), s);
+  SJ_HIP(hipStreamSynchronize(s));
+}
+
 // Work units over the given runs; qlist == nullptr: contiguous queries.
 // Returns the number of units; *eval receives the evaluated pair count.
 // With by_stretch, the units are ordered by their stretch index within
@@ -552,15 +608,17 @@ USearch usearch_of(const sj_index &ix) {
 uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
                          const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
                          DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch,
-                         DevBuf *u_ranges) {
-  const uint64_t nc = ix.ncell;
+                         DevBuf *u_ranges, const CellGroups *groups) {
+  // query blocks are cut from the cells, or from groups of consecutive cells
+  const uint64_t nc = groups ? groups->n : ix.ncell;
+  const uint32_t *cstart = groups ? groups->start.as<uint32_t>() : ix.cell_start.as<uint32_t>();
   ScratchScope scope;  // every temporary below is dead at the final synchronisation
   TmpBuf qb_off, run_total, scan, tot;
   qb_off.alloc((nc + 1) * 4);
   run_total.alloc(nc * 8);
   tot.alloc(64);
   SJ_HIP(hipMemsetAsync(qb_off.p, 0, (nc + 1) * 4, s));
-  launch_wu_cells(nc, tq, ix.cell_start.as<uint32_t>(), qlist, nq, run_off.as<uint32_t>(),
+  launch_wu_cells(nc, tq, cstart, qlist, nq, run_off.as<uint32_t>(),
                   runs.as<uint2>(), qb_off.as<uint32_t>(), run_total.as<uint64_t>(), s);
   scan.alloc(scan_tmp_bytes(std::max<uint64_t>(nc + 1, 1)) + 64);
   exclusive_scan_u32(qb_off.as<uint32_t>(), qb_off.as<uint32_t>(), nc + 1, tot.as<uint32_t>(),
@@ -607,7 +665,7 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
   ev.alloc((nqb + 1) * 8);
   SJ_HIP(hipMemsetAsync(units.p, 0, (nqb + 1) * 4, s));
   SJ_HIP(hipMemsetAsync(ev.p, 0, (nqb + 1) * 8, s));
-  launch_wu_count(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+  launch_wu_count(nqb, sym, nc, tq, tc, cstart, qlist, nq,
                   qb_off.as<uint32_t>(), r_off, r_runs, r_total, units.as<uint32_t>(),
                   ev.as<uint64_t>(), s, per_block);
   scan.alloc(scan_tmp_bytes(nqb + 1) + 64);
@@ -626,7 +684,7 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
     unordered.alloc(n_wu * sizeof(WorkUnit));
     keys[0].alloc(n_wu * 8);
     keys[1].alloc(n_wu * 8);
-    launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+    launch_wu_fill(nqb, sym, nc, tq, tc, cstart, qlist, nq,
                    qb_off.as<uint32_t>(), r_off, r_runs, r_total, units.as<uint32_t>(),
                    unordered.as<WorkUnit>(), keys[0].as<uint64_t>(), s, per_block);
     // stable LSD sort on the stretch index (high word) keeps block order
@@ -637,7 +695,7 @@ uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t 
     radix_sort_u64(kb, nullptr, n_wu, sh.data(), (int)sh.size(), rtmp.p, s);
     launch_gather_wu(unordered.as<WorkUnit>(), kb[0], n_wu, out.as<WorkUnit>(), s);
   } else {
-    launch_wu_fill(nqb, sym, nc, tq, tc, ix.cell_start.as<uint32_t>(), qlist, nq,
+    launch_wu_fill(nqb, sym, nc, tq, tc, cstart, qlist, nq,
                    qb_off.as<uint32_t>(), r_off, r_runs, r_total, units.as<uint32_t>(),
                    out.as<WorkUnit>(), nullptr, s, per_block);
   }
@@ -964,9 +1022,14 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, 16384, probe, &ev, s,
                     false, su ? &probe_r : nullptr);
     ix.tc = choose_tc(ev, ix.tq);
-    ix.n_wu = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq, ix.tc,
-                              ix.wu, &ix.evaluated_sym, s, kWuByStretch,
-                              su ? &ix.uruns : nullptr);
+    // FP32 units of small cells from groups of neighbouring cells
+    ix.wu_grouped = kFp32CellGroups && ix.small_cells && !su &&
+                    ix.opt.precision == SJ_PREC_FP32;
+    if (ix.wu_grouped) build_cell_groups(ix, ix.tq, ix.groups, s);
+    const CellGroups *grp = ix.wu_grouped ? &ix.groups : nullptr;
+    ix.n_wu = build_workunits(ix, 1, nullptr, 0, grp ? grp->run_off : ix.run_off_sym,
+                              grp ? grp->runs : ix.runs_sym, ix.tq, ix.tc, ix.wu,
+                              &ix.evaluated_sym, s, kWuByStretch, su ? &ix.uruns : nullptr, grp);
   }
   if (ix.opt.precision != SJ_PREC_FP32) {
     mfma_prepare(ix, s);
@@ -1294,6 +1357,10 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
         ix.band_cap = want;
         ix.band.alloc(ix.band_cap * 8);
       }
+      // result and recheck counts before this launch (a rerun starts from them)
+      uint64_t base[2] = {0, 0};
+      SJ_HIP(hipMemcpyAsync(base, ix.counters.p, 16, hipMemcpyDeviceToHost, s));
+      SJ_HIP(hipStreamSynchronize(s));
       for (int attempt = 0;; ++attempt) {
         SJ_HIP(hipMemsetAsync(band_cursor, 0, 8, s));
         m.view.band = ix.band.as<uint64_t>();
@@ -1307,7 +1374,9 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
         if (attempt == 2) fail(SJ_ERR_DEVICE, "band list size did not settle");
         ix.band_cap = nb + nb / 8;
         ix.band.alloc(ix.band_cap * 8);
-        SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));  // the join starts over
+        // the launch starts over
+        SJ_HIP(hipMemcpyAsync(ix.counters.p, base, 16, hipMemcpyHostToDevice, s));
+        SJ_HIP(hipStreamSynchronize(s));
       }
     }
   } else {
@@ -1412,7 +1481,9 @@ void run_single(sj_index &ix, uint64_t est, hipStream_t s) {
     SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
     const bool m = ix.prec != SJ_PREC_FP32;
     const bool self = !ix.entries;  // a self-join's units are symmetric
+    const bool grouped = !m && ix.wu_grouped;
     const DevBuf &runs = ix.opt.sortidu ? (m ? ix.uruns_m : ix.uruns)
+                         : grouped      ? ix.groups.runs
                                         : (self ? ix.runs_sym : ix.runs_full);
     join_launch(ix, m ? ix.wu_m : ix.wu, m ? ix.n_wu_m : ix.n_wu, runs, nullptr, self ? 1 : 0, 0,
                 ix.pairs.as<uint64_t>(), cap, s, &ms_join);

@@ -378,6 +378,57 @@ __global__ __launch_bounds__(kBlock) void k_runs(int pass, int sym, uint64_t nce
   if (!pass) run_count[A] = cnt;
 }
 
+// Union of the candidate runs of each group of consecutive cells
+// [gfirst[g], gfirst[g + 1]) (at most kGroupMaxCells cells): the cells' run
+// lists, each sorted and disjoint, merged in position order with
+// overlapping or touching ranges joined, so that no candidate appears
+// twice.  pass 0 counts the group's runs, pass 1 writes them at goff[g].
+__global__ __launch_bounds__(kBlock) void k_group_runs(int pass, uint64_t ngroup,
+                                                       const uint32_t *__restrict__ gfirst,
+                                                       const uint32_t *__restrict__ run_off,
+                                                       const uint2 *__restrict__ runs,
+                                                       uint32_t *__restrict__ gcount,
+                                                       const uint32_t *__restrict__ goff,
+                                                       uint2 *__restrict__ gruns) {
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= ngroup) return;
+  const uint32_t a0 = gfirst[g], na = gfirst[g + 1] - a0;
+  uint32_t at[kGroupMaxCells], end[kGroupMaxCells];
+  for (uint32_t i = 0; i < kGroupMaxCells; ++i) {
+    at[i] = i < na ? run_off[a0 + i] : 0u;
+    end[i] = i < na ? run_off[a0 + i + 1] : 0u;
+  }
+  uint32_t cnt = 0, w = pass ? goff[g] : 0u;
+  bool have = false;
+  uint2 cur = make_uint2(0u, 0u);
+  for (;;) {
+    int best = -1;
+    uint32_t bx = 0xffffffffu;
+    for (uint32_t i = 0; i < kGroupMaxCells; ++i)
+      if (at[i] < end[i] && runs[at[i]].x < bx) {
+        bx = runs[at[i]].x;
+        best = (int)i;
+      }
+    if (best < 0) break;
+    const uint2 r = runs[at[best]++];
+    if (have && r.x <= cur.y) {
+      cur.y = r.y > cur.y ? r.y : cur.y;
+    } else {
+      if (have) {
+        if (pass) gruns[w + cnt] = cur;
+        ++cnt;
+      }
+      cur = r;
+      have = true;
+    }
+  }
+  if (have) {
+    if (pass) gruns[w + cnt] = cur;
+    ++cnt;
+  }
+  if (!pass) gcount[g] = cnt;
+}
+
 // Work units (see WorkUnit).  Query slots of cell A are [qa, qb): positions
 // in contiguous mode, indices into the sorted query list in list mode.
 // In symmetric mode the first run of A starts at A itself and each query
@@ -453,7 +504,9 @@ __device__ __forceinline__ QBlock query_block(uint64_t t, int sym, uint64_t ncel
   }
   b.r0 = run_off[lo];
   b.r1 = run_off[lo + 1];
-  b.skip = sym ? (b.q0 - runs[b.r0].x) : 0u;
+  // a symmetric block starts at its first query's position (in list mode
+  // the list holds whole cells, so that position is qlist[q0])
+  b.skip = sym ? ((qlist ? qlist[b.q0] : b.q0) - runs[b.r0].x) : 0u;
   b.L = run_total[lo] - b.skip;
   return b;
 }
@@ -763,6 +816,15 @@ void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
   if (!ncell) return;
   hipLaunchKernelGGL(k_runs, dim3(blocks_for(ncell)), dim3(kBlock), 0, s, pass, sym, ncell,
                      cell_start, nbr_off, nbr_cell, run_count, run_off, runs);
+  SJ_HIP(hipGetLastError());
+}
+
+void launch_group_runs(int pass, uint64_t ngroup, const uint32_t *gfirst, const uint32_t *run_off,
+                       const uint2 *runs, uint32_t *gcount, const uint32_t *goff, uint2 *gruns,
+                       hipStream_t s) {
+  if (!ngroup) return;
+  hipLaunchKernelGGL(k_group_runs, dim3(blocks_for(ngroup)), dim3(kBlock), 0, s, pass, ngroup,
+                     gfirst, run_off, runs, gcount, goff, gruns);
   SJ_HIP(hipGetLastError());
 }
 

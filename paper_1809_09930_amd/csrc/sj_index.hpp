@@ -68,6 +68,12 @@ void launch_neighbors(int pass, const uint64_t *qkey, uint64_t nq, const uint64_
 void launch_runs(int pass, int sym, uint64_t ncell, const uint32_t *cell_start,
                  const uint32_t *nbr_off, const uint32_t *nbr_cell, uint32_t *run_count,
                  const uint32_t *run_off, uint2 *runs, hipStream_t s);
+// Union runs of groups of at most kGroupMaxCells consecutive cells (two
+// passes: count into gcount, then write at the scanned offsets goff).
+constexpr uint32_t kGroupMaxCells = 3;
+void launch_group_runs(int pass, uint64_t ngroup, const uint32_t *gfirst, const uint32_t *run_off,
+                       const uint2 *runs, uint32_t *gcount, const uint32_t *goff, uint2 *gruns,
+                       hipStream_t s);
 // Work units in three steps: per cell (query blocks, run total), per query
 // block (units, evaluated pairs), per query block (fill).  With per_block,
 // run_off / run_total are indexed by query block (each block has runs of

@@ -231,6 +231,17 @@ inline double gamma_n(double m, double u) { return m * u / (1.0 - m * u); }
 
 }  // namespace sj
 
+namespace sj {
+// Groups of consecutive small cells that share one work unit (see
+// build_cell_groups): n groups, group g holds the positions
+// [start[g], start[g + 1]) and the candidate runs
+// runs[run_off[g] .. run_off[g + 1]), the union of its cells' runs.
+struct CellGroups {
+  uint64_t n = 0;
+  DevBuf start, run_off, runs;
+};
+}  // namespace sj
+
 // The opaque handle of the C ABI.
 struct sj_index {
   typedef sj::DevBuf DevBuf;
@@ -292,6 +303,8 @@ struct sj_index {
   DevBuf norm_qa, norm_cr;      // its per-point tables
   DevBuf wu_m;
   uint64_t n_wu_m = 0, evaluated_sym_m = 0;
+  sj::CellGroups groups;       // groups of small cells (n = 0: none built)
+  bool wu_grouped = false;     // the FP32 units wu are cut from the groups
   uint32_t tq_m = 128, tc_m = 4096;
 
   // results
@@ -321,7 +334,13 @@ void build(sj_index &ix, const float *points, hipStream_t s);
 uint64_t build_workunits(sj_index &ix, int sym, const uint32_t *qlist, uint64_t nq,
                          const DevBuf &run_off, const DevBuf &runs, uint32_t tq, uint32_t tc,
                          DevBuf &out, uint64_t *eval, hipStream_t s, bool by_stretch = false,
-                         DevBuf *u_ranges = nullptr);
+                         DevBuf *u_ranges = nullptr, const CellGroups *groups = nullptr);
+// Groups of consecutive non-empty cells of ix (symmetric runs) for units of
+// up to max_q queries: a group takes the next cell while that cell lies in
+// the same row of the last indexed dimension, at most two cells past the
+// group's first, and the group stays within max_q points.  Its runs are the
+// union of its cells' symmetric runs.
+void build_cell_groups(sj_index &ix, uint32_t max_q, CellGroups &g, hipStream_t s);
 // Builds the query handle q (opt, n set) of the points `queries` against
 // the indexed set E (see sj_index::entries).
 void build_query(sj_index &q, const sj_index &E, const float *queries, hipStream_t s);

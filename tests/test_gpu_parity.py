@@ -881,3 +881,23 @@ def test_symmetric_batches_edge_cases():
     far = np.arange(12, dtype=np.float32)[:, None] * np.ones((1, 4), np.float32)
     info = assert_same_as_oracle(far, 0.5, min_batches=5)
     assert info["pairs"] == 12
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16", "bf16"])
+def test_small_cell_groups(prec):
+    """FP32 small-cell units take groups of up to three neighbouring cells
+    along the last indexed dimension (one unit of up to 64 queries, the union
+    of the cells' candidate runs); pairs inside a group, across groups and
+    with cells that join no group must all be found once: 2-D cells of about
+    18 points (groups of three), 3-D cells of a few points, clusters whose
+    cells straddle the limit of 64 queries, and a multi-batch run.  The
+    matrix-core precisions run the same cases with per-wave units."""
+    P = datagen.uniform_grid(20000, 2, 96)
+    info = assert_same_as_oracle(P, 0.03, precision=prec)
+    assert info["units"] == 2
+    Q = datagen.offgrid("uniform64", 8000, 3, 97)
+    assert assert_same_as_oracle(Q, calibrated(Q, 6), precision=prec)["units"] == 2
+    std = np.full(6, 0.01)
+    C = datagen.gaussian_mixture(6000, 6, 40, std, 98)
+    assert_same_as_oracle(C, 0.02, precision=prec)
+    assert_same_as_oracle(P, 0.03, precision=prec, min_batches=3)
