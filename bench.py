@@ -69,6 +69,9 @@ def parse():
                     help="instead of the self-join: the general join of N_b entity-partitioned "
                          "query sets Q_l (every N_b-th point from offset l) against the whole "
                          "workload, one query handle per set")
+    ap.add_argument("--batch-pairs", type=float, default=0,
+                    help="result batches of at most this many pairs (streamed to pinned host "
+                         "memory); 0 = as the memory budget allows")
     ap.add_argument("--sortidu", action="store_true",
                     help="build every index with SORTIDU (search along one un-indexed dimension)")
     ap.add_argument("--host-io", action="store_true",
@@ -362,11 +365,13 @@ def bench_k_sweep(a, P, Pd, eps):
     print(json.dumps(out), flush=True)
 
 
-def selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, record):
+def selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, record, batch_pairs=0):
     """One step: build (automatic k), run (estimate, join, recheck, sort in
-    device memory) and free, for every epsilon of the sweep."""
+    device memory, or in batches to pinned host memory) and free, for every
+    epsilon of the sweep."""
     for t, eps in zip(targets, eps_list):
-        h = sj.selfjoin_build_index(Pd, eps, precision=precision, sortidu=sortidu)
+        h = sj.selfjoin_build_index(Pd, eps, precision=precision, sortidu=sortidu,
+                                    batch_pairs=batch_pairs)
         total = sj.selfjoin_run(h)
         info = sj.selfjoin_get_info(h)
         perm = sj.selfjoin_get_perm(h, d)
@@ -375,15 +380,16 @@ def selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, record):
             record.append((t, eps, total, info, perm))
 
 
-def timed_steps(sj, Pd, d, eps_list, targets, precision, steps, warmup, sortidu=False):
+def timed_steps(sj, Pd, d, eps_list, targets, precision, steps, warmup, sortidu=False,
+                batch_pairs=0):
     import torch
     for _ in range(warmup):
-        selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, None)
+        selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, None, batch_pairs)
     torch.cuda.synchronize()
     recs = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, recs)
+        selfjoin_step(sj, Pd, d, eps_list, targets, precision, sortidu, recs, batch_pairs)
     torch.cuda.synchronize()
     return recs, time.perf_counter() - t0
 
@@ -644,7 +650,7 @@ def main():
         return
 
     recs, elapsed = timed_steps(sj, Pd, d, eps_list, targets, a.precision, a.steps, a.warmup,
-                                a.sortidu)
+                                a.sortidu, int(a.batch_pairs))
     fp32 = a.precision == "fp32"
     head, flops, tjoin = summarise(P, recs, elapsed, a.steps, len(targets), a.precision)
     achieved = flops / tjoin / 1e12 if tjoin > 0 else 0.0
@@ -675,7 +681,9 @@ def main():
                    "epsilons": eps_list,
                    "path": ("plain FP32 grid join" if fp32 else
                             "%s matrix-core join with FP64 band recheck" % a.precision)
-                   + ", k auto in 4..8, symmetric tiles" + (", SORTIDU" if a.sortidu else "")},
+                   + ", k auto in 4..8, symmetric tiles" + (", SORTIDU" if a.sortidu else "")
+                   + (", result batches of at most %d pairs in pinned host memory"
+                      % int(a.batch_pairs) if a.batch_pairs else "")},
         "result_pairs_per_s": head["result_pairs_per_s"],
         "per_epsilon": head["per_epsilon"],
         "roofline": {"bound": "alu" if fp32 else "mfma", "achieved": achieved,
@@ -703,7 +711,7 @@ def main():
     if compare:
         out["compare"] = compare
     default_line = (a.workload == "uniform_2m_d16" and not a.targets and not a.sortidu
-                    and fp32 and not a.no_extras)
+                    and fp32 and not a.no_extras and not a.batch_pairs)
     if default_line:
         print("bench: host-complete", file=sys.stderr, flush=True)
         out["host_complete"] = bench_host_complete(sj, P, Pd, eps_list, targets, "fp32")

@@ -19,10 +19,12 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <exception>
 #include <cstdio>
 #include <cstdlib>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -76,6 +78,97 @@ constexpr uint32_t kMaxBatchN = (1u << 20) - 1;  // positions fit 20 bits
 #endif
 constexpr uint32_t kBuildThreads = SJ_BUILD_THREADS;  // host threads building job indexes
 constexpr size_t kBuildScratchKeep = (size_t)256 << 20;  // scratch a build thread keeps
+
+// Host threads that build the jobs' indexes, one pool per device for the
+// life of the process.  Each thread owns a non-blocking stream on that
+// device, created once, and keeps its scratch chunks while a task runs; a
+// task hands out job indices through an atomic counter, and run() returns
+// when every job is done and every thread's stream has drained.  No thread
+// or stream is created or destroyed per call.
+class BuildPool {
+ public:
+  explicit BuildPool(int dev) : dev_(dev) {
+    const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const uint32_t n = std::max(1u, std::min(hw, kBuildThreads));
+    for (uint32_t w = 0; w < n; ++w) threads_.emplace_back([this] { loop(); });
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_done_.wait(lk, [this] { return ready_ == threads_.size(); });
+  }
+  // the pool lives until the process ends (threads wait on a condition
+  // variable, with no device work, when it does)
+  ~BuildPool() = delete;
+
+  // Runs fn(job, stream) for job = 0 .. njobs - 1 on the pool's threads.
+  void run(uint32_t njobs, const std::function<void(uint32_t, hipStream_t)> &fn) {
+    std::lock_guard<std::mutex> one(run_mu_);  // one task at a time per pool
+    std::unique_lock<std::mutex> lk(mu_);
+    // threads without a stream take no jobs; the others take them all
+    if (working_ == 0) fail(SJ_ERR_DEVICE, "no build thread could create its stream");
+    fn_ = &fn;
+    njobs_ = njobs;
+    next_.store(0);
+    busy_ = threads_.size();
+    ++gen_;
+    cv_work_.notify_all();
+    cv_done_.wait(lk, [this] { return busy_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void loop() {
+    hipStream_t st = nullptr;
+    bool ok = hipSetDevice(dev_) == hipSuccess &&
+              hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) (void)hipGetLastError();
+    uint64_t seen = 0;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (ok) ++working_;
+      ++ready_;
+      cv_done_.notify_all();
+    }
+    for (;;) {
+      const std::function<void(uint32_t, hipStream_t)> *fn = nullptr;
+      uint32_t njobs = 0;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_work_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        fn = fn_;
+        njobs = njobs_;
+      }
+      if (ok) {
+        Scratch &scr = thread_scratch();
+        scr.keep_bytes = kBuildScratchKeep;  // reuse chunks from one job to the next
+        for (uint32_t j = next_.fetch_add(1); j < njobs; j = next_.fetch_add(1)) (*fn)(j, st);
+        (void)hipStreamSynchronize(st);
+        scr.keep_bytes = 0;
+        scr.trim();
+      }
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--busy_ == 0) cv_done_.notify_all();
+    }
+  }
+
+  int dev_;
+  std::vector<std::thread> threads_;
+  std::mutex mu_, run_mu_;
+  std::condition_variable cv_work_, cv_done_;
+  const std::function<void(uint32_t, hipStream_t)> *fn_ = nullptr;
+  uint32_t njobs_ = 0;
+  std::atomic<uint32_t> next_{0};
+  size_t busy_ = 0, ready_ = 0, working_ = 0;
+  uint64_t gen_ = 0;
+};
+
+BuildPool &build_pool(int dev) {
+  static std::mutex mu;
+  static std::map<int, BuildPool *> pools;  // never freed (see ~BuildPool)
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it == pools.end()) it = pools.emplace(dev, new BuildPool(dev)).first;
+  return *it->second;
+}
 
 __global__ void k_tag_wus(WorkUnit *__restrict__ wu, uint64_t count, uint32_t job) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -303,27 +396,9 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
   }
   std::vector<std::exception_ptr> err(njobs);
   std::vector<float> ms_est(njobs, 0.0f);
-  std::atomic<uint32_t> next{0};
   std::atomic<bool> stop{false};
-  auto worker = [&]() {
-    // keep this thread's scratch chunks from one job to the next
-    Scratch &scr = thread_scratch();
-    const size_t keep0 = scr.keep_bytes;
-    scr.keep_bytes = kBuildScratchKeep;
-    hipStream_t ws = nullptr;
-    try {
-      SJ_HIP(hipSetDevice(dev));
-      SJ_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
-    } catch (...) {
-      const uint32_t j = next.fetch_add(1);
-      if (j < njobs) err[j] = std::current_exception();
-      stop = true;
-      scr.keep_bytes = keep0;
-      return;
-    }
-    for (;;) {
-      const uint32_t j = next.fetch_add(1);
-      if (j >= njobs || stop) break;
+  auto build_job = [&](uint32_t j, hipStream_t ws) {
+      if (stop) return;
       try {
         const sj_job &jb = jobs[j];
         std::unique_ptr<sj_index> ix(new sj_index());
@@ -345,20 +420,8 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
         err[j] = std::current_exception();
         stop = true;
       }
-    }
-    (void)hipStreamSynchronize(ws);
-    (void)hipStreamDestroy(ws);
-    scr.keep_bytes = keep0;
-    scr.trim();
   };
-  const uint32_t hw = std::max(1u, std::thread::hardware_concurrency());
-  const uint32_t nthr = std::max(1u, std::min({njobs, hw, kBuildThreads}));
-  {
-    std::vector<std::thread> pool;
-    for (uint32_t w = 1; w < nthr; ++w) pool.emplace_back(worker);
-    worker();
-    for (auto &th : pool) th.join();
-  }
+  build_pool(dev).run(njobs, build_job);
   for (uint32_t j = 0; j < njobs; ++j)
     if (err[j]) std::rethrow_exception(err[j]);
   for (uint32_t j = 0; j < njobs; ++j) {
