@@ -404,7 +404,10 @@ def per_eps_table(P, recs, ntargets, precision):
     n, d = P.shape
     per_eps, flops_total, time_total = {}, 0.0, 0.0
     for t, eps, total, info, perm in recs[:ntargets]:
-        ms = info["ms_join"] / max(info["join_launches"], 1)
+        # one join per epsilon: per launch (a rerun after an undersized
+        # buffer repeats it), or the sum over result batches
+        ms = (info["ms_join"] if info["batches"] > 1
+              else info["ms_join"] / max(info["join_launches"], 1))
         npair = (info["candidates"] + n) / 2.0
         row = {"eps": eps, "pairs": total, "sd": (total - n) / n, "k": info["k"],
                "cells": info["n_cells"], "candidates": info["candidates"],

@@ -1568,27 +1568,48 @@ void run_batched(sj_index &ix, uint64_t est, uint64_t per_batch, bool sym, hipSt
   const uint32_t bits = bits_for(n - 1);
   std::vector<int> qsh;
   for (uint32_t b = 0; b < bits; b += 8) qsh.push_back((int)b);
-  DevBuf qk[2], rt, p32, wu;
+  // every batch's query positions (caller indices [i0, i1), sorted on the
+  // device) and work units, before the first join: the copies of finished
+  // batches then overlap the next joins rather than the short launches and
+  // read-backs of this preparation (the copies run as kernels that hold
+  // the compute units)
+  struct Prep {
+    DevBuf p32, wu;
+    uint64_t nwu = 0;
+  };
+  std::vector<std::unique_ptr<Prep>> prep(nb);
+  {
+    DevBuf qk[2], rt;
+    const uint64_t nq_max = (n + nb - 1) / nb + 1;
+    qk[0].ensure(nq_max * 8);
+    qk[1].ensure(nq_max * 8);
+    rt.ensure(radix_tmp_bytes(nq_max));
+    for (uint64_t bi = 0; bi < nb; ++bi) {
+      const uint64_t i0 = n * bi / nb, i1 = n * (bi + 1) / nb;
+      prep[bi].reset(new Prep());
+      if (i1 <= i0) continue;
+      const uint64_t nq = i1 - i0;
+      Prep &pb = *prep[bi];
+      pb.p32.alloc(nq * 4);
+      launch_widen(ix.pos_of.as<uint32_t>() + i0, qk[0].as<uint64_t>(), nq, s);
+      uint64_t *kb[2] = {qk[0].as<uint64_t>(), qk[1].as<uint64_t>()};
+      radix_sort_u64(kb, nullptr, nq, qsh.data(), (int)qsh.size(), rt.p, s);
+      launch_narrow(kb[0], pb.p32.as<uint32_t>(), nq, s);
+      uint64_t ev = 0;
+      pb.nwu = build_workunits(ix, 0, pb.p32.as<uint32_t>(), nq, ix.run_off_full, ix.runs_full,
+                               mf ? ix.tq_single : ix.tq, mf ? ix.tc_single : ix.tc, pb.wu, &ev,
+                               s, kWuByStretch);
+      evaluated += ev;
+    }
+    SJ_HIP(hipStreamSynchronize(s));
+  }
   std::vector<std::unique_ptr<Event>> sort_ev;  // (start, end) of each sort, read at the end
   uint64_t slot = 0;
   for (uint64_t bi = 0; bi < nb; ++bi) {
     const uint64_t i0 = n * bi / nb, i1 = n * (bi + 1) / nb;
     if (i1 <= i0) continue;
-    const uint64_t nq = i1 - i0;
-    // positions of the caller indices [i0, i1), sorted on the device
-    qk[0].ensure(nq * 8);
-    qk[1].ensure(nq * 8);
-    p32.ensure(nq * 4);
-    launch_widen(ix.pos_of.as<uint32_t>() + i0, qk[0].as<uint64_t>(), nq, s);
-    rt.ensure(radix_tmp_bytes(nq));
-    uint64_t *kb[2] = {qk[0].as<uint64_t>(), qk[1].as<uint64_t>()};
-    radix_sort_u64(kb, nullptr, nq, qsh.data(), (int)qsh.size(), rt.p, s);
-    launch_narrow(kb[0], p32.as<uint32_t>(), nq, s);
-    uint64_t ev = 0;
-    const uint64_t nwu = build_workunits(ix, 0, p32.as<uint32_t>(), nq, ix.run_off_full,
-                                         ix.runs_full, mf ? ix.tq_single : ix.tq,
-                                         mf ? ix.tc_single : ix.tc, wu, &ev, s, kWuByStretch);
-    evaluated += ev;
+    const DevBuf &p32 = prep[bi]->p32, &wu = prep[bi]->wu;
+    const uint64_t nwu = prep[bi]->nwu;
     Slot &sl = slots[slot % kSlots];
     if (sl.busy) {
       SJ_HIP(hipEventSynchronize(sl.done_copy.e));
