@@ -1282,9 +1282,10 @@ int debug_box_mode();
 uint64_t read_counter(sj_index &ix, int which, hipStream_t s);
 constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
 // result + band pairs per 32 x 32 tile above which the matrix-core kernels
-// scan tile elements directly instead of testing each tile's minimum first
-constexpr double kFrequentHitsNarrow = 0.2;  // K padding <= 48 (mask hit path)
-constexpr double kFrequentHitsWide = 0.05;   // K padding > 48 (accumulator hit path)
+// scan every tile's elements instead of testing each tile's minimum first
+// (measured: 1.5 against the former 0.2 / 0.05 with a mask-building hit path
+// took the 2M x 16 FP16 join at S_D 512 from 168 to 135 ms)
+constexpr double kFrequentHits = 1.5;
 constexpr uint32_t kBoxMaxDims = 24;  // dimensions up to which workgroup units use the box
 constexpr double kBoxMaxHitsPerTile = 0.1;  // and hits per 32 x 32 tile below which
 
@@ -1334,11 +1335,9 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     m.cursor = a.cursor;
     m.rechecks = a.rechecks;
     m.per_wave = ix.mfma_per_wave ? 1 : 0;
-    // tiles with a hit common enough: scan elements directly (measured
-    // break-even: about one hit per five 32 x 32 tiles against the mask
-    // path of K <= 48, one per twenty against the accumulator path above)
+    // hits common enough: scan the elements of every tile directly
     const double per_tile = ix.hit_density * 1024.0;
-    m.hits_frequent = per_tile > (ix.kp > 48 ? kFrequentHitsWide : kFrequentHitsNarrow) ? 1 : 0;
+    m.hits_frequent = per_tile > kFrequentHits ? 1 : 0;
     if (const int forced = debug_hits_mode(); forced >= 0) m.hits_frequent = forced;
     // the query-box prefilter pays where 8 dimensions are a good part of
     // the distance (the bound uses the first 8 of the variance order) and

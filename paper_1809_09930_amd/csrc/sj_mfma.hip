@@ -294,130 +294,6 @@ __device__ __forceinline__ bool tiles_any(const float16v (&acc)[QB], const float
   return any;
 }
 
-// Element-by-element filter of QB tiles with at least one candidate hit.
-// The accumulators are first reduced to two 16-bit masks per tile (at or
-// below the upper and the lower threshold), so the rest of the path holds
-// no accumulator; it runs only for the rare tiles with a hit.  Element e of
-// a lane's tile is candidate row c0 + 8*(e/4) + 4*half + e%4.
-template <int QB>
-__device__ __forceinline__ void tiles_hits(const float16v (&acc)[QB], const float (&th)[QB],
-                                           const float (&tl)[QB], const uint32_t (&qpos)[QB],
-                                           uint32_t c0, uint32_t cend, uint32_t half,
-                                           const MfmaView &v, Stage &st, BandSink &bs,
-                                           uint64_t *__restrict__ out, uint64_t capacity,
-                                           unsigned long long *__restrict__ cursor,
-                                           uint64_t &n_recheck) {
-  uint32_t mh[QB], ml[QB];
-#pragma unroll
-  for (int j = 0; j < QB; ++j) {
-    uint32_t a = 0, b = 0;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      a |= (acc[j][e] <= th[j] ? 1u : 0u) << e;
-      b |= (acc[j][e] <= tl[j] ? 1u : 0u) << e;
-    }
-    mh[j] = a;
-    ml[j] = b;
-  }
-  const bool sym = v.symmetric != 0;
-#pragma unroll
-  for (int j = 0; j < QB; ++j) {
-    SJ_UNROLL(SJ_HIT_UNROLL)
-    for (uint32_t e = 0; e < 16; ++e) {
-      const bool h = ((mh[j] >> e) & 1u) != 0u;
-      if (ballot(h) == 0) continue;
-      const uint32_t cp = c0 + 8u * (e / 4u) + 4u * half + (e % 4u);
-      const bool ok = h && cp < cend && (!sym || qpos[j] <= cp);
-      bool acc_ok = ok && ((ml[j] >> e) & 1u) != 0u;
-      const bool band = ok && !acc_ok;
-      const uint64_t bm = ballot(band);
-      if (bm) {
-        if (bs.buf) {  // deferred: the pair waits in the band list
-          const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
-          if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
-          if (band)
-            bs.st.buf[bs.st.cnt + lanes_below(bm)] =
-                v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
-          bs.st.cnt += nb;
-        } else {
-          if (band)
-            acc_ok = canonical_within(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
-          n_recheck += (uint64_t)__builtin_popcountll(bm);
-        }
-      }
-      const uint64_t am = ballot(acc_ok);
-      if (am == 0) continue;
-      // keys hold cell-order positions; they are mapped to caller indices
-      // before the result is sorted
-      const bool two = acc_ok && sym && qpos[j] != cp;
-      const uint64_t m2 = ballot(two);
-      const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
-      if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
-      const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
-      if (acc_ok) {
-        st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
-        if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
-      }
-      st.cnt += total;
-    }
-  }
-}
-
-// The same filter reading the accumulators element by element (fully
-// unrolled, accumulators live throughout): fewer instructions per hit tile
-// than building the masks, at a higher register count, which matters less
-// when the operands of a long K already dominate the registers.
-template <int QB>
-__device__ __forceinline__ void tiles_hits_acc(const float16v (&acc)[QB], const float (&th)[QB],
-                                               const float (&tl)[QB],
-                                               const uint32_t (&qpos)[QB], uint32_t c0,
-                                               uint32_t cend, uint32_t half, const MfmaView &v,
-                                               Stage &st, BandSink &bs, uint64_t *__restrict__ out,
-                                               uint64_t capacity,
-                                               unsigned long long *__restrict__ cursor,
-                                               uint64_t &n_recheck) {
-  const bool sym = v.symmetric != 0;
-#pragma unroll
-  for (int j = 0; j < QB; ++j) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const bool h = acc[j][e] <= th[j];
-      if (ballot(h) == 0) continue;
-      const uint32_t cp = c0 + 8 * (e / 4) + 4 * half + (e % 4);
-      const bool ok = h && cp < cend && (!sym || qpos[j] <= cp);
-      bool acc_ok = ok && acc[j][e] <= tl[j];
-      const bool band = ok && !acc_ok;
-      const uint64_t bm = ballot(band);
-      if (bm) {
-        if (bs.buf) {  // deferred: the pair waits in the band list
-          const uint32_t nb = (uint32_t)__builtin_popcountll(bm);
-          if (bs.st.cnt + nb > (uint32_t)kBandStage) flush(bs.st, bs.buf, bs.cap, bs.cursor);
-          if (band)
-            bs.st.buf[bs.st.cnt + lanes_below(bm)] =
-                v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
-          bs.st.cnt += nb;
-        } else {
-          if (band)
-            acc_ok = canonical_within(v.Xq, qpos[j], v.X, cp, v.inv_perm, v.d, v.dp, v.eps2);
-          n_recheck += (uint64_t)__builtin_popcountll(bm);
-        }
-      }
-      const uint64_t am = ballot(acc_ok);
-      if (am == 0) continue;
-      const bool two = acc_ok && sym && qpos[j] != cp;
-      const uint64_t m2 = ballot(two);
-      const uint32_t total = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
-      if (st.cnt + total > (uint32_t)kStage) flush(st, out, capacity, cursor);
-      const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
-      if (acc_ok) {
-        st.buf[off] = v.key_hi | ((uint64_t)qpos[j] << v.pshift) | cp;
-        if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)cp << v.pshift) | qpos[j];
-      }
-      st.cnt += total;
-    }
-  }
-}
-
 // Hit path for tiles where hits are common (clustered data: a few result or
 // band pairs in most tiles).  No minimum over the tile first: the 16 element
 // compares of a query block are the wave masks themselves, taken four
@@ -486,20 +362,10 @@ __device__ __forceinline__ void tiles_hits_scan(const float16v (&acc)[QB], const
 }
 
 // Hit modes of the single-join kernels: kHitsRare tests the minimum of each
-// tile first and enters a hit path only for tiles with a hit; kHitsFrequent
+// tile first and scans the elements only of tiles with a hit; kHitsFrequent
 // goes straight to the element scan.
 constexpr int kHitsRare = 0;
 constexpr int kHitsFrequent = 1;
-
-// K padding above which the workgroup kernel takes the accumulator-based
-// hit path; the persistent batched kernel holds all its variants in one
-// register allocation and keeps the mask path throughout.
-#ifndef SJ_HIT_ACC_ABOVE_KP
-#define SJ_HIT_ACC_ABOVE_KP 48
-#endif
-#ifndef SJ_BATCH_HIT_ACC_ABOVE_KP
-#define SJ_BATCH_HIT_ACC_ABOVE_KP 1024
-#endif
 
 // Walks the 32-row candidate blocks of a work unit, run by run.
 struct BlockIter {
@@ -604,12 +470,8 @@ __device__ __forceinline__ void mfma_unit(const MfmaView &v, const WorkUnit &wu,
       tiles_hits_scan<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
                           n_recheck);
     } else if (ballot(tiles_any<QB>(acc, th))) {
-      if constexpr (KP > SJ_BATCH_HIT_ACC_ABOVE_KP)
-        tiles_hits_acc<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
-                           n_recheck);
-      else
-        tiles_hits<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
-                       n_recheck);
+      tiles_hits_scan<QB>(acc, th, tl, qpos, c, ce, half, v, st, bs, out, capacity, cursor,
+                          n_recheck);
     }
     if (!more) break;
 #pragma unroll
@@ -761,12 +623,8 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg(MfmaView v,
       tiles_hits_scan<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
                           n_recheck);
     } else if (ballot(tiles_any<QB>(acc, th))) {
-      if constexpr (KP > SJ_HIT_ACC_ABOVE_KP)
-        tiles_hits_acc<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
-                           n_recheck);
-      else
-        tiles_hits<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
-                       n_recheck);
+      tiles_hits_scan<QB>(acc, th, tl, qpos, c0, cend, half, v, st, bs, out, capacity, cursor,
+                          n_recheck);
     }
   };
   auto block_mfma = [&](int buf, int blk, float16v(&acc)[QB]) __attribute__((always_inline)) {
