@@ -526,7 +526,8 @@ def bench_other_configs(sj, table):
     path against the plain FP32 path on the same data (few steps each)."""
     import torch
     out = {}
-    plan = [("uniform_2m_d64", [("fp16", 2, 1), ("fp32", 1, 0)]),
+    # the 2M x 64 configuration names BF16 tiles; FP16 runs beside them
+    plan = [("uniform_2m_d64", [("fp16", 2, 1), ("bf16", 2, 1), ("fp32", 1, 0)]),
             ("mixture50_5m_d18", [("fp16", 3, 1), ("fp32", 3, 1)]),
             ("mixture20_515k_d90", [("fp16", 3, 1), ("fp32", 2, 1)])]
     for name, runs in plan:
@@ -539,7 +540,9 @@ def bench_other_configs(sj, table):
             print("bench: %s %s" % (name, prec), file=sys.stderr, flush=True)
             recs, el = timed_steps(sj, Pd, P.shape[1], eps_list, targets, prec, steps, warmup)
             row[prec] = summarise(P, recs, el, steps, len(targets), prec)[0]
-        row["speedup_fp16_vs_fp32"] = row["fp16"]["value"] / row["fp32"]["value"]
+        for prec in ("fp16", "bf16"):
+            if prec in row:
+                row["speedup_%s_vs_fp32" % prec] = row[prec]["value"] / row["fp32"]["value"]
         out[name] = row
         del Pd
         torch.cuda.empty_cache()
