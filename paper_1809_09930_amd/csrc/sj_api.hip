@@ -412,9 +412,11 @@ uint64_t build_grid(sj_index &ix, const float *P, const Geometry &g, BuildTmp &t
   launch_cellkey(P, n, ix.d, g.kp, t.keys[0].as<uint64_t>(), t.ids[0].as<uint32_t>(), s);
   uint64_t *kb[2] = {t.keys[0].as<uint64_t>(), t.keys[1].as<uint64_t>()};
   uint32_t *vb[2] = {t.ids[0].as<uint32_t>(), t.ids[1].as<uint32_t>()};
+  // a probe of k only counts candidates: the cell part of the keys, without
+  // the point ids, is all it sorts
   std::vector<int> shifts;
-  for (uint32_t b = 0; b < g.key_bits; b += 8) shifts.push_back((int)b);
-  radix_sort_u64(kb, vb, n, shifts.data(), (int)shifts.size(), t.radix.p, s);
+  for (uint32_t b = keep ? 0u : g.fine_bits; b < g.key_bits; b += 8) shifts.push_back((int)b);
+  radix_sort_u64(kb, keep ? vb : nullptr, n, shifts.data(), (int)shifts.size(), t.radix.p, s);
   if (keep) {
     launch_gather(P, n, ix.d, ix.dp, ix.perm_d.as<uint32_t>(), vb[0], ix.X.as<float>(),
                   ix.orig_id.as<uint32_t>(), ix.pos_of.as<uint32_t>(), s);
