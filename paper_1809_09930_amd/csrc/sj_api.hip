@@ -1007,10 +1007,12 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
   if (ix.opt.precision == SJ_PREC_FP32) choose_fp32_form(ix, s);
   // one query per lane when units of the class's width would spend more
   // than a quarter of their lane work on idle query slots (many small cells)
+  // (a job of the batched path runs on the matrix cores with its own units)
   ix.small_cells =
+      !ix.batch_job &&
       live_slot_share(ix, t.cand_sum.as<uint64_t>(),
                       64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form, false), s) <
-      kLiveSlotShareMin;
+          kLiveSlotShareMin;
   ix.tq = 64u * (uint32_t)fp32_rq_for(ix.dp, ix.norm_form, ix.small_cells);
   ix.info.units = ix.small_cells ? SJ_UNITS_SMALL_CELLS : SJ_UNITS_CELL;
   uint64_t ev = 0;
@@ -1041,6 +1043,7 @@ void build(sj_index &ix, const float *points, hipStream_t s) {
     // quarter of the workgroup units' lane work would fall on idle query
     // slots (the work-weighted test of the FP32 join)
     const uint32_t tq_wg = mfma_wg_queries(ix.kp);
+    // (also for a job of the batched path: its sampled count runs these units)
     ix.mfma_per_wave =
         live_slot_share(ix, t.cand_sum.as<uint64_t>(), tq_wg, s) < kLiveSlotShareMin;
     ix.info.units = ix.mfma_per_wave ? SJ_UNITS_SMALL_CELLS : SJ_UNITS_CELL;
