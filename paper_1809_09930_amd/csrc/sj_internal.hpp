@@ -55,17 +55,24 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 // rounded (no contraction), accepted iff the sum is <= eps2.  Every device
 // filter sends the pairs it cannot decide here, so this is the one place the
 // include/exclude decision is taken in FP64.
-#ifndef SJ_RECHECK_INLINE
-#define SJ_RECHECK_INLINE __noinline__
-#endif
-static __device__ SJ_RECHECK_INLINE bool canonical_within(const float *__restrict__ XA, uint32_t a,
-                                                          const float *__restrict__ XB, uint32_t b,
-                                                          const uint16_t *__restrict__ inv_perm,
-                                                          uint32_t d, uint32_t dp, double eps2) {
+// The body is inlined into the kernels that do nothing but recheck (one pair
+// per lane), with the loop unrolled U times so that the loads of several
+// dimensions are in flight together; unrolling keeps the order of the
+// additions.  The join kernels call it out of line and not unrolled
+// (SJ_RECHECK_INLINE), as their rare band lanes would otherwise carry its
+// registers everywhere.
+template <int U>
+static __device__ __forceinline__ bool canonical_within_body(const float *__restrict__ XA,
+                                                             uint32_t a,
+                                                             const float *__restrict__ XB,
+                                                             uint32_t b,
+                                                             const uint16_t *__restrict__ inv_perm,
+                                                             uint32_t d, uint32_t dp, double eps2) {
 #pragma clang fp contract(off)
   const float *pa = XA + (uint64_t)a * dp;
   const float *pb = XB + (uint64_t)b * dp;
   double acc = 0.0;
+#pragma unroll U
   for (uint32_t t = 0; t < d; ++t) {
     const uint32_t r = inv_perm[t];
     const double diff = (double)pa[r] - (double)pb[r];
@@ -73,6 +80,15 @@ static __device__ SJ_RECHECK_INLINE bool canonical_within(const float *__restric
     acc = acc + sq;
   }
   return acc <= eps2;
+}
+#ifndef SJ_RECHECK_INLINE
+#define SJ_RECHECK_INLINE __noinline__
+#endif
+static __device__ SJ_RECHECK_INLINE bool canonical_within(const float *__restrict__ XA, uint32_t a,
+                                                          const float *__restrict__ XB, uint32_t b,
+                                                          const uint16_t *__restrict__ inv_perm,
+                                                          uint32_t d, uint32_t dp, double eps2) {
+  return canonical_within_body<1>(XA, a, XB, b, inv_perm, d, dp, eps2);
 }
 
 // float <-> order-preserving uint32 (for atomic min/max of finite floats)

@@ -998,16 +998,108 @@ __global__ __launch_bounds__(kBlock) void k_join_mfma_wg_box(MfmaView v,
 // Deferred FP64 recheck of the band pairs of a launch: one pair per lane,
 // all lanes busy, instead of the few band lanes of one tile element at a
 // time.  Accepted pairs are staged and appended like the join's own.
+constexpr int kRecheckUnroll = 8;
+constexpr int kRecheckBlocksPerCu = 8;
+
+// Appends the pairs of one batch of rechecks (lane: pair q, c, accepted or
+// not; both orders in a symmetric join).
+__device__ __forceinline__ void emit_rechecked(const MfmaView &v, bool ok, uint32_t q, uint32_t c,
+                                               Stage &st, uint64_t *__restrict__ out,
+                                               uint64_t capacity,
+                                               unsigned long long *__restrict__ cursor) {
+  const uint64_t am = ballot(ok);
+  if (am == 0) return;
+  const bool two = ok && v.symmetric != 0 && q != c;
+  const uint64_t m2 = ballot(two);
+  const uint32_t n = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
+  if (st.cnt + n > (uint32_t)kStage) flush(st, out, capacity, cursor);
+  const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
+  if (ok) {
+    st.buf[off] = v.key_hi | ((uint64_t)q << v.pshift) | c;
+    if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)c << v.pshift) | q;
+  }
+  st.cnt += n;
+}
+
+// Rows of up to DPM padded dimensions: one wave per workgroup.  The wave
+// first copies the two rows of each of its 64 pairs into LDS, 16 bytes per
+// lane and whole row segments per instruction (a row costs two or four
+// cache-line requests instead of one per dimension and lane); each lane then
+// evaluates its pair from LDS in the caller's dimension order.  Rows are
+// DPM + 1 floats apart, so the lanes' reads of one dimension fall in
+// different banks.
+template <int DPM>
+__global__ __launch_bounds__(kWave) void k_band_recheck_staged(
+    MfmaView v, const unsigned long long *__restrict__ band_count, uint64_t *__restrict__ out,
+    uint64_t capacity, unsigned long long *__restrict__ cursor,
+    unsigned long long *__restrict__ rechecks) {
+  constexpr int kRow = DPM + 1;
+  constexpr int kVecs = 2 * kWave * DPM / 4 / kWave;  // 16-byte loads per lane and batch
+  __shared__ float rows[2][kWave][kRow];
+  __shared__ uint32_t pos[2][kWave];
+  __shared__ uint64_t stage_mem[kStage];
+  __shared__ uint16_t perm[SJ_MAX_DIM];
+  const uint32_t l = threadIdx.x;
+  for (uint32_t t = l; t < v.d; t += kWave) perm[t] = v.inv_perm[t];
+  Stage st{stage_mem, 0u};
+  const uint64_t total = *band_count;
+  const uint64_t count = total < v.band_cap ? total : v.band_cap;
+  const uint32_t dv = v.dp / 4;  // 16-byte vectors per row (dp <= DPM, a multiple of 8)
+  for (uint64_t base = (uint64_t)blockIdx.x * kWave; base < count;
+       base += (uint64_t)gridDim.x * kWave) {
+    const uint64_t i = base + l;
+    const bool live = i < count;
+    uint32_t q = 0, c = 0;  // lanes past the end stage row 0 and drop it
+    if (live) {
+      const uint64_t key = v.band[i];
+      q = (uint32_t)(key >> 32);
+      c = (uint32_t)key;
+    }
+    pos[0][l] = q;
+    pos[1][l] = c;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kVecs; ++k) {
+      // vector e of the batch's 2 x 64 rows of DPM / 4 vectors
+      const uint32_t e = (uint32_t)k * kWave + l;
+      const uint32_t row = e / (DPM / 4), col = e % (DPM / 4);
+      const uint32_t side = row / kWave, slot = row % kWave;
+      if (col < dv) {
+        const float *src = side ? v.X : v.Xq;
+        const float4 x =
+            *reinterpret_cast<const float4 *>(src + (uint64_t)pos[side][slot] * v.dp + col * 4);
+        float *dst = &rows[side][slot][col * 4];
+        dst[0] = x.x;
+        dst[1] = x.y;
+        dst[2] = x.z;
+        dst[3] = x.w;
+      }
+    }
+    __syncthreads();
+    const bool ok = live && canonical_within_body<kRecheckUnroll>(&rows[0][l][0], 0, &rows[1][l][0],
+                                                                 0, perm, v.d, 0, v.eps2);
+    __syncthreads();  // the rows are overwritten by the next batch
+    emit_rechecked(v, ok, q, c, st, out, capacity, cursor);
+  }
+  flush(st, out, capacity, cursor);
+  if (blockIdx.x == 0 && l == 0 && count) atomicAdd(rechecks, (unsigned long long)count);
+}
+
+// Rows of more padded dimensions: each lane gathers its two rows from
+// memory in the caller's dimension order, the predicate's loop unrolled so
+// that those loads overlap.
 __global__ __launch_bounds__(kBlock) void k_band_recheck(
     MfmaView v, const unsigned long long *__restrict__ band_count, uint64_t *__restrict__ out,
     uint64_t capacity, unsigned long long *__restrict__ cursor,
     unsigned long long *__restrict__ rechecks) {
   __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
+  __shared__ uint16_t perm[SJ_MAX_DIM];  // the dimension map, read by every lane
+  for (uint32_t t = threadIdx.x; t < v.d; t += kBlock) perm[t] = v.inv_perm[t];
+  __syncthreads();
   const uint32_t w = uniform_u32(threadIdx.x / kWave);
   Stage st{&stage_mem[w][0], 0u};
   const uint64_t total = *band_count;
   const uint64_t count = total < v.band_cap ? total : v.band_cap;
-  const bool sym = v.symmetric != 0;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (uint64_t)w * kWave; base < count;
        base += stride) {
@@ -1018,20 +1110,9 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck(
       const uint64_t key = v.band[i];
       q = (uint32_t)(key >> 32);
       c = (uint32_t)key;
-      ok = canonical_within(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
+      ok = canonical_within_body<kRecheckUnroll>(v.Xq, q, v.X, c, perm, v.d, v.dp, v.eps2);
     }
-    const uint64_t am = ballot(ok);
-    if (am == 0) continue;
-    const bool two = ok && sym && q != c;
-    const uint64_t m2 = ballot(two);
-    const uint32_t n = (uint32_t)(__builtin_popcountll(am) + __builtin_popcountll(m2));
-    if (st.cnt + n > (uint32_t)kStage) flush(st, out, capacity, cursor);
-    const uint32_t off = st.cnt + lanes_below(am) + lanes_below(m2);
-    if (ok) {
-      st.buf[off] = v.key_hi | ((uint64_t)q << v.pshift) | c;
-      if (two) st.buf[off + 1] = v.key_hi | ((uint64_t)c << v.pshift) | q;
-    }
-    st.cnt += n;
+    emit_rechecked(v, ok, q, c, st, out, capacity, cursor);
   }
   flush(st, out, capacity, cursor);
   if (blockIdx.x == 0 && threadIdx.x == 0 && count) atomicAdd(rechecks, (unsigned long long)count);
@@ -1126,7 +1207,7 @@ __global__ __launch_bounds__(kBlock) void k_band_recheck_batched(
       const uint32_t job = (uint32_t)(key >> 40);
       const uint32_t q = (uint32_t)((key >> 20) & kMask), c = (uint32_t)(key & kMask);
       const MfmaView &v = jobs[job].view;
-      ok = canonical_within(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
+      ok = canonical_within_body<kRecheckUnroll>(v.Xq, q, v.X, c, v.inv_perm, v.d, v.dp, v.eps2);
       two = ok && v.symmetric && q != c;
       rkey = ((uint64_t)job << 40) | ((uint64_t)c << 20) | q;
     }
@@ -1364,8 +1445,16 @@ void launch_band_recheck(const MfmaView &v, uint64_t *out, uint64_t capacity,
   int dev = 0, cus = 256;
   SJ_HIP(hipGetDevice(&dev));
   SJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  hipLaunchKernelGGL(k_band_recheck, dim3((uint32_t)cus * 4), dim3(kBlock), 0, s, v,
-                     v.band_cursor, out, capacity, cursor, rechecks);
+  const dim3 grid((uint32_t)cus * kRecheckBlocksPerCu);
+  if (v.dp <= 32)
+    hipLaunchKernelGGL(k_band_recheck_staged<32>, grid, dim3(kWave), 0, s, v, v.band_cursor, out,
+                       capacity, cursor, rechecks);
+  else if (v.dp <= 64)
+    hipLaunchKernelGGL(k_band_recheck_staged<64>, grid, dim3(kWave), 0, s, v, v.band_cursor, out,
+                       capacity, cursor, rechecks);
+  else
+    hipLaunchKernelGGL(k_band_recheck, grid, dim3(kBlock), 0, s, v, v.band_cursor, out, capacity,
+                       cursor, rechecks);
   SJ_HIP(hipGetLastError());
 }
 
