@@ -1285,7 +1285,8 @@ bool debug_undersize();
 int debug_hits_mode();
 int debug_box_mode();
 uint64_t read_counter(sj_index &ix, int which, hipStream_t s);
-constexpr uint64_t kBandStart = 1u << 20;  // least band-list slots
+constexpr uint64_t kBandStart = 1u << 20;       // least band-list slots of a join
+constexpr uint64_t kCountBandStart = 1u << 16;  // and of a sampled count
 // result + band pairs per 32 x 32 tile above which the matrix-core kernels
 // scan every tile's elements instead of testing each tile's minimum first
 // (measured: 1.5 against the former 0.2 / 0.05 with a mask-building hit path
@@ -1350,13 +1351,13 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
     // 13 % faster at 0.004 and 0.03 hits per tile, 15 % slower at 0.26)
     m.box = !m.per_wave && ix.d <= kBoxMaxDims && per_tile < kBoxMaxHitsPerTile ? 1 : 0;
     if (const int forced = debug_box_mode(); forced >= 0) m.box = m.per_wave ? 0 : forced;
-    if (count_only) {
-      launch_join_mfma(m, s);  // band pairs rechecked in place
-    } else {
+    {
       // band pairs are collected during the join and rechecked afterwards,
       // one per lane; a band list that overflowed is grown and the join rerun
+      // (a count-only pass counts the accepted band pairs the same way)
       unsigned long long *band_cursor = ix.counters.as<unsigned long long>() + 2;
-      const uint64_t want = debug_undersize() ? 16 : std::max(kBandStart, ix.band_hint);
+      const uint64_t least = count_only ? kCountBandStart : kBandStart;
+      const uint64_t want = debug_undersize() ? 16 : std::max(least, ix.band_hint);
       if (ix.band_cap < want) {
         ix.band_cap = want;
         ix.band.alloc(ix.band_cap * 8);
@@ -1371,8 +1372,8 @@ void join_launch(sj_index &ix, const DevBuf &wu, uint64_t n_wu, const DevBuf &ru
         m.view.band_cap = ix.band_cap;
         m.view.band_cursor = band_cursor;
         launch_join_mfma(m, s);
-        ix.info.join_launches++;
-        launch_band_recheck(m.view, out, cap, a.cursor, a.rechecks, s);
+        if (!count_only) ix.info.join_launches++;
+        launch_band_recheck(m.view, m.out, m.capacity, a.cursor, a.rechecks, s);
         const uint64_t nb = read_counter(ix, 2, s);
         if (nb <= ix.band_cap) break;
         if (attempt == 2) fail(SJ_ERR_DEVICE, "band list size did not settle");
@@ -1426,8 +1427,8 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
   ql.alloc(nq * 4);
   launch_iota_strided(ql.as<uint32_t>(), nq, stride, run, s);
   uint64_t ev = 0;
-  // the matrix-core path counts with its own filter (no keys are stored at
-  // capacity 0); the FP32 path has a count-only kernel
+  // the matrix-core path counts with its own filter and its band list (no
+  // keys are stored at capacity 0); the FP32 path has a count-only kernel
   const bool mf = ix.prec != SJ_PREC_FP32;
   // candidate chunks of at most 4096: the sample's few units are split
   // finely enough to spread over the chip
@@ -1436,12 +1437,14 @@ uint64_t estimate_pairs(sj_index &ix, hipStream_t s, float *ms) {
                                        mf ? std::min<uint32_t>(ix.tc_single, 4096) : 4096, wu,
                                        &ev, s);
   SJ_HIP(hipMemsetAsync(ix.counters.p, 0, 16, s));
+  // the sample's band list: at most one pair in 512 is expected in the band
+  // (a larger band reruns the count with the list at its exact size)
+  if (mf) ix.band_hint = ev / 512;
   join_launch(ix, wu, nwu, ix.runs_full, ql.as<uint32_t>(), 0, 1, nullptr, 0, s, ms);
   const uint64_t cnt = read_counter(ix, 0, s);
   const double scale = (double)n / (double)nq;
   if (mf) {
-    // band pairs of the sample (rechecked in place here) size the deferred
-    // recheck list of the join
+    // band pairs of the sample size the deferred recheck list of the join
     const double nband = (double)read_counter(ix, 1, s);
     ix.band_hint = (uint64_t)std::ceil(nband * scale * 1.25) + (1u << 16);
     ix.hit_density = ev ? ((double)cnt + nband) / (double)ev : 0.0;
