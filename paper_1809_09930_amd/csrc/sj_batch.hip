@@ -55,6 +55,7 @@ struct sj_batch {
   uint64_t capacity = 0;
   uint32_t tc = 4096, grab = 1;
   uint32_t grid = 0;
+  int dev = 0;  // device of the batch (and of its build pool)
   int job_bits = 1;
   hipStream_t cs = nullptr;
   hipGraph_t graph = nullptr;
@@ -210,16 +211,26 @@ void tune_cache_store(const std::string &sig, uint32_t tc, uint32_t grab) {
 
 // Concatenated work units of all jobs with candidate stretches of length tc,
 // biggest jobs first (longest-processing-time order for the shared queue).
+// Each job's units are cut on the build pool (a chain of short launches and
+// read-backs per job, several in flight), then copied into one queue on s.
 void make_queue(sj_batch &b, uint32_t tc, hipStream_t s) {
   const size_t nj = b.jobs.size();
   std::vector<DevBuf> per(nj);
   std::vector<uint64_t> cnt(nj), ev(nj);
-  for (size_t j = 0; j < nj; ++j) {
-    sj_index &ix = *b.jobs[j];
-    if (ix.n == 0) continue;
-    cnt[j] = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_m, tc, per[j],
-                             &ev[j], s);
-  }
+  std::vector<std::exception_ptr> err(nj);
+  build_pool(b.dev).run((uint32_t)nj, [&](uint32_t j, hipStream_t ws) {
+    try {
+      sj_index &ix = *b.jobs[j];
+      if (ix.n == 0) return;
+      // returns after its stream has drained: per[j] is complete
+      cnt[j] = build_workunits(ix, 1, nullptr, 0, ix.run_off_sym, ix.runs_sym, ix.tq_m, tc,
+                               per[j], &ev[j], ws);
+    } catch (...) {
+      err[j] = std::current_exception();
+    }
+  });
+  for (size_t j = 0; j < nj; ++j)
+    if (err[j]) std::rethrow_exception(err[j]);
   std::vector<size_t> order(nj);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return ev[a] > ev[c]; });
@@ -331,18 +342,26 @@ float time_join(sj_batch &b) {
   return elapsed_ms(e0, e1);
 }
 
+// The stretch and grab the tuner chose before for a batch of this signature.
+bool tune_cache_lookup(const sj_batch &b, uint32_t *tc, uint32_t *grab) {
+  const std::string sig = batch_signature(b);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune_cache.empty()) tune_cache_load();
+  auto it = g_tune_cache.find(sig);
+  if (it == g_tune_cache.end()) return false;
+  *tc = it->second.first;
+  *grab = it->second.second;
+  return true;
+}
+
 void autotune(sj_batch &b) {
   const std::string sig = batch_signature(b);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (g_tune_cache.empty()) tune_cache_load();
-    auto it = g_tune_cache.find(sig);
-    if (it != g_tune_cache.end()) {
-      if (b.tc != it->second.first) make_queue(b, it->second.first, b.cs);
-      b.grab = it->second.second;
-      b.info.tuned = 2;
-      return;
-    }
+  uint32_t tc_known = 0, grab_known = 0;
+  if (tune_cache_lookup(b, &tc_known, &grab_known)) {
+    if (b.tc != tc_known) make_queue(b, tc_known, b.cs);
+    b.grab = grab_known;
+    b.info.tuned = 2;
+    return;
   }
   const uint32_t tcs[] = {1024, 4096, 16384};
   const uint32_t grabs[] = {1, 4};
@@ -375,6 +394,7 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
   SJ_HIP(hipStreamCreateWithFlags(&b.cs, hipStreamNonBlocking));
   int dev = 0;
   SJ_HIP(hipGetDevice(&dev));
+  b.dev = dev;
   auto t0 = std::chrono::steady_clock::now();
   b.jobs.resize(njobs);
   b.est.assign(njobs, 0);
@@ -465,7 +485,11 @@ void run_batch(sj_batch &b, const sj_job *jobs, uint32_t njobs, const sj_options
   hipDeviceProp_t prop;
   SJ_HIP(hipGetDeviceProperties(&prop, dev));
   b.grid = (uint32_t)(prop.multiProcessorCount * batched_blocks_per_cu());
-  make_queue(b, 4096, b.cs);
+  // the queue is cut once at the stretch tuned before for batches of this
+  // signature, else at 4096 (the tuner then cuts it again per candidate)
+  uint32_t tc0 = 4096, grab0 = 1;
+  if (!autotune_on || !tune_cache_lookup(b, &tc0, &grab0)) tc0 = 4096;
+  make_queue(b, tc0, b.cs);
   if (debug_undersize()) cap = std::max<uint64_t>(64, cap / 64);
   alloc_outputs(b, cap, b.cs);
   auto t2 = std::chrono::steady_clock::now();
