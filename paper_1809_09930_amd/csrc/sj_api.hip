@@ -123,20 +123,28 @@ void dev_free(void *p, size_t got, int dev, bool idle) {
     return;
   }
   BlockCache &c = g_cache[dev];
-  std::lock_guard<std::mutex> lock(c.mu);
-  if (got > cache_cap(c) - std::min(c.bytes, cache_cap(c))) {
-    (void)hipFree(p);
-    return;
+  auto fits = [&]() { return got <= cache_cap(c) - std::min(c.bytes, cache_cap(c)); };
+  bool keep;
+  {
+    std::lock_guard<std::mutex> lock(c.mu);
+    keep = fits();
   }
   // the block may still be read or written by queued work on any stream;
-  // the next user may run on another stream
-  if (!idle && hipDeviceSynchronize() != hipSuccess) {
+  // the next user may run on another stream.  The wait is not taken under
+  // the cache's lock, so that other threads allocate meanwhile.
+  if (keep && !idle && hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(p);
-    return;
+    keep = false;
   }
-  c.blocks.emplace(got, p);
-  c.bytes += got;
+  if (keep) {
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (fits()) {  // checked again: other blocks may have come in meanwhile
+      c.blocks.emplace(got, p);
+      c.bytes += got;
+      return;
+    }
+  }
+  (void)hipFree(p);
 }
 
 size_t dev_cached_bytes(int dev) {
