@@ -76,44 +76,76 @@ __device__ __forceinline__ typename Fmt<FMT>::T quantise(double v) {
 // ---------------------------------------------------------------------------
 // Preparation, pass 1: quantised rows, norms and the global maxima.
 // ---------------------------------------------------------------------------
+// One centred, quantised coordinate (the same value wherever it is needed).
+template <int FMT>
+__device__ __forceinline__ typename Fmt<FMT>::T prep_coord(float x, float c) {
+  const float diff = x - c;  // rounded to FP32: budgeted
+  return quantise<FMT>((double)diff);
+}
+
+// The operand rows: 8 consecutive K slots per thread, so that the 16-byte
+// stores of XA and XB are contiguous across the lanes.  A rows [x~ | 0],
+// B columns [-2 x~ | 0] (scaling by -2 is exact); padding rows are zero.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_mfma_prep(
     const float *__restrict__ X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
     uint32_t kp, const float *__restrict__ centre, typename Fmt<FMT>::T *__restrict__ XA,
-    typename Fmt<FMT>::T *__restrict__ XB, float *__restrict__ cn, double *__restrict__ norm2,
-    double *__restrict__ dist_c, double *__restrict__ fold_err,
-    unsigned long long *__restrict__ maxima) {
+    typename Fmt<FMT>::T *__restrict__ XB) {
+  typedef typename Fmt<FMT>::T T;
+  typedef typename Fmt<FMT>::V8 V8;
+  const uint32_t kv = kp / 8;  // vectors per row
+  const uint64_t total = n_pad * kv;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t p = e / kv;
+    const uint32_t k0 = (uint32_t)(e - p * kv) * 8u;
+    V8 a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t t = k0 + (uint32_t)j;
+      const T q = p < n && t < d ? prep_coord<FMT>(X[p * dp + t], centre[t]) : (T)0.0f;
+      a[j] = q;
+      b[j] = (T)(-2.0f * (float)q);  // exact
+    }
+    reinterpret_cast<V8 *>(XA)[e] = a;
+    reinterpret_cast<V8 *>(XB)[e] = b;
+  }
+}
+
+// Per point, in dimension order: the quantised norm |x~|^2 and the distance
+// from the centre, both in FP64.  The norm enters the MFMA as the
+// candidate's initial accumulator, rounded to FP32; that rounding is the
+// "fold" error of the bound.  Padding rows get the norm +inf (D = +inf for
+// every query).  Each lane reads its own row as 16-byte vectors.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_mfma_norms(
+    const float *__restrict__ X, uint64_t n, uint64_t n_pad, uint32_t d, uint32_t dp,
+    const float *__restrict__ centre, float *__restrict__ cn, double *__restrict__ norm2,
+    double *__restrict__ dist_c, double *__restrict__ fold_err) {
   typedef typename Fmt<FMT>::T T;
   const uint64_t p = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (p >= n_pad) return;
-  T *a = XA + p * kp;
-  T *b = XB + p * kp;
-  if (p >= n) {  // padding rows: D = +inf for every query
-    for (uint32_t k = 0; k < kp; ++k) {
-      a[k] = (T)0.0f;
-      b[k] = (T)0.0f;
-    }
+  if (p >= n) {
     cn[p] = __builtin_inff();
     return;
   }
-  const float *x = X + p * dp;
+  const float4 *x4 = reinterpret_cast<const float4 *>(X + p * dp);  // dp: a multiple of 8
   double nn = 0.0, dc = 0.0;
-  for (uint32_t t = 0; t < d; ++t) {
-    const float diff = x[t] - centre[t];  // rounded to FP32: budgeted
-    const T q = quantise<FMT>((double)diff);
-    a[t] = q;
-    b[t] = (T)(-2.0f * (float)q);  // exact
-    const double qd = (double)(float)q;
-    nn += qd * qd;
-    const double e = (double)x[t] - (double)centre[t];
-    dc += e * e;
+  for (uint32_t t0 = 0; t0 < d; t0 += 4) {
+    const float4 v = x4[t0 / 4];
+    const float xv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t t = t0 + (uint32_t)j;
+      if (t < d) {
+        const T q = prep_coord<FMT>(xv[j], centre[t]);
+        const double qd = (double)(float)q;
+        nn += qd * qd;
+        const double e = (double)xv[j] - (double)centre[t];
+        dc += e * e;
+      }
+    }
   }
-  for (uint32_t k = d; k < kp; ++k) {
-    a[k] = (T)0.0f;
-    b[k] = (T)0.0f;
-  }
-  // the candidate's norm enters the MFMA as its initial accumulator,
-  // rounded to FP32; the rounding is the "fold" error of the bound
   const float h = (float)nn;
   cn[p] = h;
   norm2[p] = nn;
@@ -1346,14 +1378,19 @@ void launch_mfma_prep(int fmt, const float *X, uint64_t n, uint64_t n_pad, uint3
                       unsigned long long *maxima, hipStream_t s) {
   const uint32_t grid = (uint32_t)((n_pad + kBlock - 1) / kBlock);
   if (!grid) return;
-  if (fmt == kFmtF16)
-    hipLaunchKernelGGL(k_mfma_prep<kFmtF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
-                       kp, centre, (_Float16 *)XA, (_Float16 *)XB, cn, norm2, dist_c, fold_err,
-                       maxima);
-  else
-    hipLaunchKernelGGL(k_mfma_prep<kFmtBF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
-                       kp, centre, (__bf16 *)XA, (__bf16 *)XB, cn, norm2, dist_c, fold_err,
-                       maxima);
+  const uint32_t grid_rows =
+      (uint32_t)std::min<uint64_t>((n_pad * (kp / 8) + kBlock - 1) / kBlock, 1u << 20);
+  if (fmt == kFmtF16) {
+    hipLaunchKernelGGL(k_mfma_prep<kFmtF16>, dim3(grid_rows), dim3(kBlock), 0, s, X, n, n_pad, d,
+                       dp, kp, centre, (_Float16 *)XA, (_Float16 *)XB);
+    hipLaunchKernelGGL(k_mfma_norms<kFmtF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
+                       centre, cn, norm2, dist_c, fold_err);
+  } else {
+    hipLaunchKernelGGL(k_mfma_prep<kFmtBF16>, dim3(grid_rows), dim3(kBlock), 0, s, X, n, n_pad,
+                       d, dp, kp, centre, (__bf16 *)XA, (__bf16 *)XB);
+    hipLaunchKernelGGL(k_mfma_norms<kFmtBF16>, dim3(grid), dim3(kBlock), 0, s, X, n, n_pad, d, dp,
+                       centre, cn, norm2, dist_c, fold_err);
+  }
   SJ_HIP(hipGetLastError());
   SJ_HIP(hipMemsetAsync(maxima, 0, 4 * sizeof(unsigned long long), s));
   const uint32_t g2 = (uint32_t)std::min<uint64_t>((n + kBlock - 1) / kBlock, 1024);
