@@ -1053,22 +1053,24 @@ __device__ __forceinline__ void emit_rechecked(const MfmaView &v, bool ok, uint3
   st.cnt += n;
 }
 
-// Rows of up to DPM padded dimensions: one wave per workgroup.  The wave
-// first copies the two rows of each of its 64 pairs into LDS, 16 bytes per
-// lane and whole row segments per instruction (a row costs two or four
-// cache-line requests instead of one per dimension and lane); each lane then
-// evaluates its pair from LDS in the caller's dimension order.  Rows are
-// DPM + 1 floats apart, so the lanes' reads of one dimension fall in
-// different banks.
-template <int DPM>
+// Rows of up to DPM padded dimensions, NP pairs per batch, one wave per
+// workgroup.  The wave first copies the two rows of each of its pairs into
+// LDS, 16 bytes per lane and whole row segments per instruction (a row costs
+// a few cache-line requests instead of one per dimension and lane); each of
+// the first NP lanes then evaluates its pair from LDS in the caller's
+// dimension order.  Rows are DPM + 1 floats apart, so the lanes' reads of
+// one dimension fall in different banks.  Above 64 padded dimensions a batch
+// holds 32 pairs, so that four waves fit a CU's LDS.
+template <int DPM, int NP>
 __global__ __launch_bounds__(kWave) void k_band_recheck_staged(
     MfmaView v, const unsigned long long *__restrict__ band_count, uint64_t *__restrict__ out,
     uint64_t capacity, unsigned long long *__restrict__ cursor,
     unsigned long long *__restrict__ rechecks) {
+  static_assert(NP == kWave || NP == kWave / 2, "one or half a pair per lane");
   constexpr int kRow = DPM + 1;
-  constexpr int kVecs = 2 * kWave * DPM / 4 / kWave;  // 16-byte loads per lane and batch
-  __shared__ float rows[2][kWave][kRow];
-  __shared__ uint32_t pos[2][kWave];
+  constexpr int kVecs = 2 * NP * DPM / 4 / kWave;  // 16-byte loads per lane and batch
+  __shared__ float rows[2][NP][kRow];
+  __shared__ uint32_t pos[2][NP];
   __shared__ uint64_t stage_mem[kStage];
   __shared__ uint16_t perm[SJ_MAX_DIM];
   const uint32_t l = threadIdx.x;
@@ -1077,25 +1079,27 @@ __global__ __launch_bounds__(kWave) void k_band_recheck_staged(
   const uint64_t total = *band_count;
   const uint64_t count = total < v.band_cap ? total : v.band_cap;
   const uint32_t dv = v.dp / 4;  // 16-byte vectors per row (dp <= DPM, a multiple of 8)
-  for (uint64_t base = (uint64_t)blockIdx.x * kWave; base < count;
-       base += (uint64_t)gridDim.x * kWave) {
+  for (uint64_t base = (uint64_t)blockIdx.x * NP; base < count;
+       base += (uint64_t)gridDim.x * NP) {
     const uint64_t i = base + l;
-    const bool live = i < count;
-    uint32_t q = 0, c = 0;  // lanes past the end stage row 0 and drop it
+    const bool live = l < (uint32_t)NP && i < count;
+    uint32_t q = 0, c = 0;  // slots past the end stage row 0 and drop it
     if (live) {
       const uint64_t key = v.band[i];
       q = (uint32_t)(key >> 32);
       c = (uint32_t)key;
     }
-    pos[0][l] = q;
-    pos[1][l] = c;
+    if (l < (uint32_t)NP) {
+      pos[0][l] = q;
+      pos[1][l] = c;
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kVecs; ++k) {
-      // vector e of the batch's 2 x 64 rows of DPM / 4 vectors
+      // vector e of the batch's 2 x NP rows of DPM / 4 vectors
       const uint32_t e = (uint32_t)k * kWave + l;
       const uint32_t row = e / (DPM / 4), col = e % (DPM / 4);
-      const uint32_t side = row / kWave, slot = row % kWave;
+      const uint32_t side = row / NP, slot = row % NP;
       if (col < dv) {
         const float *src = side ? v.X : v.Xq;
         const float4 x =
@@ -1108,46 +1112,15 @@ __global__ __launch_bounds__(kWave) void k_band_recheck_staged(
       }
     }
     __syncthreads();
-    const bool ok = live && canonical_within_body<kRecheckUnroll>(&rows[0][l][0], 0, &rows[1][l][0],
-                                                                 0, perm, v.d, 0, v.eps2);
+    const uint32_t lr = l < (uint32_t)NP ? l : 0u;  // the row a lane evaluates
+    const bool ok = live && canonical_within_body<kRecheckUnroll>(&rows[0][lr][0], 0,
+                                                                 &rows[1][lr][0], 0, perm, v.d, 0,
+                                                                 v.eps2);
     __syncthreads();  // the rows are overwritten by the next batch
     emit_rechecked(v, ok, q, c, st, out, capacity, cursor);
   }
   flush(st, out, capacity, cursor);
   if (blockIdx.x == 0 && l == 0 && count) atomicAdd(rechecks, (unsigned long long)count);
-}
-
-// Rows of more padded dimensions: each lane gathers its two rows from
-// memory in the caller's dimension order, the predicate's loop unrolled so
-// that those loads overlap.
-__global__ __launch_bounds__(kBlock) void k_band_recheck(
-    MfmaView v, const unsigned long long *__restrict__ band_count, uint64_t *__restrict__ out,
-    uint64_t capacity, unsigned long long *__restrict__ cursor,
-    unsigned long long *__restrict__ rechecks) {
-  __shared__ uint64_t stage_mem[kWavesPerBlock][kStage];
-  __shared__ uint16_t perm[SJ_MAX_DIM];  // the dimension map, read by every lane
-  for (uint32_t t = threadIdx.x; t < v.d; t += kBlock) perm[t] = v.inv_perm[t];
-  __syncthreads();
-  const uint32_t w = uniform_u32(threadIdx.x / kWave);
-  Stage st{&stage_mem[w][0], 0u};
-  const uint64_t total = *band_count;
-  const uint64_t count = total < v.band_cap ? total : v.band_cap;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (uint64_t)w * kWave; base < count;
-       base += stride) {
-    const uint64_t i = base + lane_id();
-    bool ok = false;
-    uint32_t q = 0, c = 0;
-    if (i < count) {
-      const uint64_t key = v.band[i];
-      q = (uint32_t)(key >> 32);
-      c = (uint32_t)key;
-      ok = canonical_within_body<kRecheckUnroll>(v.Xq, q, v.X, c, perm, v.d, v.dp, v.eps2);
-    }
-    emit_rechecked(v, ok, q, c, st, out, capacity, cursor);
-  }
-  flush(st, out, capacity, cursor);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && count) atomicAdd(rechecks, (unsigned long long)count);
 }
 
 // query column blocks per wave of the persistent batched kernel
@@ -1484,14 +1457,14 @@ void launch_band_recheck(const MfmaView &v, uint64_t *out, uint64_t capacity,
   SJ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const dim3 grid((uint32_t)cus * kRecheckBlocksPerCu);
   if (v.dp <= 32)
-    hipLaunchKernelGGL(k_band_recheck_staged<32>, grid, dim3(kWave), 0, s, v, v.band_cursor, out,
-                       capacity, cursor, rechecks);
+    hipLaunchKernelGGL((k_band_recheck_staged<32, kWave>), grid, dim3(kWave), 0, s, v,
+                       v.band_cursor, out, capacity, cursor, rechecks);
   else if (v.dp <= 64)
-    hipLaunchKernelGGL(k_band_recheck_staged<64>, grid, dim3(kWave), 0, s, v, v.band_cursor, out,
-                       capacity, cursor, rechecks);
-  else
-    hipLaunchKernelGGL(k_band_recheck, grid, dim3(kBlock), 0, s, v, v.band_cursor, out, capacity,
-                       cursor, rechecks);
+    hipLaunchKernelGGL((k_band_recheck_staged<64, kWave>), grid, dim3(kWave), 0, s, v,
+                       v.band_cursor, out, capacity, cursor, rechecks);
+  else  // 32 pairs per batch: 33 KB of rows, four waves per CU
+    hipLaunchKernelGGL((k_band_recheck_staged<SJ_MAX_DIM, kWave / 2>), grid, dim3(kWave), 0, s, v,
+                       v.band_cursor, out, capacity, cursor, rechecks);
   SJ_HIP(hipGetLastError());
 }
 
